@@ -1,0 +1,218 @@
+/*
+ * ecsim.h -- C ABI of the MI355X (gfx950) ECsim particle hot path.
+ *
+ * The semi-implicit, energy-conserving PIC scheme (ECsim) advances, per time
+ * step: moment gathering (hatted current J-hat, Eq. 1; mass matrices M, Eq. 3),
+ * the implicit field solve (Eqs. 6-7, GMRES) and the particle mover
+ * (Eqs. 4, 5, 8). This library implements those steps as HIP kernels.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Units: Gaussian with the 4 pi factor, c = 1, theta = 1/2 (the value the
+ *    paper states gives energy conservation, Sec. II).
+ *  - Grid: periodic, n[d] cells of size h[d]; nodes sit at i*h, cell i spans
+ *    [i h, (i+1) h). Node and cell index: ix + nx*(iy + ny*iz). Every node has
+ *    the control volume V = hx*hy*hz.
+ *  - Node fields (E, B at nodes, J-hat, gradients) are [3][Nn] structure of
+ *    arrays. Cell-centred B_C is [3][Nc] with the index of the cell.
+ *  - Mass matrices are stored as 14 offset blocks per node, [14][9][Nn]:
+ *    block k of node g is M_{g, g+o_k}; component ij = 3*i + j. The 14 offsets
+ *    o_k are (0,0,0); (1,0,0); (ox,1,0) for ox = -1,0,1; and (ox,oy,1) with ox
+ *    fastest and oy, ox in -1..1 (Eq. 3 and the symmetry M_{NN'} = M_{N'N}
+ *    stated after it: the 13 offsets not stored satisfy M_{g,g-o} = M_{g-o,g},
+ *    which is block k of node g-o).
+ *  - Every pointer to an array is a DEVICE pointer owned by the caller, except
+ *    where marked "host". The library never frees caller memory. Calls are
+ *    asynchronous on `stream` (a hipStream_t; NULL is the default stream)
+ *    unless marked "synchronous".
+ *  - Arguments are validated on the host before anything is launched; a bad
+ *    argument returns ECSIM_EINVAL and launches nothing. A HIP launch or
+ *    runtime failure returns ECSIM_EHIP. ecsim_last_error() describes the last
+ *    non-OK status of the calling thread. Nothing throws across this ABI.
+ *  - Precision: ECSIM_F64 particles use FP64 fields and outputs. ECSIM_F32
+ *    particles store an int32 cell index plus FP32 in-cell offsets in [0,1)
+ *    and FP32 velocities, use FP32 node fields, and accumulate J-hat and M in
+ *    FP32 with compensated (Neumaier) tile sums.
+ */
+#ifndef ECSIM_H
+#define ECSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ecsim_status;
+enum {
+  ECSIM_OK = 0,
+  ECSIM_EINVAL = -1,       /* invalid argument (nothing launched)            */
+  ECSIM_EHIP = -2,         /* HIP runtime or launch error                    */
+  ECSIM_EWORKSPACE = -3,   /* workspace missing or smaller than required     */
+  ECSIM_ENOCONV = -5       /* GMRES did not reach the tolerance              */
+};
+
+enum { ECSIM_F64 = 0, ECSIM_F32 = 1 };
+
+/* flags */
+enum {
+  ECSIM_ACCUMULATE = 1,    /* add into J/M (or gE/gB) instead of overwriting */
+  ECSIM_SORTED = 2,        /* particles are grouped by cell; cell_start valid */
+  ECSIM_BWD_THROUGH_MOVER = 8 /* backward: differentiate mover -> moments   */
+};
+
+typedef struct {
+  int32_t n[3];            /* cells per dimension, >= 1                      */
+  double h[3];             /* cell size, > 0                                  */
+  double dt;               /* time step, > 0                                  */
+} ecsim_grid;
+
+/* One species. All arrays have np entries and live on the device. */
+typedef struct {
+  int32_t prec;            /* ECSIM_F64 or ECSIM_F32                          */
+  int64_t np;              /* number of particles, 0 <= np < 2^31             */
+  double qom;              /* charge-to-mass ratio (q/m) of the species        */
+  void *pos[3];            /* F64: absolute position in [0, n*h);
+                              F32: in-cell offset in [0, 1)                   */
+  int32_t *cell;           /* F32: cell index of the particle; F64: NULL       */
+  void *vel[3];            /* velocity components (prec)                      */
+  const void *q;           /* per-particle charge (prec), or NULL             */
+  double q_const;          /* charge of every particle when q == NULL         */
+  const int32_t *cell_start; /* optional, with ECSIM_SORTED: [Nc+1] offsets of
+                              each cell's particles (particles of cell c are
+                              [cell_start[c], cell_start[c+1]))               */
+} ecsim_particles;
+
+/* Thread-local description of the last non-OK status (never NULL). */
+const char *ecsim_last_error(void);
+
+/* Library version string (host). */
+const char *ecsim_version(void);
+
+/* Bytes of device workspace that ecsim_sort / ecsim_moments need for `np`
+ * particles of precision `prec` on this grid (host, synchronous). */
+ecsim_status ecsim_workspace_size(const ecsim_grid *grid, int64_t np, int32_t prec,
+                                  uint32_t flags, size_t *bytes /* host out */);
+
+/*
+ * Particle mover, Eqs. 4, 5 and 8 of the paper:
+ *   E_p, B_p = trilinear gathers of E_node = E^{n+theta} and B_node = B^n at
+ *              x^{n-1/2};
+ *   vbar     = alpha_p (v^n + beta_p E_p), alpha_p from Eq. 2 with beta_p =
+ *              (q/m) dt / 2;
+ *   v^{n+1}  = 2 vbar - v^n;  x^{n+1/2} = x^{n-1/2} + dt v^{n+1}, wrapped into
+ *              the periodic box (F32: offset and cell updated).
+ * Updates pos/cell/vel of `sp` in place, preserving particle order.
+ * E_node, B_node: [3][Nn] in the particles' precision.
+ * ke_out: optional device double; receives (+=) sum_p 1/2 m_p |v^{n+1}|^2 with
+ * m_p = q_p/(q/m). Per-particle charges are read only for ke_out.
+ */
+ecsim_status ecsim_move(const ecsim_grid *grid, const ecsim_particles *sp,
+                        const void *E_node, const void *B_node, double *ke_out,
+                        void *stream);
+
+/*
+ * Moment gather, Eqs. 1 and 3 of the paper, summed over `nspecies` species:
+ *   J[g]    = sum_p q_p (alpha_p v_p) W_pg / V                      [3][Nn]
+ *   M[g][k] = sum_p (beta_p q_p / V) alpha_p W_pg W_p(g+o_k)    [14][9][Nn]
+ * with alpha_p built from B_node (= B^n, [3][Nn]) gathered at x_p.
+ * All species must share one precision; J, M and B_node are in it.
+ * J and M are overwritten unless ECSIM_ACCUMULATE is set. With ECSIM_SORTED
+ * every species must carry cell_start and the tiled, LDS-binned deposit is
+ * used; otherwise a per-particle atomic deposit handles any order.
+ * ws/ws_bytes: device workspace of at least ecsim_workspace_size() bytes
+ * (may be NULL/0 when that size is 0).
+ */
+ecsim_status ecsim_moments(const ecsim_grid *grid, const ecsim_particles *species,
+                           int32_t nspecies, const void *B_node, void *J, void *M,
+                           void *ws, size_t ws_bytes, uint32_t flags, void *stream);
+
+/*
+ * Matrix-free mass-matrix apply inside the field solve (Eq. 7):
+ *   y = a * (M x) + b * y,   (M x)_g = sum over the 27 neighbours g' of
+ *   M_{g g'} x_{g'}, using the 14 stored blocks and M_{g,g-o} = M_{g-o,g}
+ *   (identical, not transposed, blocks).
+ * M: [14][9][Nn] in precision m_prec; x, y: FP64 [3][Nn]; x and y must not
+ * alias. Arithmetic is FP64.
+ */
+ecsim_status ecsim_mass_apply(const ecsim_grid *grid, int32_t m_prec, const void *M,
+                              const double *x, double a, double b, double *y,
+                              void *stream);
+
+/*
+ * Adjoint of (mover ->) moments for the scalar L = <gJ, J> + <gM, M>, where J
+ * and M are the moments of Eqs. 1 and 3 over the 14 stored blocks.
+ * `sp` holds the particle state the forward started from. With
+ * ECSIM_BWD_THROUGH_MOVER the forward is x', v' = mover(x, v; E_node, B_node)
+ * followed by moments(x', v'; B_node) (same B_node); without it the forward is
+ * moments(x, v; B_node) and E_node may be NULL.
+ * Outputs: gpos[3], gvel[3] per particle, dL/d(position) and dL/d(velocity),
+ * in the particles' precision (F32: position derivative is with respect to the
+ * physical coordinate, i.e. dL/d(offset) / h). gE, gB: [3][Nn], accumulated
+ * (+=) always; gE untouched without ECSIM_BWD_THROUGH_MOVER. gJ: [3][Nn],
+ * gM: [14][9][Nn], in the particles' precision. Alpha and the weights are
+ * recomputed, not stored.
+ */
+ecsim_status ecsim_moments_backward(const ecsim_grid *grid, const ecsim_particles *sp,
+                                    const void *E_node, const void *B_node,
+                                    const void *gJ, const void *gM, void *gpos[3],
+                                    void *gvel[3], void *gE, void *gB,
+                                    uint32_t flags, void *stream);
+
+/*
+ * Counting sort of one species by cell, out of place: the particles of `src`
+ * are written to the arrays of `dst` (same precision and np, no aliasing) in
+ * cell order; the order inside a cell is not specified. cell_start_out [Nc+1]
+ * receives each cell's range in dst and, if perm_out is not NULL,
+ * perm_out[i] (int32) the index in src of the particle now at dst[i].
+ * ws: device workspace of ecsim_workspace_size() bytes.
+ */
+ecsim_status ecsim_sort(const ecsim_grid *grid, const ecsim_particles *src,
+                        const ecsim_particles *dst, int32_t *cell_start_out,
+                        int32_t *perm_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Node magnetic field: B_N[g] = mean of the 8 cell-centred values around node
+ * g (FP64 in, FP64 out; B_N32 optional FP32 copy). */
+ecsim_status ecsim_centres_to_nodes(const ecsim_grid *grid, const double *B_C, double *B_N,
+                                    float *B_N32, void *stream);
+
+/* FP64 -> FP32 copy of n values (node fields for the FP32 path). */
+ecsim_status ecsim_to_f32(int64_t n, const double *src, float *dst, void *stream);
+
+/*
+ * Field solve of Eqs. 6-7 for theta = 1/2 (synchronous on `stream`):
+ *   A E = b,  A E = E + (c theta dt)^2 curl_N curl_C E + 4 pi theta dt (M E),
+ *   b = E^n - 4 pi theta dt J + c theta dt curl_N B_C^n,
+ * by restarted GMRES(restart), 1 <= restart <= 120, from E^n, stopping when ||b - A E||_2 <=
+ * tol ||b||_2; then B_C^{n+theta} = B_C^n - c theta dt curl_C E^{n+theta},
+ * E^{n+1} = 2 E^{n+theta} - E^n and B_C^{n+1} = 2 B_C^{n+theta} - B_C^n.
+ * The curls average the four edge differences of a cell (curl_C, nodes to
+ * centres) or the four around a node (curl_N, centres to nodes); curl_N is the
+ * transpose of curl_C. M [14][9][Nn] and J [3][Nn] in m_prec (the precision
+ * of the moments); every other vector FP64 [3][Nn]; the arithmetic is FP64.
+ * ws: device workspace of ecsim_solve_workspace_size() bytes.
+ * iters_out, resid_out (host, nullable): iterations and final relative
+ * residual. Returns ECSIM_ENOCONV if maxit iterations did not reach tol (the
+ * outputs then hold the last iterate).
+ */
+ecsim_status ecsim_solve_workspace_size(const ecsim_grid *grid, int32_t restart, size_t *bytes);
+ecsim_status ecsim_field_solve(const ecsim_grid *grid, int32_t m_prec, const void *M,
+                               const void *J, const double *E_n, const double *B_C_n,
+                               double tol, int32_t restart, int32_t maxit, double *E_theta,
+                               double *E_next, double *B_C_next, void *ws, size_t ws_bytes,
+                               int32_t *iters_out, double *resid_out, void *stream);
+
+/* out (device double) = V/(8 pi) * sum over the 3*Nn values of F^2: the
+ * field energy of an FP64 [3][Nn] array, the W_E and W_B terms of the total
+ * energy the scheme conserves for theta = 1/2 (Sec. I-II). Deterministic
+ * (fixed-order tree reduction). ws: device scratch of ECSIM_ENERGY_WS_BYTES. */
+#define ECSIM_ENERGY_WS_BYTES 2048
+ecsim_status ecsim_field_energy(const ecsim_grid *grid, const double *F, double *out,
+                                void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ECSIM_H */

@@ -1,0 +1,406 @@
+// C ABI of the ECsim hot path: argument validation, dispatch to the kernel
+// launchers on the caller's stream, and the host driver of the FP64 GMRES
+// field solve (Eqs. 6-7). Declarations and the contract of every entry point
+// are in include/ecsim.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/ecsim.h"
+#include "internal.h"
+
+using namespace ecsim;
+
+namespace {
+
+thread_local char g_err[512] = "no error";
+
+ecsim_status fail(ecsim_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+ecsim_status hip_fail(hipError_t e, const char* where) {
+  return fail(ECSIM_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTheta = 0.5;
+constexpr double kC = 1.0;
+constexpr int64_t kMaxCells = (int64_t)1 << 20;   // counting-sort scan limit
+
+ecsim_status make_grid(const ecsim_grid* gr, Grid& g) {
+  if (!gr) return fail(ECSIM_EINVAL, "grid is NULL");
+  for (int d = 0; d < 3; ++d) {
+    if (gr->n[d] < 1) return fail(ECSIM_EINVAL, "grid n[%d] = %d must be >= 1", d, gr->n[d]);
+    if (!(gr->h[d] > 0.0) || !std::isfinite(gr->h[d])) return fail(ECSIM_EINVAL, "grid h[%d] must be > 0", d);
+  }
+  if (!(gr->dt > 0.0) || !std::isfinite(gr->dt)) return fail(ECSIM_EINVAL, "grid dt must be > 0");
+  int64_t nn = (int64_t)gr->n[0] * gr->n[1] * gr->n[2];
+  if (nn >= ((int64_t)1 << 31)) return fail(ECSIM_EINVAL, "grid has %lld cells; at most 2^31 - 1", (long long)nn);
+  g.nx = gr->n[0];
+  g.ny = gr->n[1];
+  g.nz = gr->n[2];
+  g.hx = gr->h[0];
+  g.hy = gr->h[1];
+  g.hz = gr->h[2];
+  g.dt = gr->dt;
+  g.nn = nn;
+  g.V = gr->h[0] * gr->h[1] * gr->h[2];
+  return ECSIM_OK;
+}
+
+ecsim_status check_prec(int32_t prec) {
+  if (prec != ECSIM_F64 && prec != ECSIM_F32) return fail(ECSIM_EINVAL, "precision %d is not ECSIM_F64/ECSIM_F32", prec);
+  return ECSIM_OK;
+}
+
+ecsim_status make_species(const ecsim_particles* sp, SpeciesArgs& a, const char* name) {
+  if (!sp) return fail(ECSIM_EINVAL, "%s: particles pointer is NULL", name);
+  if (check_prec(sp->prec) != ECSIM_OK) return ECSIM_EINVAL;
+  if (sp->np < 0 || sp->np >= ((int64_t)1 << 31)) return fail(ECSIM_EINVAL, "%s: np = %lld out of range", name, (long long)sp->np);
+  if (!std::isfinite(sp->qom) || sp->qom == 0.0) return fail(ECSIM_EINVAL, "%s: qom must be finite and non-zero", name);
+  if (sp->np > 0) {
+    for (int d = 0; d < 3; ++d)
+      if (!sp->pos[d] || !sp->vel[d]) return fail(ECSIM_EINVAL, "%s: position/velocity pointer %d is NULL", name, d);
+    if (sp->prec == ECSIM_F32 && !sp->cell) return fail(ECSIM_EINVAL, "%s: FP32 particles need a cell array", name);
+  }
+  if (sp->prec == ECSIM_F64 && sp->cell) return fail(ECSIM_EINVAL, "%s: FP64 particles take no cell array", name);
+  if (!sp->q && !std::isfinite(sp->q_const)) return fail(ECSIM_EINVAL, "%s: q_const must be finite", name);
+  a.np = (int)sp->np;
+  a.qom = sp->qom;
+  for (int d = 0; d < 3; ++d) {
+    a.pos[d] = sp->pos[d];
+    a.vel[d] = sp->vel[d];
+  }
+  a.cell = sp->cell;
+  a.q = sp->q;
+  a.q_const = sp->q_const;
+  a.cell_start = sp->cell_start;
+  return ECSIM_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+const char* ecsim_last_error(void) { return g_err; }
+
+const char* ecsim_version(void) { return "ecsim-mi355x 0.1 (gfx950)"; }
+
+ecsim_status ecsim_workspace_size(const ecsim_grid* grid, int64_t np, int32_t prec, uint32_t flags, size_t* bytes) {
+  (void)flags;
+  Grid g;
+  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
+  if (check_prec(prec) != ECSIM_OK) return ECSIM_EINVAL;
+  if (!bytes) return fail(ECSIM_EINVAL, "bytes is NULL");
+  if (np < 0 || np >= ((int64_t)1 << 31)) return fail(ECSIM_EINVAL, "np out of range");
+  *bytes = sort_workspace_bytes(g, np);
+  return ECSIM_OK;
+}
+
+ecsim_status ecsim_move(const ecsim_grid* grid, const ecsim_particles* sp, const void* E_node, const void* B_node,
+                        double* ke_out, void* stream) {
+  Grid g;
+  SpeciesArgs a;
+  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
+  if (make_species(sp, a, "ecsim_move") != ECSIM_OK) return ECSIM_EINVAL;
+  if (!E_node || !B_node) return fail(ECSIM_EINVAL, "ecsim_move: E_node and B_node are required");
+  hipError_t e = launch_move(g, sp->prec == ECSIM_F32, a, E_node, B_node, ke_out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ecsim_move");
+  return ECSIM_OK;
+}
+
+ecsim_status ecsim_moments(const ecsim_grid* grid, const ecsim_particles* species, int32_t nspecies,
+                           const void* B_node, void* J, void* M, void* ws, size_t ws_bytes, uint32_t flags,
+                           void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  Grid g;
+  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
+  if (nspecies < 1 || nspecies > kMaxSpecies) return fail(ECSIM_EINVAL, "ecsim_moments: nspecies = %d not in 1..%d", nspecies, kMaxSpecies);
+  if (!species) return fail(ECSIM_EINVAL, "ecsim_moments: species is NULL");
+  if (!B_node || !J || !M) return fail(ECSIM_EINVAL, "ecsim_moments: B_node, J and M are required");
+  if (flags & ~(uint32_t)(ECSIM_ACCUMULATE | ECSIM_SORTED)) return fail(ECSIM_EINVAL, "ecsim_moments: unknown flags 0x%x", flags);
+  SpeciesArgs a[kMaxSpecies];
+  const int32_t prec = species[0].prec;
+  for (int s = 0; s < nspecies; ++s) {
+    if (make_species(&species[s], a[s], "ecsim_moments") != ECSIM_OK) return ECSIM_EINVAL;
+    if (species[s].prec != prec) return fail(ECSIM_EINVAL, "ecsim_moments: species have mixed precisions");
+    if ((flags & ECSIM_SORTED) && !species[s].cell_start)
+      return fail(ECSIM_EINVAL, "ecsim_moments: ECSIM_SORTED needs cell_start for every species");
+  }
+  const bool f32 = prec == ECSIM_F32;
+  const size_t esz = f32 ? 4 : 8;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (!(flags & ECSIM_ACCUMULATE)) {
+    if ((e = launch_zero(J, esz * 3 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_moments zero J");
+    if ((e = launch_zero(M, esz * 126 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_moments zero M");
+  }
+  if ((flags & ECSIM_SORTED) && tiled_supported(g))
+    e = launch_deposit_tiled(g, f32, a, nspecies, B_node, J, M, st);
+  else
+    e = launch_deposit_atomic(g, f32, a, nspecies, B_node, J, M, st);
+  if (e != hipSuccess) return hip_fail(e, "ecsim_moments");
+  return ECSIM_OK;
+}
+
+ecsim_status ecsim_mass_apply(const ecsim_grid* grid, int32_t m_prec, const void* M, const double* x, double a,
+                              double b, double* y, void* stream) {
+  Grid g;
+  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
+  if (check_prec(m_prec) != ECSIM_OK) return ECSIM_EINVAL;
+  if (!M || !x || !y) return fail(ECSIM_EINVAL, "ecsim_mass_apply: M, x and y are required");
+  if ((const void*)x == (const void*)y) return fail(ECSIM_EINVAL, "ecsim_mass_apply: x and y must not alias");
+  hipError_t e = launch_mass_apply(g, m_prec == ECSIM_F32, M, x, a, b, y, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ecsim_mass_apply");
+  return ECSIM_OK;
+}
+
+ecsim_status ecsim_moments_backward(const ecsim_grid* grid, const ecsim_particles* sp, const void* E_node,
+                                    const void* B_node, const void* gJ, const void* gM, void* gpos[3],
+                                    void* gvel[3], void* gE, void* gB, uint32_t flags, void* stream) {
+  Grid g;
+  SpeciesArgs a;
+  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
+  if (make_species(sp, a, "ecsim_moments_backward") != ECSIM_OK) return ECSIM_EINVAL;
+  if (flags & ~(uint32_t)(ECSIM_BWD_THROUGH_MOVER | ECSIM_ACCUMULATE))
+    return fail(ECSIM_EINVAL, "ecsim_moments_backward: unknown flags 0x%x", flags);
+  const bool through = flags & ECSIM_BWD_THROUGH_MOVER;
+  if (!B_node || !gJ || !gM || !gB) return fail(ECSIM_EINVAL, "ecsim_moments_backward: B_node, gJ, gM, gB are required");
+  if (through && (!E_node || !gE)) return fail(ECSIM_EINVAL, "ecsim_moments_backward: through the mover needs E_node and gE");
+  if (!gpos || !gvel) return fail(ECSIM_EINVAL, "ecsim_moments_backward: gpos and gvel are required");
+  if (sp->np > 0)
+    for (int d = 0; d < 3; ++d)
+      if (!gpos[d] || !gvel[d]) return fail(ECSIM_EINVAL, "ecsim_moments_backward: gpos/gvel[%d] is NULL", d);
+  hipError_t e = launch_backward(g, sp->prec == ECSIM_F32, a, E_node, B_node, gJ, gM, gpos, gvel, gE, gB, through,
+                                 (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ecsim_moments_backward");
+  return ECSIM_OK;
+}
+
+ecsim_status ecsim_sort(const ecsim_grid* grid, const ecsim_particles* src, const ecsim_particles* dst,
+                        int32_t* cell_start_out, int32_t* perm_out, void* ws, size_t ws_bytes, void* stream) {
+  Grid g;
+  SpeciesArgs a, b;
+  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
+  if (g.nn > kMaxCells) return fail(ECSIM_EINVAL, "ecsim_sort: at most %lld cells", (long long)kMaxCells);
+  if (make_species(src, a, "ecsim_sort src") != ECSIM_OK) return ECSIM_EINVAL;
+  if (make_species(dst, b, "ecsim_sort dst") != ECSIM_OK) return ECSIM_EINVAL;
+  if (src->prec != dst->prec || src->np != dst->np) return fail(ECSIM_EINVAL, "ecsim_sort: src and dst differ in precision or np");
+  if ((src->q == nullptr) != (dst->q == nullptr)) return fail(ECSIM_EINVAL, "ecsim_sort: src and dst must both have or lack q");
+  for (int d = 0; d < 3; ++d)
+    if (src->np > 0 && (src->pos[d] == dst->pos[d] || src->vel[d] == dst->vel[d]))
+      return fail(ECSIM_EINVAL, "ecsim_sort: src and dst arrays must not alias");
+  if (!cell_start_out) return fail(ECSIM_EINVAL, "ecsim_sort: cell_start_out is required");
+  size_t need = sort_workspace_bytes(g, src->np);
+  if (!ws || ws_bytes < need) return fail(ECSIM_EWORKSPACE, "ecsim_sort: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
+  hipError_t e = launch_sort(g, src->prec == ECSIM_F32, a, b, cell_start_out, perm_out, ws, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ecsim_sort");
+  return ECSIM_OK;
+}
+
+ecsim_status ecsim_centres_to_nodes(const ecsim_grid* grid, const double* B_C, double* B_N, float* B_N32,
+                                    void* stream) {
+  Grid g;
+  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
+  if (!B_C || (!B_N && !B_N32)) return fail(ECSIM_EINVAL, "ecsim_centres_to_nodes: B_C and an output are required");
+  hipError_t e = launch_centres_to_nodes(g, B_C, B_N, B_N32, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ecsim_centres_to_nodes");
+  return ECSIM_OK;
+}
+
+ecsim_status ecsim_to_f32(int64_t n, const double* src, float* dst, void* stream) {
+  if (n < 0) return fail(ECSIM_EINVAL, "ecsim_to_f32: n < 0");
+  if (n > 0 && (!src || !dst)) return fail(ECSIM_EINVAL, "ecsim_to_f32: NULL pointer");
+  hipError_t e = launch_to_f32(n, src, dst, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ecsim_to_f32");
+  return ECSIM_OK;
+}
+
+ecsim_status ecsim_field_energy(const ecsim_grid* grid, const double* F, double* out, void* ws, size_t ws_bytes,
+                                void* stream) {
+  Grid g;
+  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
+  if (!F || !out) return fail(ECSIM_EINVAL, "ecsim_field_energy: NULL pointer");
+  if (!ws || ws_bytes < ECSIM_ENERGY_WS_BYTES)
+    return fail(ECSIM_EWORKSPACE, "ecsim_field_energy: workspace of %d bytes needed", (int)ECSIM_ENERGY_WS_BYTES);
+  hipError_t e = launch_sumsq(F, 3 * g.nn, g.V / (8.0 * kPi), (double*)ws, out, false, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ecsim_field_energy");
+  return ECSIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES(m) field solve
+// ---------------------------------------------------------------------------
+ecsim_status ecsim_solve_workspace_size(const ecsim_grid* grid, int32_t restart, size_t* bytes) {
+  Grid g;
+  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
+  if (restart < 1 || restart > kMaxRestart) return fail(ECSIM_EINVAL, "restart = %d not in 1..%d", restart, kMaxRestart);
+  if (!bytes) return fail(ECSIM_EINVAL, "bytes is NULL");
+  const size_t vec = align256(sizeof(double) * 3 * (size_t)g.nn);
+  // V (m+1 vectors), w, r/b, cc (curl scratch), partials, small device scalars
+  *bytes = vec * (size_t)(restart + 1) + 3 * vec + align256(sizeof(double) * kDotBlocks * (restart + 2)) +
+           align256(sizeof(double) * 2 * (restart + 2));
+  return ECSIM_OK;
+}
+
+namespace {
+
+struct Solver {
+  Grid g;
+  bool mf32;
+  const void* M;
+  hipStream_t st;
+  double* cc;       // curl scratch (3 Nn)
+  double ctd2, cm;  // (c theta dt)^2, 4 pi theta dt
+
+  hipError_t apply(const double* x, double* out) {
+    hipError_t e;
+    if ((e = launch_curl_C(g, x, cc, st)) != hipSuccess) return e;
+    if ((e = launch_field_op_curl(g, x, cc, ctd2, out, st)) != hipSuccess) return e;
+    return launch_mass_apply(g, mf32, M, x, cm, 1.0, out, st);
+  }
+};
+
+}  // namespace
+
+ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const void* M, const void* J,
+                               const double* E_n, const double* B_C_n, double tol, int32_t restart, int32_t maxit,
+                               double* E_theta, double* E_next, double* B_C_next, void* ws, size_t ws_bytes,
+                               int32_t* iters_out, double* resid_out, void* stream) {
+  Grid g;
+  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
+  if (check_prec(m_prec) != ECSIM_OK) return ECSIM_EINVAL;
+  if (!M || !J || !E_n || !B_C_n || !E_theta || !E_next || !B_C_next)
+    return fail(ECSIM_EINVAL, "ecsim_field_solve: NULL array");
+  if (!(tol > 0.0) || !(tol < 1.0)) return fail(ECSIM_EINVAL, "ecsim_field_solve: tol must be in (0, 1)");
+  if (maxit < 1) return fail(ECSIM_EINVAL, "ecsim_field_solve: maxit must be >= 1");
+  size_t need = 0;
+  if (ecsim_solve_workspace_size(grid, restart, &need) != ECSIM_OK) return ECSIM_EINVAL;
+  if (!ws || ws_bytes < need) return fail(ECSIM_EWORKSPACE, "ecsim_field_solve: workspace of %zu bytes needed", need);
+
+  const int m = restart;
+  const int64_t n = 3 * g.nn;
+  const size_t vec = align256(sizeof(double) * (size_t)n);
+  const int64_t ld = (int64_t)(vec / sizeof(double));
+  char* w8 = (char*)ws;
+  double* V = (double*)w8;
+  w8 += vec * (size_t)(m + 1);
+  double* w = (double*)w8;
+  w8 += vec;
+  double* bvec = (double*)w8;
+  w8 += vec;
+  double* cc = (double*)w8;
+  w8 += vec;
+  double* partial = (double*)w8;
+  w8 += align256(sizeof(double) * kDotBlocks * (m + 2));
+  double* dsc = (double*)w8;   // device scalars: h column (m+1) + spare
+
+  hipStream_t st = (hipStream_t)stream;
+  Solver S{g, m_prec == ECSIM_F32, M, st, cc, (kC * kTheta * g.dt) * (kC * kTheta * g.dt), 4.0 * kPi * kTheta * g.dt};
+  hipError_t e;
+#define HIPCK(x)                                                 \
+  do {                                                           \
+    if ((e = (x)) != hipSuccess) return hip_fail(e, "ecsim_field_solve"); \
+  } while (0)
+
+  // b = E^n - 4 pi theta dt J + c theta dt curl_N B_C^n
+  HIPCK(launch_rhs(g, E_n, m_prec == ECSIM_F32, J, B_C_n, -4.0 * kPi * kTheta * g.dt, kC * kTheta * g.dt, bvec, st));
+  HIPCK(hipMemcpyAsync(E_theta, E_n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), hcol(m + 1), h2(m + 1);
+  auto dot_host = [&](const double* Vb, int nv, const double* x, double* out_host) -> hipError_t {
+    hipError_t ee = launch_dots(Vb, ld, nv, x, n, partial, dsc, st);
+    if (ee != hipSuccess) return ee;
+    ee = hipMemcpyAsync(out_host, dsc, sizeof(double) * nv, hipMemcpyDeviceToHost, st);
+    if (ee != hipSuccess) return ee;
+    return hipStreamSynchronize(st);
+  };
+  double bnorm2 = 0.0;
+  HIPCK(dot_host(bvec, 1, bvec, &bnorm2));
+  const double bnorm = std::sqrt(bnorm2);
+  int it = 0;
+  double rel = 0.0;
+  bool converged = false;
+  if (bnorm == 0.0) {
+    HIPCK(launch_scale_copy(n, 0.0, E_n, E_theta, st));
+    converged = true;
+  }
+  while (!converged) {
+    // r = b - A x  (into V_0)
+    HIPCK(S.apply(E_theta, w));
+    HIPCK(hipMemcpyAsync(V, bvec, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    HIPCK(launch_axpby(n, -1.0, w, 1.0, V, st));
+    double beta2 = 0.0;
+    HIPCK(dot_host(V, 1, V, &beta2));
+    double beta = std::sqrt(beta2);
+    rel = beta / bnorm;
+    if (rel <= tol) { converged = true; break; }
+    if (it >= maxit) break;
+    HIPCK(launch_scale_copy(n, 1.0 / beta, V, V, st));
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    int j = 0;
+    for (; j < m && it < maxit;) {
+      double* Vj = V + (size_t)j * ld;
+      double* Vj1 = V + (size_t)(j + 1) * ld;
+      HIPCK(S.apply(Vj, w));
+      // classical Gram-Schmidt, twice (CGS2): all j+1 projections per pass
+      HIPCK(dot_host(V, j + 1, w, hcol.data()));
+      HIPCK(launch_sub_combo(V, ld, j + 1, hcol.data(), w, n, st));
+      HIPCK(dot_host(V, j + 1, w, h2.data()));
+      HIPCK(launch_sub_combo(V, ld, j + 1, h2.data(), w, n, st));
+      for (int i = 0; i <= j; ++i) hcol[i] += h2[i];
+      double hn2 = 0.0;
+      HIPCK(dot_host(w, 1, w, &hn2));
+      double hn = std::sqrt(hn2);
+      if (hn > 0.0) HIPCK(launch_scale_copy(n, 1.0 / hn, w, Vj1, st));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
+      H[(size_t)(j + 1) * m + j] = hn;
+      for (int i = 0; i < j; ++i) {
+        double t = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
+        H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = t;
+      }
+      double aa = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+      double rr = std::hypot(aa, bb);
+      cs[j] = aa / rr;
+      sn[j] = bb / rr;
+      H[(size_t)j * m + j] = rr;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      ++j;
+      ++it;
+      if (std::fabs(gv[j]) <= 0.5 * tol * bnorm || hn == 0.0) break;
+    }
+    for (int i = j - 1; i >= 0; --i) {
+      double s = gv[i];
+      for (int k = i + 1; k < j; ++k) s -= H[(size_t)i * m + k] * y[k];
+      y[i] = s / H[(size_t)i * m + i];
+    }
+    // x += V y  (as w -= V (-y))
+    for (int i = 0; i < j; ++i) y[i] = -y[i];
+    HIPCK(launch_sub_combo(V, ld, j, y.data(), E_theta, n, st));
+  }
+  // advance the fields: B_C^{n+theta} = B_C^n - c theta dt curl_C E^{n+theta}
+  HIPCK(launch_curl_C(g, E_theta, cc, st));
+  HIPCK(launch_finish(g, E_n, E_theta, B_C_n, cc, kC * kTheta * g.dt, E_next, B_C_next, st));
+  HIPCK(hipStreamSynchronize(st));
+#undef HIPCK
+  if (iters_out) *iters_out = it;
+  if (resid_out) *resid_out = rel;
+  if (!converged) return fail(ECSIM_ENOCONV, "ecsim_field_solve: relative residual %.3e after %d iterations", rel, it);
+  return ECSIM_OK;
+}
+
+}  // extern "C"

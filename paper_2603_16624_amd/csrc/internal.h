@@ -1,0 +1,75 @@
+// Host-side declarations shared by the C-ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "device.h"
+
+namespace ecsim {
+
+// A species as the launchers see it (validated by the C-ABI layer).
+struct SpeciesArgs {
+  int np;
+  double qom;
+  void* pos[3];
+  int32_t* cell;
+  void* vel[3];
+  const void* q;
+  double q_const;
+  const int32_t* cell_start;
+};
+
+constexpr int kMaxSpecies = 8;
+
+hipError_t launch_move(const Grid& g, bool f32, const SpeciesArgs& sp, const void* E, const void* B,
+                       double* ke, hipStream_t st);
+
+hipError_t launch_deposit_atomic(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* B,
+                                 void* J, void* M, hipStream_t st);
+
+// Tiled deposit over cell-sorted particles; returns hipErrorInvalidValue if
+// the grid does not admit the tiling.
+hipError_t launch_deposit_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* B,
+                                void* J, void* M, hipStream_t st);
+bool tiled_supported(const Grid& g);
+
+size_t sort_workspace_bytes(const Grid& g, int64_t np);
+hipError_t launch_sort(const Grid& g, bool f32, const SpeciesArgs& src, const SpeciesArgs& dst,
+                       int32_t* cell_start, int32_t* perm, void* ws, hipStream_t st);
+
+hipError_t launch_mass_apply(const Grid& g, bool f32, const void* M, const double* x, double a, double b,
+                             double* y, hipStream_t st);
+hipError_t launch_centres_to_nodes(const Grid& g, const double* BC, double* BN, float* BN32, hipStream_t st);
+hipError_t launch_to_f32(int64_t n, const double* src, float* dst, hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
+// field-solve building blocks (FP64)
+hipError_t launch_curl_C(const Grid& g, const double* E, double* out, hipStream_t st);
+hipError_t launch_field_op_curl(const Grid& g, const double* E, const double* curlC_E, double ctd2,
+                                double* out, hipStream_t st);
+hipError_t launch_rhs(const Grid& g, const double* E_n, bool jf32, const void* J, const double* BC, double c_j,
+                      double c_b, double* b, hipStream_t st);
+hipError_t launch_finish(const Grid& g, const double* E_n, const double* E_t, const double* BC_n,
+                         const double* curlC_Et, double ctd, double* E_next, double* BC_next, hipStream_t st);
+// out[v] = <V_v, w> for v < nv (V_v = V + v*ld); partial: >= nv*kDotBlocks doubles
+constexpr int kDotBlocks = 256;
+hipError_t launch_dots(const double* V, int64_t ld, int nv, const double* w, int64_t n, double* partial,
+                       double* out, hipStream_t st);
+// w -= sum_v coef[v] V_v  (coef: host array of nv <= kMaxRestart + 1 values,
+// passed to the kernel by value)
+constexpr int kMaxRestart = 120;
+hipError_t launch_sub_combo(const double* V, int64_t ld, int nv, const double* coef_host, double* w, int64_t n,
+                            hipStream_t st);
+// y = a x + b y
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
+hipError_t launch_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t st);
+hipError_t launch_sumsq(const double* x, int64_t n, double scale, double* partial, double* out, bool accumulate,
+                        hipStream_t st);
+
+hipError_t launch_backward(const Grid& g, bool f32, const SpeciesArgs& sp, const void* E, const void* B,
+                           const void* gJ, const void* gM, void* const gpos[3], void* const gvel[3], void* gE,
+                           void* gB, bool through_mover, hipStream_t st);
+
+}  // namespace ecsim

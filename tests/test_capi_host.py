@@ -1,0 +1,166 @@
+"""The C-ABI library: loads, exports every declared symbol, validates arguments.
+
+These run without a GPU: argument validation happens on the host before any
+HIP call, so invalid calls must return ECSIM_EINVAL / ECSIM_EWORKSPACE.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ecsim.h")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2603_16624_amd import ecsim
+    if not os.path.exists(ecsim.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return ecsim
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ecsim_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_hot_path(E):
+    names = declared_symbols()
+    for required in ("ecsim_move", "ecsim_moments", "ecsim_mass_apply", "ecsim_moments_backward"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(E):
+    L = E.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+    assert sorted(E.EXPORTED) == declared_symbols()
+
+
+def test_version(E):
+    assert "gfx950" in E.version()
+
+
+def _grid(E, n=(4, 4, 4), h=(0.5, 0.5, 0.5), dt=0.1):
+    return E.Grid(n, h, dt).c()
+
+
+def test_invalid_grid_rejected(E):
+    L = E.lib()
+    out = ctypes.c_size_t(0)
+    for n, h, dt in [((0, 4, 4), (0.5,) * 3, 0.1), ((4, 4, 4), (0.5, -1.0, 0.5), 0.1),
+                     ((4, 4, 4), (0.5,) * 3, 0.0), ((4, 4, 4), (0.5, float("nan"), 0.5), 0.1)]:
+        g = E.Grid(n, h, dt).c()
+        st = L.ecsim_workspace_size(ctypes.byref(g), 10, E.F64, 0, ctypes.byref(out))
+        assert st == E.EINVAL
+        assert b"grid" in L.ecsim_last_error()
+    assert L.ecsim_workspace_size(None, 10, E.F64, 0, ctypes.byref(out)) == E.EINVAL
+    assert L.ecsim_workspace_size(ctypes.byref(_grid(E)), 10, 7, 0, ctypes.byref(out)) == E.EINVAL
+
+
+def test_workspace_size_positive(E):
+    L = E.lib()
+    out = ctypes.c_size_t(0)
+    assert L.ecsim_workspace_size(ctypes.byref(_grid(E)), 1000, E.F32, 0, ctypes.byref(out)) == E.OK
+    assert out.value >= 2 * 4 * 1000 + 4 * 64
+
+
+def _particles(E, prec=0, np_=8, qom=-1.0, cell=False, ptr=0x1000):
+    p = E._Particles()
+    p.prec = prec
+    p.np = np_
+    p.qom = qom
+    for d in range(3):
+        p.pos[d] = ptr
+        p.vel[d] = ptr
+    p.cell = ptr if cell else None
+    p.q = None
+    p.q_const = 1.0
+    p.cell_start = None
+    return p
+
+
+def test_move_argument_validation(E):
+    L = E.lib()
+    g = _grid(E)
+    fake = ctypes.c_void_p(0x1000)
+    # NULL fields
+    p = _particles(E)
+    assert L.ecsim_move(ctypes.byref(g), ctypes.byref(p), None, fake, None, None) == E.EINVAL
+    # FP32 without a cell array
+    p = _particles(E, prec=E.F32)
+    assert L.ecsim_move(ctypes.byref(g), ctypes.byref(p), fake, fake, None, None) == E.EINVAL
+    assert b"cell" in L.ecsim_last_error()
+    # FP64 with a cell array
+    p = _particles(E, prec=E.F64, cell=True)
+    assert L.ecsim_move(ctypes.byref(g), ctypes.byref(p), fake, fake, None, None) == E.EINVAL
+    # zero charge-to-mass ratio, negative np, bad precision
+    for kw in (dict(qom=0.0), dict(np_=-1), dict(prec=3)):
+        p = _particles(E, **kw)
+        assert L.ecsim_move(ctypes.byref(g), ctypes.byref(p), fake, fake, None, None) == E.EINVAL
+    # NULL position pointer with np > 0
+    p = _particles(E)
+    p.pos[1] = None
+    assert L.ecsim_move(ctypes.byref(g), ctypes.byref(p), fake, fake, None, None) == E.EINVAL
+
+
+def test_moments_argument_validation(E):
+    L = E.lib()
+    g = _grid(E)
+    fake = ctypes.c_void_p(0x1000)
+    arr = (E._Particles * 2)(_particles(E), _particles(E, prec=E.F32, cell=True))
+    # mixed precisions
+    assert L.ecsim_moments(ctypes.byref(g), arr, 2, fake, fake, fake, None, 0, 0, None) == E.EINVAL
+    arr = (E._Particles * 1)(_particles(E))
+    # nspecies out of range, unknown flags, sorted without cell_start, NULL outputs
+    assert L.ecsim_moments(ctypes.byref(g), arr, 0, fake, fake, fake, None, 0, 0, None) == E.EINVAL
+    assert L.ecsim_moments(ctypes.byref(g), arr, 1, fake, fake, fake, None, 0, 0x80, None) == E.EINVAL
+    assert L.ecsim_moments(ctypes.byref(g), arr, 1, fake, fake, fake, None, 0, E.SORTED, None) == E.EINVAL
+    assert L.ecsim_moments(ctypes.byref(g), arr, 1, fake, None, fake, None, 0, 0, None) == E.EINVAL
+
+
+def test_mass_apply_and_solve_validation(E):
+    L = E.lib()
+    g = _grid(E)
+    fake = ctypes.c_void_p(0x1000)
+    # aliasing x and y
+    assert L.ecsim_mass_apply(ctypes.byref(g), E.F64, fake, fake, 1.0, 0.0, fake, None) == E.EINVAL
+    assert L.ecsim_mass_apply(ctypes.byref(g), 5, fake, fake, 1.0, 0.0, ctypes.c_void_p(0x2000), None) == E.EINVAL
+    out = ctypes.c_size_t(0)
+    assert L.ecsim_solve_workspace_size(ctypes.byref(g), 0, ctypes.byref(out)) == E.EINVAL
+    assert L.ecsim_solve_workspace_size(ctypes.byref(g), 30, ctypes.byref(out)) == E.OK
+    need = out.value
+    it = ctypes.c_int32(0)
+    res = ctypes.c_double(0)
+    args = [ctypes.byref(g), E.F64, fake, fake, fake, fake, 1e-10, 30, 100, fake, fake, fake]
+    # workspace too small
+    st = L.ecsim_field_solve(*args, fake, need - 1, ctypes.byref(it), ctypes.byref(res), None)
+    assert st == E.EWORKSPACE
+    # tolerance out of range
+    bad = list(args)
+    bad[6] = 0.0
+    assert L.ecsim_field_solve(*bad, fake, need, ctypes.byref(it), ctypes.byref(res), None) == E.EINVAL
+
+
+def test_sort_and_backward_validation(E):
+    L = E.lib()
+    g = _grid(E)
+    fake = ctypes.c_void_p(0x1000)
+    src = _particles(E, ptr=0x1000)
+    dst = _particles(E, ptr=0x1000)   # aliases src
+    assert L.ecsim_sort(ctypes.byref(g), ctypes.byref(src), ctypes.byref(dst), fake, None, fake, 1 << 20, None) == E.EINVAL
+    dst = _particles(E, ptr=0x9000)
+    assert L.ecsim_sort(ctypes.byref(g), ctypes.byref(src), ctypes.byref(dst), fake, None, fake, 1, None) == E.EWORKSPACE
+    p = _particles(E)
+    gp = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
+    # through the mover without E
+    st = L.ecsim_moments_backward(ctypes.byref(g), ctypes.byref(p), None, fake, fake, fake, gp, gp, fake, fake,
+                                  E.BWD_THROUGH_MOVER, None)
+    assert st == E.EINVAL
+    st = L.ecsim_moments_backward(ctypes.byref(g), ctypes.byref(p), fake, fake, fake, fake, gp, gp, fake, fake,
+                                  0x40, None)
+    assert st == E.EINVAL

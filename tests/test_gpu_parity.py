@@ -1,0 +1,426 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances (relative max-norm over each output array): 1e-12 for the FP64
+path and 1e-5 for the FP32 path. Atomic accumulation order makes the
+results non-deterministic at the rounding level, so bit-exactness is not
+asked for; FP32 inputs are compared against the oracle fed the same FP32
+values widened exactly to FP64.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import dev, host, need_gpu, periodic_rel, rel, round32, say, torch
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def E():
+    need_gpu()
+    from paper_2603_16624_amd import ecsim
+    ecsim.lib()
+    return ecsim
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def I():
+    from paper_2603_16624_amd import inputs
+    return inputs
+
+
+CASES = [((5, 4, 3), 7), ((2, 2, 2), 5), ((1, 3, 2), 6), ((8, 8, 8), 27), ((13, 7, 5), 3)]
+
+
+def make_case(I, n, ppc, seed):
+    p = I.uniform_plasma(200 + seed, n, ppc)
+    rng = np.random.default_rng(300 + seed)
+    En = 1e-2 * rng.standard_normal((3, p.nn))
+    BN = np.array([[0.02], [-0.03], [0.2]]) + 0.05 * rng.standard_normal((3, p.nn))
+    return p, En, BN
+
+
+# ---------------------------------------------------------------------------
+# mover
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,ppc", CASES)
+def test_move_f64(E, O, I, n, ppc):
+    say("move f64", n, ppc)
+    p, En, BN = make_case(I, n, ppc, 1)
+    grid = E.Grid(p.n, p.h, p.dt)
+    for s in p.species:
+        sp = E.Species.from_f64(s.qom, s.x, s.v, s.q)
+        E.move(grid, sp, dev(En), dev(BN))
+        xo, vo = O.move(p.n, p.h, p.dt, s.x, s.v, s.qom, En, BN)
+        assert rel(host(sp.vel), vo) < TOL64
+        assert periodic_rel(host(sp.pos), xo, p.L) < TOL64
+
+
+@pytest.mark.parametrize("n,ppc", CASES)
+def test_move_f32(E, O, I, n, ppc):
+    say("move f32", n, ppc)
+    p, En, BN = make_case(I, n, ppc, 2)
+    grid = E.Grid(p.n, p.h, p.dt)
+    for s, f in zip(p.species, I.to_f32_state(p)):
+        sp = E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"])
+        E.move(grid, sp, dev(En, torch.float32), dev(BN, torch.float32))
+        xo, vo = O.move(p.n, p.h, p.dt, f["x64"], f["v64"], s.qom, round32(En), round32(BN))
+        assert rel(host(sp.vel), vo) < TOL32
+        x32 = I.decode_f32(host(sp.cell), host(sp.pos), p.n, p.h)
+        assert periodic_rel(x32, xo, p.L) < TOL32
+        off = host(sp.pos)
+        assert np.all((off >= 0) & (off < 1))
+
+
+def test_move_kinetic_energy_and_edge_positions(E, O, I):
+    """Particles exactly on node planes and crossing the periodic boundary."""
+    say("move edges")
+    n = (4, 3, 5)
+    h = (0.5, 0.5, 0.5)
+    L = [n[d] * h[d] for d in range(3)]
+    x = np.array([[0.0, 0.5, L[0] - 1e-9, 1.0, L[0] - 0.01],
+                  [0.0, 1.0, 0.7, L[1] - 1e-12, 0.01],
+                  [0.0, 2.0, 1.1, 0.25, L[2] - 0.001]])
+    v = np.array([[0.01, -0.3, 0.5, -0.2, 0.4],
+                  [0.02, 0.1, -0.4, 0.3, -0.3],
+                  [-0.03, 0.2, 0.1, -0.5, 0.2]])
+    q = np.array([1e-3, 2e-3, -1e-3, 5e-4, 3e-3])
+    rng = np.random.default_rng(5)
+    nn = int(np.prod(n))
+    En = 1e-2 * rng.standard_normal((3, nn))
+    BN = 0.1 * rng.standard_normal((3, nn))
+    grid = E.Grid(n, h, 0.1)
+    sp = E.Species.from_f64(-1.0, x, v, q)
+    ke = torch.zeros(1, dtype=torch.float64, device="cuda")
+    E.move(grid, sp, dev(En), dev(BN), ke)
+    xo, vo = O.move(n, h, 0.1, x, v, -1.0, En, BN)
+    assert rel(host(sp.vel), vo) < TOL64
+    assert periodic_rel(host(sp.pos), xo, L) < TOL64
+    assert np.all((host(sp.pos) >= 0) & (host(sp.pos) < np.array(L)[:, None]))
+    assert abs(host(ke)[0] - O.kinetic(vo, q, -1.0)) <= 1e-14 * abs(O.kinetic(vo, q, -1.0))
+
+
+def test_empty_species(E, I):
+    say("empty species")
+    grid = E.Grid((3, 3, 3), (0.5,) * 3, 0.1)
+    sp = E.Species.from_f64(-1.0, np.zeros((3, 0)), np.zeros((3, 0)), 1.0)
+    B = torch.zeros((3, 27), dtype=torch.float64, device="cuda")
+    E.move(grid, sp, B, B)
+    J = torch.ones((3, 27), dtype=torch.float64, device="cuda")
+    M = torch.ones((14, 9, 27), dtype=torch.float64, device="cuda")
+    E.moments(grid, [sp], B, J, M)
+    assert np.all(host(J) == 0) and np.all(host(M) == 0)
+
+
+# ---------------------------------------------------------------------------
+# moments
+# ---------------------------------------------------------------------------
+
+def oracle_moments(O, p, xs, vs, qs, BN):
+    J = np.zeros((3, p.nn))
+    M27 = np.zeros((27, 9, p.nn))
+    for s, x, v, q in zip(p.species, xs, vs, qs):
+        O.moments(p.n, p.h, p.dt, x, v, q, s.qom, BN, J, M27)
+    return J, O.m14(p.n, M27)
+
+
+@pytest.mark.parametrize("n,ppc", CASES)
+def test_moments_f64_any_order(E, O, I, n, ppc):
+    say("moments f64 atomic", n, ppc)
+    p, _, BN = make_case(I, n, ppc, 3)
+    grid = E.Grid(p.n, p.h, p.dt)
+    sp = [E.Species.from_f64(s.qom, s.x, s.v, s.q) for s in p.species]
+    J = torch.empty((3, p.nn), dtype=torch.float64, device="cuda")
+    M = torch.empty((14, 9, p.nn), dtype=torch.float64, device="cuda")
+    E.moments(grid, sp, dev(BN), J, M)
+    Jo, Mo = oracle_moments(O, p, [s.x for s in p.species], [s.v for s in p.species], [s.q for s in p.species], BN)
+    assert rel(host(J), Jo) < TOL64
+    assert rel(host(M), Mo) < TOL64
+
+
+@pytest.mark.parametrize("n,ppc", CASES)
+def test_moments_f32_any_order(E, O, I, n, ppc):
+    say("moments f32 atomic", n, ppc)
+    p, _, BN = make_case(I, n, ppc, 4)
+    grid = E.Grid(p.n, p.h, p.dt)
+    st = I.to_f32_state(p)
+    sp = [E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"]) for s, f in zip(p.species, st)]
+    J = torch.empty((3, p.nn), dtype=torch.float32, device="cuda")
+    M = torch.empty((14, 9, p.nn), dtype=torch.float32, device="cuda")
+    E.moments(grid, sp, dev(BN, torch.float32), J, M)
+    Jo, Mo = oracle_moments(O, p, [f["x64"] for f in st], [f["v64"] for f in st], [f["q64"] for f in st],
+                            round32(BN))
+    assert rel(host(J), Jo) < TOL32
+    assert rel(host(M), Mo) < TOL32
+
+
+def test_moments_accumulate_flag(E, O, I):
+    say("moments accumulate")
+    p, _, BN = make_case(I, (4, 4, 4), 5, 5)
+    grid = E.Grid(p.n, p.h, p.dt)
+    sp = [E.Species.from_f64(s.qom, s.x, s.v, s.q) for s in p.species]
+    J = torch.empty((3, p.nn), dtype=torch.float64, device="cuda")
+    M = torch.empty((14, 9, p.nn), dtype=torch.float64, device="cuda")
+    E.moments(grid, sp[:1], dev(BN), J, M)
+    E.moments(grid, sp[1:], dev(BN), J, M, flags=E.ACCUMULATE)
+    Jo, Mo = oracle_moments(O, p, [s.x for s in p.species], [s.v for s in p.species], [s.q for s in p.species], BN)
+    assert rel(host(J), Jo) < TOL64 and rel(host(M), Mo) < TOL64
+
+
+# ---------------------------------------------------------------------------
+# sort
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_sort(E, I, f32):
+    say("sort", f32)
+    p = I.config1(ppc=4, n=(16, 8, 4))
+    grid = E.Grid(p.n, p.h, p.dt)
+    s = p.species[0]     # electrons: random order
+    if f32:
+        f = I.to_f32_state(p)[0]
+        src = E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"])
+        key = f["cell"].astype(np.int64)
+    else:
+        src = E.Species.from_f64(s.qom, s.x, s.v, s.q)
+        ijk = [np.floor(s.x[d] / p.h[d]).astype(np.int64) for d in range(3)]
+        key = ijk[0] + p.n[0] * (ijk[1] + p.n[1] * ijk[2])
+    dst = src.empty_like()
+    cs = torch.empty(p.nn + 1, dtype=torch.int32, device="cuda")
+    perm = torch.empty(s.np, dtype=torch.int32, device="cuda")
+    E.sort(grid, src, dst, cs, perm)
+    perm_h = host(perm).astype(np.int64)
+    assert np.array_equal(np.sort(perm_h), np.arange(s.np))
+    # keys are non-decreasing in the output and cell_start brackets each cell
+    kd = key[perm_h]
+    assert np.all(np.diff(kd) >= 0)
+    cs_h = host(cs).astype(np.int64)
+    assert cs_h[0] == 0 and cs_h[-1] == s.np
+    assert np.array_equal(cs_h[:-1], np.searchsorted(kd, np.arange(p.nn), side="left"))
+    # payload moved with its key
+    assert np.array_equal(host(dst.pos), host(src.pos)[:, perm_h])
+    assert np.array_equal(host(dst.vel), host(src.vel)[:, perm_h])
+    if f32:
+        assert np.array_equal(host(dst.cell), host(src.cell)[perm_h])
+
+
+# ---------------------------------------------------------------------------
+# mass-matrix apply
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,ppc", CASES)
+@pytest.mark.parametrize("mprec", ["f64", "f32"])
+def test_mass_apply(E, O, I, n, ppc, mprec):
+    say("mass apply", mprec, n, ppc)
+    p, _, BN = make_case(I, n, ppc, 6)
+    _, M27 = O.species_moments(p, [s.x for s in p.species], [s.v for s in p.species], BN)
+    M14 = O.m14(p.n, M27)
+    if mprec == "f32":
+        M14 = round32(M14)
+        M27 = round32(M27)
+    x = np.random.default_rng(7).standard_normal((3, p.nn))
+    y0 = np.random.default_rng(8).standard_normal((3, p.nn))
+    grid = E.Grid(p.n, p.h, p.dt)
+    Mt = dev(M14, torch.float32 if mprec == "f32" else torch.float64)
+    y = dev(y0)
+    E.mass_apply(grid, Mt, dev(x), y, a=0.7, b=-0.3)
+    ref = 0.7 * O.mass_apply27(p.n, M27, x) - 0.3 * y0
+    assert rel(host(y), ref) < TOL64
+
+
+def test_mass_apply_dense_2x2x2(E, O, I):
+    """Every unit vector through the 14-block apply equals the dense brute-force operator."""
+    say("mass apply dense 2x2x2")
+    p, _, BN = make_case(I, (2, 2, 2), 5, 9)
+    _, M27 = O.species_moments(p, [s.x for s in p.species], [s.v for s in p.species], BN)
+    grid = E.Grid(p.n, p.h, p.dt)
+    Mt = dev(O.m14(p.n, M27))
+    n3 = 3 * p.nn
+    eye = np.eye(n3)
+    cols = np.zeros((n3, n3))
+    for j in range(n3):
+        y = torch.zeros((3, p.nn), dtype=torch.float64, device="cuda")
+        E.mass_apply(grid, Mt, dev(eye[j].reshape(3, -1)), y)
+        cols[:, j] = host(y).ravel()
+    ref = np.stack([O.mass_apply27(p.n, M27, eye[j].reshape(3, -1)).ravel() for j in range(n3)], axis=1)
+    assert rel(cols, ref) < TOL64
+
+
+# ---------------------------------------------------------------------------
+# field solve and the full step
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mprec", ["f64", "f32"])
+def test_field_solve(E, O, I, mprec):
+    say("field solve", mprec)
+    p, _, BN = make_case(I, (6, 5, 4), 6, 10)
+    J, M27 = O.species_moments(p, [s.x for s in p.species], [s.v for s in p.species], BN)
+    rng = np.random.default_rng(11)
+    En = 1e-3 * rng.standard_normal((3, p.nn))
+    BC = BN + 1e-3 * rng.standard_normal((3, p.nn))
+    M14 = O.m14(p.n, M27)
+    tdt = torch.float64
+    if mprec == "f32":
+        M14, M27, J = round32(M14), round32(M27), round32(J)
+        tdt = torch.float32
+    ref = O.field_solve(p.n, p.h, p.dt, M27, J, En, BC, tol=1e-13)
+    grid = E.Grid(p.n, p.h, p.dt)
+    Et, En1, Bn1 = (torch.empty((3, p.nn), dtype=torch.float64, device="cuda") for _ in range(3))
+    it, res = E.field_solve(grid, dev(M14, tdt), dev(J, tdt), dev(En), dev(BC), Et, En1, Bn1, tol=1e-10)
+    assert it > 0 and res <= 1e-10
+    assert rel(host(Et), ref["E_theta"]) < 1e-9
+    assert rel(host(En1), ref["E_next"]) < 1e-9
+    assert rel(host(Bn1), ref["BC_next"]) < 1e-9
+    # independent residual check with the oracle's operator
+    b = O.field_rhs(p.n, p.h, p.dt, J, En, BC)
+    r = b - O.field_operator(p.n, p.h, p.dt, M27, host(Et))
+    assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
+
+
+def test_centres_to_nodes_and_energy(E, O, I):
+    say("centres to nodes, field energy")
+    n = (5, 6, 7)
+    rng = np.random.default_rng(12)
+    BC = rng.standard_normal((3, 210))
+    grid = E.Grid(n, (0.5,) * 3, 0.1)
+    BN = torch.empty((3, 210), dtype=torch.float64, device="cuda")
+    BN32 = torch.empty((3, 210), dtype=torch.float32, device="cuda")
+    E.centres_to_nodes(grid, dev(BC), BN, BN32)
+    ref = O.centres_to_nodes(n, BC)
+    assert rel(host(BN), ref) < 1e-15
+    assert rel(host(BN32), ref) < 1e-7
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    E.field_energy(grid, dev(BC), out)
+    assert abs(host(out)[0] - O.field_energy(n, (0.5,) * 3, BC)) < 1e-13 * O.field_energy(n, (0.5,) * 3, BC)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_small_workload_ten_steps(E, O, I, prec):
+    """8^3 cells, 27 ppc x 2 species, 10 steps: state parity and energy drift."""
+    say("config-0 ten steps", prec)
+    p = I.config0()
+    P = E.F64 if prec == "f64" else E.F32
+    sim = E.Simulation(p, prec=P, tol=1e-10, sort=False)
+    if prec == "f32":
+        st = I.to_f32_state(p)
+        for s, f in zip(p.species, st):
+            s.x, s.v, s.q = f["x64"], f["v64"], f["q64"]
+    vs = [s.v for s in p.species]
+    K0 = sum(O.kinetic(v, s.q, s.qom) for s, v in zip(p.species, vs))
+    WE0, WB0 = sim.energy()
+    e0 = K0 + WE0 + WB0
+    drift = 0.0
+    for step in range(10):
+        sim.step()
+        K = host(sim.scal)[0]
+        WE, WB = sim.energy()
+        drift = max(drift, abs(K + WE + WB - e0) / e0)
+        assert sim.last_resid <= 1e-10
+    say("drift", drift)
+    if prec == "f64":
+        assert drift <= 1e-10
+        ref, _ = O.run_steps(p, 10, tol=1e-13)
+        assert rel(host(sim.E), ref["E"]) < 1e-9
+        for s, x, v in zip(sim.species, ref["x"], ref["v"]):
+            assert rel(host(s.vel), v) < 1e-9
+            assert periodic_rel(host(s.pos), x, p.L) < 1e-9
+    else:
+        # FP32 particle arithmetic: energy error from FP32 rounding of v, J and M
+        assert drift <= 1e-6
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+
+def grad_case(I, n=(5, 4, 4), ppc=4, seed=13):
+    p = I.uniform_plasma(400 + seed, n, ppc)
+    rng = np.random.default_rng(500 + seed)
+    En = 1e-2 * rng.standard_normal((3, p.nn))
+    BN = np.array([[0.0], [0.05], [0.2]]) + 0.05 * rng.standard_normal((3, p.nn))
+    gJ = rng.standard_normal((3, p.nn))
+    gM = rng.standard_normal((14, 9, p.nn))
+    return p, En, BN, gJ, gM
+
+
+@pytest.mark.parametrize("n,ppc", [((5, 4, 4), 4), ((2, 2, 2), 6), ((3, 1, 2), 5)])
+def test_backward_f64_matches_dual_oracle(E, O, I, n, ppc):
+    say("backward f64", n, ppc)
+    p, En, BN, gJ, gM = grad_case(I, n, ppc)
+    grid = E.Grid(p.n, p.h, p.dt)
+    gE = torch.zeros((3, p.nn), dtype=torch.float64, device="cuda")
+    gB = torch.zeros((3, p.nn), dtype=torch.float64, device="cuda")
+    gEo = np.zeros((3, p.nn))
+    gBo = np.zeros((3, p.nn))
+    for s in p.species:
+        sp = E.Species.from_f64(s.qom, s.x, s.v, s.q)
+        gx = torch.empty_like(sp.pos)
+        gv = torch.empty_like(sp.vel)
+        E.moments_backward(grid, sp, dev(En), dev(BN), dev(gJ), dev(gM), gx, gv, gE, gB, through_mover=True)
+        gxo, gvo, _, _ = O.grad(p.n, p.h, p.dt, s.x, s.v, s.q, s.qom, En, BN, gJ, gM, gEo, gBo)
+        assert rel(host(gx), gxo) < TOL64
+        assert rel(host(gv), gvo) < TOL64
+    assert rel(host(gE), gEo) < TOL64
+    assert rel(host(gB), gBo) < TOL64
+
+
+def test_backward_f32_matches_dual_oracle(E, O, I):
+    say("backward f32")
+    p, En, BN, gJ, gM = grad_case(I, (5, 4, 4), 4, 14)
+    grid = E.Grid(p.n, p.h, p.dt)
+    gE = torch.zeros((3, p.nn), dtype=torch.float32, device="cuda")
+    gB = torch.zeros((3, p.nn), dtype=torch.float32, device="cuda")
+    gEo = np.zeros((3, p.nn))
+    gBo = np.zeros((3, p.nn))
+    E32, B32, gJ32, gM32 = round32(En), round32(BN), round32(gJ), round32(gM)
+    for s, f in zip(p.species, I.to_f32_state(p)):
+        sp = E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"])
+        gx = torch.empty_like(sp.pos)
+        gv = torch.empty_like(sp.vel)
+        E.moments_backward(grid, sp, dev(E32, torch.float32), dev(B32, torch.float32), dev(gJ32, torch.float32),
+                           dev(gM32, torch.float32), gx, gv, gE, gB, through_mover=True)
+        gxo, gvo, _, _ = O.grad(p.n, p.h, p.dt, f["x64"], f["v64"], f["q64"], s.qom, E32, B32, gJ32, gM32, gEo, gBo)
+        assert rel(host(gx), gxo) < TOL32
+        assert rel(host(gv), gvo) < TOL32
+    assert rel(host(gE), gEo) < TOL32
+    assert rel(host(gB), gBo) < TOL32
+
+
+def test_backward_moments_only_matches_fd(E, O, I):
+    """Without the mover: dL/dx, dL/dv of <gJ,J> + <gM,M> by central differences of the oracle's moments."""
+    say("backward moments-only")
+    p, En, BN, gJ, gM = grad_case(I, (4, 4, 3), 2, 15)
+    grid = E.Grid(p.n, p.h, p.dt)
+    s = p.species[0]
+    sp = E.Species.from_f64(s.qom, s.x, s.v, s.q)
+    gx = torch.empty_like(sp.pos)
+    gv = torch.empty_like(sp.vel)
+    gB = torch.zeros((3, p.nn), dtype=torch.float64, device="cuda")
+    E.moments_backward(grid, sp, None, dev(BN), dev(gJ), dev(gM), gx, gv, None, gB, through_mover=False)
+    gx, gv = host(gx), host(gv)
+
+    def loss_one(x, v, i):
+        J, M27 = O.moments(p.n, p.h, p.dt, x[:, i:i + 1], v[:, i:i + 1], s.q[i:i + 1], s.qom, BN)
+        return np.sum(gJ * J) + np.sum(gM * O.m14(p.n, M27))
+
+    eps = 1e-6
+    for i in range(0, s.np, max(1, s.np // 12)):
+        for c in range(3):
+            for arr, g in ((s.x, gx), (s.v, gv)):
+                up = arr.copy(); up[c, i] += eps
+                dn = arr.copy(); dn[c, i] -= eps
+                if arr is s.x:
+                    fd = (loss_one(up, s.v, i) - loss_one(dn, s.v, i)) / (2 * eps)
+                else:
+                    fd = (loss_one(s.x, up, i) - loss_one(s.x, dn, i)) / (2 * eps)
+                assert abs(g[c, i] - fd) <= 1e-6 * max(np.max(np.abs(g)), 1e-30)
