@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark of the ECsim per-step particle hot path on one MI355X.
+
+Workload (synthetic, seeded): 64^3 periodic cells, cell size 0.5 d_e, dt = 0.1,
+two species (electrons q/m = -1, ions q/m = 1/25) with 64 particles per cell
+each (33,554,432 particles), Maxwellian velocities (v_th 0.05 / 0.01),
+electron density perturbed by 1% cos(2 pi x / L_x), B0 = (0, 0, 0.2), E = 0.
+
+One step is the scheme's step: cell sort -> moment gather (J-hat, M) ->
+FP64 GMRES field solve (tol 1e-10) -> mover. The metric is particles per
+second through mover + moments (+ the sort that keeps the deposit tiled), in
+the FP32 storage form (headline) and the FP64 form; the field solve is run in
+every step and reported separately. Times are HIP events on the stream the
+kernels run on, inside a region bracketed by device synchronisation.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--ppc", type=int, default=64)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 form")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=8, help="oracle runs on 1/cpu-sample of the particles")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(prec, nparticles, nn):
+    """Bytes the method must move per step through sort + moments + mover.
+
+    Per particle: the state (positions + velocities [+ cell]) read and written
+    once by the mover and read once by the deposit; per node: E^{n+theta} and
+    B^n read by the mover, B read by the deposit, J-hat and the 14 x 9 mass
+    matrix entries written once.
+    """
+    if prec == "f32":
+        part = 28          # 3 offsets + cell + 3 velocities
+        fld = 4
+    else:
+        part = 48          # 3 positions + 3 velocities
+        fld = 8
+    per_particle = part * 3                # deposit read, mover read + write
+    per_node = fld * (3 + 3 + 3 + 3 + 126)  # E, B (mover), B (deposit), J, M
+    deposit = part * nparticles + fld * (3 + 3 + 126) * nn
+    return per_particle * nparticles + per_node * nn, deposit
+
+
+def run_form(prec, args, plasma):
+    import torch
+    from paper_2603_16624_amd import ecsim as E
+    P = E.F32 if prec == "f32" else E.F64
+    sim = E.Simulation(plasma, prec=P, tol=1e-10, sort=True)
+    st = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def one_step(record):
+        e = [ev() for _ in range(8)]
+        e[0].record(st)
+        sim.sort_particles()
+        e[1].record(st)
+        sim.node_B()
+        e[2].record(st)
+        sim.deposit()
+        e[3].record(st)
+        sim.solve()
+        e[4].record(st)
+        sim.scal[0] = 0.0
+        e[5].record(st)
+        sim.push(sim.scal[0:1])
+        e[6].record(st)
+        sim.advance_fields()
+        e[7].record(st)
+        if record is not None:
+            record.append(e)
+
+    for _ in range(args.warmup):
+        one_step(None)
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step(rec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sort_ms = [r[0].elapsed_time(r[1]) for r in rec]
+    mom_ms = [r[2].elapsed_time(r[3]) for r in rec]
+    solve_ms = [r[3].elapsed_time(r[4]) for r in rec]
+    move_ms = [r[5].elapsed_time(r[6]) for r in rec]
+    full_ms = [r[0].elapsed_time(r[7]) for r in rec]
+    mean = lambda a: sum(a) / len(a)
+    pass_ms = mean(sort_ms) + mean(mom_ms) + mean(move_ms)
+    npart = plasma.n_particles
+    total_bytes, dep_bytes = algorithmic_bytes(prec, npart, plasma.nn)
+    return dict(prec=prec, particles=npart, pass_ms=pass_ms, sort_ms=mean(sort_ms), moments_ms=mean(mom_ms),
+                move_ms=mean(move_ms), solve_ms=mean(solve_ms), full_step_ms=mean(full_ms), wall_s=wall,
+                gmres_iters=sim.last_iters, gmres_resid=sim.last_resid,
+                particles_per_s=npart / (pass_ms * 1e-3), bytes_per_step=total_bytes,
+                hbm_frac_pass=total_bytes / (pass_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                deposit_bytes=dep_bytes, deposit_gbs=dep_bytes / (mean(mom_ms) * 1e-3) / 1e9)
+
+
+def cpu_baseline(plasma, sample):
+    """The FP64 oracle's mover + moments on 1/sample of the particles, on the host."""
+    import numpy as np
+    from oracle import oracle as O
+    rng = np.random.default_rng(12345)
+    BN = O.centres_to_nodes(plasma.n, plasma.B_C)
+    En = 1e-4 * rng.standard_normal((3, plasma.nn))
+    nn = plasma.nn
+    J = np.zeros((3, nn))
+    M27 = np.zeros((27, 9, nn))
+    count = 0
+    t0 = time.perf_counter()
+    for s in plasma.species:
+        k = max(1, s.np // sample)
+        x = np.ascontiguousarray(s.x[:, :k])
+        v = np.ascontiguousarray(s.v[:, :k])
+        x1, v1 = O.move(plasma.n, plasma.h, plasma.dt, x, v, s.qom, En, BN)
+        O.moments(plasma.n, plasma.h, plasma.dt, x1, v1, s.q[:k], s.qom, BN, J, M27)
+        count += k
+    dt = time.perf_counter() - t0
+    return dict(value=count / dt, unit="particles/s", cores=1, kind="oracle",
+                sample=f"FP64 oracle mover+moments on {count} particles (1/{sample} of each species) "
+                       f"of the 64^3 workload, single thread, {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_2603_16624_amd import ecsim as E
+    from paper_2603_16624_amd import inputs as I
+    if not os.path.exists(E.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    t0 = time.perf_counter()
+    plasma = I.config1(ppc=args.ppc, n=(args.n, args.n, args.n))
+    print(f"[bench] workload generated in {time.perf_counter() - t0:.1f} s: {plasma.name}", file=sys.stderr,
+          flush=True)
+    r32 = run_form("f32", args, plasma)
+    print(f"[bench] f32: {json.dumps(r32)}", file=sys.stderr, flush=True)
+    r64 = None
+    if not args.no_fp64:
+        torch.cuda.empty_cache()
+        r64 = run_form("f64", args, plasma)
+        print(f"[bench] f64: {json.dumps(r64)}", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(plasma, args.cpu_sample)
+        print(f"[bench] cpu: {json.dumps(cpu)}", file=sys.stderr, flush=True)
+    achieved = r32["deposit_gbs"]
+    out = {
+        "metric": "particles/s through mover+moments (FP32 vs FP64) at fixed error; % HBM peak",
+        "value": r32["particles_per_s"],
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["pass_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{plasma.name}; FP32 offset+cell storage, FP32 mover and deposit, "
+                               f"FP64 GMRES (tol 1e-10)",
+                   "cells": list(plasma.n), "particles": plasma.n_particles, "ppc_per_species": args.ppc,
+                   "parallelism": "single GPU"},
+        "hbm_frac": r32["hbm_frac_pass"],
+        "breakdown_ms": {k: r32[k] for k in ("sort_ms", "moments_ms", "move_ms", "solve_ms", "full_step_ms")},
+        "gmres": {"iters_last": r32["gmres_iters"], "rel_resid_last": r32["gmres_resid"]},
+        "fp64": None if r64 is None else {
+            "value": r64["particles_per_s"], "ms_per_step": r64["pass_ms"], "hbm_frac": r64["hbm_frac_pass"],
+            "breakdown_ms": {k: r64[k] for k in ("sort_ms", "moments_ms", "move_ms", "solve_ms", "full_step_ms")}},
+        "roofline": {"kernel": "ecsim_moments (FP32)", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -13,11 +13,30 @@
 
 namespace ecsim {
 
+// Division by a runtime constant for numerators below 2^24: a float
+// reciprocal estimate, off by at most one, corrected with one remainder test.
+struct FastDiv {
+  uint32_t d;
+  float inv;
+};
+
+__device__ __forceinline__ uint32_t fast_divmod(uint32_t n, FastDiv f, uint32_t& r) {
+  uint32_t q = (uint32_t)((float)n * f.inv);
+  int32_t rr = (int32_t)(n - q * f.d);
+  if (rr < 0) { q -= 1; rr += (int32_t)f.d; }
+  else if (rr >= (int32_t)f.d) { q += 1; rr -= (int32_t)f.d; }
+  r = (uint32_t)rr;
+  return q;
+}
+
 struct Grid {
   int nx, ny, nz;
   double hx, hy, hz, dt;
   int64_t nn;        // nodes = cells
   double V;          // control volume of a node
+  FastDiv div_x;     // by nx
+  FastDiv div_xy;    // by nx * ny
+  int fastdiv;       // nn < 2^24: cell indices decode with FastDiv
 };
 
 template <typename T> struct Vec3 { T x, y, z; };
@@ -57,12 +76,24 @@ __device__ __forceinline__ Stencil<double> stencil_abs(const Grid& g, double x, 
 }
 
 // FP32 form: int32 cell index + in-cell offsets in [0, 1).
+__device__ __forceinline__ void decode_cell(const Grid& g, int cell, int& ix, int& iy, int& iz) {
+  if (g.fastdiv) {
+    uint32_t r, r2;
+    iz = (int)fast_divmod((uint32_t)cell, g.div_xy, r);
+    iy = (int)fast_divmod(r, g.div_x, r2);
+    ix = (int)r2;
+  } else {
+    ix = cell % g.nx;
+    int t = cell / g.nx;
+    iy = t % g.ny;
+    iz = t / g.ny;
+  }
+}
+
 __device__ __forceinline__ Stencil<float> stencil_cell(const Grid& g, int cell, float ox, float oy, float oz) {
   Stencil<float> s;
-  int ix = cell % g.nx;
-  int t = cell / g.nx;
-  int iy = t % g.ny;
-  int iz = t / g.ny;
+  int ix, iy, iz;
+  decode_cell(g, cell, ix, iy, iz);
   s.i[0] = ix; s.i[1] = iy; s.i[2] = iz;
   s.ip[0] = wrap_up(ix, g.nx); s.ip[1] = wrap_up(iy, g.ny); s.ip[2] = wrap_up(iz, g.nz);
   s.w1[0] = ox; s.w1[1] = oy; s.w1[2] = oz;
@@ -165,8 +196,12 @@ __device__ __forceinline__ float push_offset(float o, float v, float dth, int& i
   float r = u - fl;
   int shift = (int)fl;
   if (r >= 1.0f) { r = 0.0f; shift += 1; }
-  int j = (idx + shift) % n;
-  idx = j < 0 ? j + n : j;
+  int j = idx + shift;
+  if (j < 0 || j >= n) {
+    j %= n;
+    if (j < 0) j += n;
+  }
+  idx = j;
   return r;
 }
 

@@ -50,9 +50,8 @@ __global__ void __launch_bounds__(kBlock) k_move(Grid g, int np, T* __restrict__
                                                  const T* __restrict__ E, const T* __restrict__ B, T beta,
                                                  T dth0, T dth1, T dth2, const T* __restrict__ q,
                                                  double q_const, double inv_qom, double* ke) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
   double kel = 0.0;
-  if (p < np) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < np; p += gridDim.x * kBlock) {
     Stencil<T> s = PState<T, CELL>::stencil(g, p0, p1, p2, cell, p);
     T W[8];
     int64_t nd[8];
@@ -84,7 +83,7 @@ __global__ void __launch_bounds__(kBlock) k_move(Grid g, int np, T* __restrict__
     if (ke) {
       double qp = q ? (double)q[p] : q_const;
       double vx = vn.x, vy = vn.y, vz = vn.z;
-      kel = 0.5 * (qp * inv_qom) * ((vx * vx + vy * vy) + vz * vz);
+      kel += 0.5 * (qp * inv_qom) * ((vx * vx + vy * vy) + vz * vz);
     }
   }
   if (ke) {
@@ -261,6 +260,11 @@ __global__ void __launch_bounds__(kBlock) k_sort_scatter(
 }
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+// grid-stride kernels: enough blocks to fill 256 CUs several times over
+inline unsigned nblocks_capped(int64_t n, int b) {
+  unsigned nb = nblocks(n, b);
+  return nb < 4096u ? nb : 4096u;
+}
 
 }  // namespace
 
@@ -273,13 +277,13 @@ hipError_t launch_move(const Grid& g, bool f32, const SpeciesArgs& sp, const voi
   const double beta = sp.qom * g.dt / 2.0;
   const double inv_qom = 1.0 / sp.qom;
   if (f32) {
-    hipLaunchKernelGGL((k_move<float, true>), dim3(nblocks(sp.np, kBlock)), dim3(kBlock), 0, st, g, sp.np,
+    hipLaunchKernelGGL((k_move<float, true>), dim3(nblocks_capped(sp.np, kBlock)), dim3(kBlock), 0, st, g, sp.np,
                        (float*)sp.pos[0], (float*)sp.pos[1], (float*)sp.pos[2], sp.cell, (float*)sp.vel[0],
                        (float*)sp.vel[1], (float*)sp.vel[2], (const float*)E, (const float*)B, (float)beta,
                        (float)(g.dt / g.hx), (float)(g.dt / g.hy), (float)(g.dt / g.hz), (const float*)sp.q,
                        sp.q_const, inv_qom, ke);
   } else {
-    hipLaunchKernelGGL((k_move<double, false>), dim3(nblocks(sp.np, kBlock)), dim3(kBlock), 0, st, g, sp.np,
+    hipLaunchKernelGGL((k_move<double, false>), dim3(nblocks_capped(sp.np, kBlock)), dim3(kBlock), 0, st, g, sp.np,
                        (double*)sp.pos[0], (double*)sp.pos[1], (double*)sp.pos[2], (int32_t*)nullptr,
                        (double*)sp.vel[0], (double*)sp.vel[1], (double*)sp.vel[2], (const double*)E,
                        (const double*)B, beta, 0.0, 0.0, 0.0, (const double*)sp.q, sp.q_const, inv_qom, ke);

@@ -164,6 +164,60 @@ def test_moments_f32_any_order(E, O, I, n, ppc):
     assert rel(host(M), Mo) < TOL32
 
 
+def sorted_species(E, grid, sp):
+    out = []
+    for s in sp:
+        d = s.empty_like()
+        cs = torch.empty(grid.nn + 1, dtype=torch.int32, device="cuda")
+        E.sort(grid, s, d, cs)
+        out.append(d)
+    return out
+
+
+@pytest.mark.parametrize("n,ppc", CASES + [((16, 8, 4), 40), ((4, 4, 4), 130)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_moments_sorted_tiled(E, O, I, n, ppc, prec):
+    """The tiled LDS deposit over cell-sorted particles (cells with > 64 particles included)."""
+    say("moments tiled", prec, n, ppc)
+    p, _, BN = make_case(I, n, ppc, 16)
+    grid = E.Grid(p.n, p.h, p.dt)
+    if prec == "f64":
+        sp = [E.Species.from_f64(s.qom, s.x, s.v, s.q) for s in p.species]
+        xs, vs, qs, B = [s.x for s in p.species], [s.v for s in p.species], [s.q for s in p.species], BN
+        tdt, tol = torch.float64, TOL64
+    else:
+        st = I.to_f32_state(p)
+        sp = [E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"]) for s, f in zip(p.species, st)]
+        xs, vs, qs, B = [f["x64"] for f in st], [f["v64"] for f in st], [f["q64"] for f in st], round32(BN)
+        tdt, tol = torch.float32, TOL32
+    sp = sorted_species(E, grid, sp)
+    J = torch.full((3, p.nn), 7.0, dtype=tdt, device="cuda")
+    M = torch.full((14, 9, p.nn), 7.0, dtype=tdt, device="cuda")
+    E.moments(grid, sp, dev(B, tdt), J, M, flags=E.SORTED)
+    Jo, Mo = oracle_moments(O, p, xs, vs, qs, B)
+    assert rel(host(J), Jo) < tol
+    assert rel(host(M), Mo) < tol
+
+
+def test_moments_tiled_variable_charge(E, O, I):
+    """Per-particle charges (the double-Harris layout) through the tiled deposit."""
+    say("moments tiled variable q")
+    p = I.harris(n=(8, 32, 4), ppc=6)
+    BN = O.centres_to_nodes(p.n, p.B_C)
+    grid = E.Grid(p.n, p.h, p.dt)
+    st = I.to_f32_state(p)
+    sp = [E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"]) for s, f in zip(p.species, st)]
+    assert sp[0].q is not None
+    sp = sorted_species(E, grid, sp)
+    J = torch.empty((3, p.nn), dtype=torch.float32, device="cuda")
+    M = torch.empty((14, 9, p.nn), dtype=torch.float32, device="cuda")
+    E.moments(grid, sp, dev(BN, torch.float32), J, M, flags=E.SORTED)
+    Jo, Mo = oracle_moments(O, p, [f["x64"] for f in st], [f["v64"] for f in st], [f["q64"] for f in st],
+                            round32(BN))
+    assert rel(host(J), Jo) < TOL32
+    assert rel(host(M), Mo) < TOL32
+
+
 def test_moments_accumulate_flag(E, O, I):
     say("moments accumulate")
     p, _, BN = make_case(I, (4, 4, 4), 5, 5)
@@ -305,12 +359,13 @@ def test_centres_to_nodes_and_energy(E, O, I):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_small_workload_ten_steps(E, O, I, prec):
+@pytest.mark.parametrize("sort", [False, True])
+def test_small_workload_ten_steps(E, O, I, prec, sort):
     """8^3 cells, 27 ppc x 2 species, 10 steps: state parity and energy drift."""
-    say("config-0 ten steps", prec)
+    say("config-0 ten steps", prec, "sorted" if sort else "unsorted")
     p = I.config0()
     P = E.F64 if prec == "f64" else E.F32
-    sim = E.Simulation(p, prec=P, tol=1e-10, sort=False)
+    sim = E.Simulation(p, prec=P, tol=1e-10, sort=sort)
     if prec == "f32":
         st = I.to_f32_state(p)
         for s, f in zip(p.species, st):
@@ -331,9 +386,18 @@ def test_small_workload_ten_steps(E, O, I, prec):
         assert drift <= 1e-10
         ref, _ = O.run_steps(p, 10, tol=1e-13)
         assert rel(host(sim.E), ref["E"]) < 1e-9
-        for s, x, v in zip(sim.species, ref["x"], ref["v"]):
-            assert rel(host(s.vel), v) < 1e-9
-            assert periodic_rel(host(s.pos), x, p.L) < 1e-9
+        if not sort:
+            for s, x, v in zip(sim.species, ref["x"], ref["v"]):
+                assert rel(host(s.vel), v) < 1e-9
+                assert periodic_rel(host(s.pos), x, p.L) < 1e-9
+        else:
+            # the sort permutes particles: match them through their x velocity, whose
+            # gaps (~1e-8) are far above the accumulated rounding (~1e-13)
+            for s, x, v in zip(sim.species, ref["x"], ref["v"]):
+                ka = np.argsort(host(s.vel)[0])
+                kb = np.argsort(v[0])
+                assert rel(host(s.vel)[:, ka], v[:, kb]) < 1e-9
+                assert periodic_rel(host(s.pos)[:, ka], x[:, kb], p.L) < 1e-9
     else:
         # FP32 particle arithmetic: energy error from FP32 rounding of v, J and M
         assert drift <= 1e-6
