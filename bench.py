@@ -6,12 +6,15 @@ two species (electrons q/m = -1, ions q/m = 1/25) with 64 particles per cell
 each (33,554,432 particles), Maxwellian velocities (v_th 0.05 / 0.01),
 electron density perturbed by 1% cos(2 pi x / L_x), B0 = (0, 0, 0.2), E = 0.
 
-One step is the scheme's step: cell sort -> moment gather (J-hat, M) ->
-FP64 GMRES field solve (tol 1e-10) -> mover. The metric is particles per
-second through mover + moments (+ the sort that keeps the deposit tiled), in
-the FP32 storage form (headline) and the FP64 form; the field solve is run in
-every step and reported separately. Times are HIP events on the stream the
-kernels run on, inside a region bracketed by device synchronisation.
+One step is the scheme's step: FP64 GMRES field solve (tol 1e-10) for
+E^{n+theta}, then one fused particle pass -- mover with (E^{n+theta}, B^n) and
+the moment gather (J-hat, M) at the new positions with B^{n+1}, i.e. the next
+step's moments -- with a cell re-sort every --sort-every steps. The metric is
+particles per second through mover + moments (the fused pass plus the
+amortised re-sort), in the FP32 storage form (headline) and the FP64 form;
+the field solve runs in every step and is reported separately. Times are HIP
+events on the stream the kernels run on, inside a region bracketed by device
+synchronisation.
 
 Prints one JSON line.
 """
@@ -38,56 +41,53 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8, help="oracle runs on 1/cpu-sample of the particles")
+    ap.add_argument("--sort-every", type=int, default=4)
     return ap.parse_args()
 
 
 def algorithmic_bytes(prec, nparticles, nn):
-    """Bytes the method must move per step through sort + moments + mover.
+    """Bytes the fused mover + moments pass must move per step.
 
-    Per particle: the state (positions + velocities [+ cell]) read and written
-    once by the mover and read once by the deposit; per node: E^{n+theta} and
-    B^n read by the mover, B read by the deposit, J-hat and the 14 x 9 mass
-    matrix entries written once.
+    Per particle: the state (positions + velocities [+ cell]) read once and
+    written once; per node: E^{n+theta}, B^n and B^{n+1} read, J-hat and the
+    14 x 9 mass-matrix entries written once.
     """
-    if prec == "f32":
-        part = 28          # 3 offsets + cell + 3 velocities
-        fld = 4
-    else:
-        part = 48          # 3 positions + 3 velocities
-        fld = 8
-    per_particle = part * 3                # deposit read, mover read + write
-    per_node = fld * (3 + 3 + 3 + 3 + 126)  # E, B (mover), B (deposit), J, M
-    deposit = part * nparticles + fld * (3 + 3 + 126) * nn
-    return per_particle * nparticles + per_node * nn, deposit
+    part, fld = (28, 4) if prec == "f32" else (48, 8)
+    return 2 * part * nparticles + fld * (9 + 3 + 126) * nn
 
 
 def run_form(prec, args, plasma):
     import torch
     from paper_2603_16624_amd import ecsim as E
     P = E.F32 if prec == "f32" else E.F64
-    sim = E.Simulation(plasma, prec=P, tol=1e-10, sort=True)
+    sim = E.Simulation(plasma, prec=P, tol=1e-10, fused=True, sort_every=args.sort_every)
+    sim.prime()
     st = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
     def one_step(record):
-        e = [ev() for _ in range(8)]
+        e = [ev() for _ in range(6)]
         e[0].record(st)
-        sim.sort_particles()
-        e[1].record(st)
-        sim.node_B()
-        e[2].record(st)
-        sim.deposit()
-        e[3].record(st)
         sim.solve()
-        e[4].record(st)
+        e[1].record(st)
         sim.scal[0] = 0.0
-        e[5].record(st)
-        sim.push(sim.scal[0:1])
-        e[6].record(st)
+        e[2].record(st)
+        sim.fused_pass(sim.scal[0:1])
+        e[3].record(st)
         sim.advance_fields()
-        e[7].record(st)
+        sim.BN, sim.BN_next = sim.BN_next, sim.BN
+        if sim.prec == E.F32:
+            sim.BN_p, sim.BN_next_p = sim.BN_next_p, sim.BN_p
+        else:
+            sim.BN_p, sim.BN_next_p = sim.BN, sim.BN_next
+        sim.nstep += 1
+        sorted_now = sim.nstep % sim.sort_every == 0
+        if sorted_now:
+            sim.sort_particles()
+        e[4].record(st)
+        e[5].record(st)
         if record is not None:
-            record.append(e)
+            record.append((e, sorted_now))
 
     for _ in range(args.warmup):
         one_step(None)
@@ -98,21 +98,21 @@ def run_form(prec, args, plasma):
         one_step(rec)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    sort_ms = [r[0].elapsed_time(r[1]) for r in rec]
-    mom_ms = [r[2].elapsed_time(r[3]) for r in rec]
-    solve_ms = [r[3].elapsed_time(r[4]) for r in rec]
-    move_ms = [r[5].elapsed_time(r[6]) for r in rec]
-    full_ms = [r[0].elapsed_time(r[7]) for r in rec]
     mean = lambda a: sum(a) / len(a)
-    pass_ms = mean(sort_ms) + mean(mom_ms) + mean(move_ms)
+    solve_ms = mean([e[0].elapsed_time(e[1]) for e, _ in rec])
+    fused_ms = mean([e[2].elapsed_time(e[3]) for e, _ in rec])
+    resort = [e[3].elapsed_time(e[4]) for e, s_ in rec if s_]
+    sort_ms = mean(resort) if resort else 0.0
+    full_ms = mean([e[0].elapsed_time(e[5]) for e, _ in rec])
+    pass_ms = fused_ms + sort_ms / args.sort_every
     npart = plasma.n_particles
-    total_bytes, dep_bytes = algorithmic_bytes(prec, npart, plasma.nn)
-    return dict(prec=prec, particles=npart, pass_ms=pass_ms, sort_ms=mean(sort_ms), moments_ms=mean(mom_ms),
-                move_ms=mean(move_ms), solve_ms=mean(solve_ms), full_step_ms=mean(full_ms), wall_s=wall,
+    nbytes = algorithmic_bytes(prec, npart, plasma.nn)
+    return dict(prec=prec, particles=npart, pass_ms=pass_ms, fused_ms=fused_ms, sort_ms=sort_ms,
+                sort_every=args.sort_every, solve_ms=solve_ms, full_step_ms=full_ms, wall_s=wall,
                 gmres_iters=sim.last_iters, gmres_resid=sim.last_resid,
-                particles_per_s=npart / (pass_ms * 1e-3), bytes_per_step=total_bytes,
-                hbm_frac_pass=total_bytes / (pass_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
-                deposit_bytes=dep_bytes, deposit_gbs=dep_bytes / (mean(mom_ms) * 1e-3) / 1e9)
+                particles_per_s=npart / (pass_ms * 1e-3), bytes_per_step=nbytes,
+                hbm_frac_pass=nbytes / (pass_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                fused_gbs=nbytes / (fused_ms * 1e-3) / 1e9)
 
 
 def cpu_baseline(plasma, sample):
@@ -170,7 +170,7 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(plasma, args.cpu_sample)
         print(f"[bench] cpu: {json.dumps(cpu)}", file=sys.stderr, flush=True)
-    achieved = r32["deposit_gbs"]
+    achieved = r32["fused_gbs"]
     out = {
         "metric": "particles/s through mover+moments (FP32 vs FP64) at fixed error; % HBM peak",
         "value": r32["particles_per_s"],
@@ -184,17 +184,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{plasma.name}; FP32 offset+cell storage, FP32 mover and deposit, "
-                               f"FP64 GMRES (tol 1e-10)",
+        "config": {"workload": f"{plasma.name}; FP32 offset+cell storage, FP32 mover and deposit "
+                               f"(Kahan-combined MFMA block sums), FP64 GMRES (tol 1e-10), "
+                               f"re-sort every {args.sort_every} steps",
                    "cells": list(plasma.n), "particles": plasma.n_particles, "ppc_per_species": args.ppc,
                    "parallelism": "single GPU"},
         "hbm_frac": r32["hbm_frac_pass"],
-        "breakdown_ms": {k: r32[k] for k in ("sort_ms", "moments_ms", "move_ms", "solve_ms", "full_step_ms")},
+        "breakdown_ms": {k: r32[k] for k in ("fused_ms", "sort_ms", "solve_ms", "full_step_ms")},
+        "sort_every": args.sort_every,
         "gmres": {"iters_last": r32["gmres_iters"], "rel_resid_last": r32["gmres_resid"]},
         "fp64": None if r64 is None else {
             "value": r64["particles_per_s"], "ms_per_step": r64["pass_ms"], "hbm_frac": r64["hbm_frac_pass"],
-            "breakdown_ms": {k: r64[k] for k in ("sort_ms", "moments_ms", "move_ms", "solve_ms", "full_step_ms")}},
-        "roofline": {"kernel": "ecsim_moments (FP32)", "bound": "hbm", "achieved": achieved,
+            "breakdown_ms": {k: r64[k] for k in ("fused_ms", "sort_ms", "solve_ms", "full_step_ms")}},
+        "roofline": {"kernel": "ecsim_move_moments (FP32): fused mover + moment gather", "bound": "hbm",
+                     "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,
     }

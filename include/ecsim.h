@@ -90,8 +90,9 @@ const char *ecsim_last_error(void);
 /* Library version string (host). */
 const char *ecsim_version(void);
 
-/* Bytes of device workspace that ecsim_sort / ecsim_moments need for `np`
- * particles of precision `prec` on this grid (host, synchronous). */
+/* Bytes of device workspace that ecsim_sort, ecsim_moments (with
+ * ECSIM_SORTED) and ecsim_move_moments need for `np` particles in total (all
+ * species of one call) of precision `prec` on this grid (host, synchronous). */
 ecsim_status ecsim_workspace_size(const ecsim_grid *grid, int64_t np, int32_t prec,
                                   uint32_t flags, size_t *bytes /* host out */);
 
@@ -119,14 +120,33 @@ ecsim_status ecsim_move(const ecsim_grid *grid, const ecsim_particles *sp,
  * with alpha_p built from B_node (= B^n, [3][Nn]) gathered at x_p.
  * All species must share one precision; J, M and B_node are in it.
  * J and M are overwritten unless ECSIM_ACCUMULATE is set. With ECSIM_SORTED
- * every species must carry cell_start and the tiled, LDS-binned deposit is
- * used; otherwise a per-particle atomic deposit handles any order.
- * ws/ws_bytes: device workspace of at least ecsim_workspace_size() bytes
- * (may be NULL/0 when that size is 0).
+ * every species must carry cell_start (particles grouped by cell ranges) and
+ * the tiled deposit is used; a particle that is not in its range's cell is
+ * still deposited correctly, through a slower stray path. Without
+ * ECSIM_SORTED a per-particle atomic deposit handles any order.
+ * ws/ws_bytes: with ECSIM_SORTED, device workspace of at least
+ * ecsim_workspace_size() bytes for the total particle count; else unused.
  */
 ecsim_status ecsim_moments(const ecsim_grid *grid, const ecsim_particles *species,
                            int32_t nspecies, const void *B_node, void *J, void *M,
                            void *ws, size_t ws_bytes, uint32_t flags, void *stream);
+
+/*
+ * Fused particle pass of one step: every species is moved as by ecsim_move
+ * (E_node = E^{n+theta}, B_node = B^n, Eqs. 4, 5, 8), then the moments of
+ * Eqs. 1 and 3 at the new positions with B_next = B^{n+1} (the next step's
+ * moment gather) are deposited into J and M, summed over species, as by
+ * ecsim_moments with ECSIM_SORTED. Every species must carry cell_start; the
+ * grouping may be stale (particles out of their range's cell take a slower
+ * path), so a re-sort every few steps keeps the pass fast. Particles keep
+ * their array positions. ke_out (nullable, device double) += the kinetic
+ * energy of v^{n+1}. At most 4 species of fewer than 2^28 particles each.
+ * ws: device workspace of ecsim_workspace_size() bytes for the total count.
+ */
+ecsim_status ecsim_move_moments(const ecsim_grid *grid, const ecsim_particles *species,
+                                int32_t nspecies, const void *E_node, const void *B_node,
+                                const void *B_next, void *J, void *M, double *ke_out,
+                                void *ws, size_t ws_bytes, uint32_t flags, void *stream);
 
 /*
  * Matrix-free mass-matrix apply inside the field solve (Eq. 7):

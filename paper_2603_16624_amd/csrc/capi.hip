@@ -105,7 +105,8 @@ ecsim_status ecsim_workspace_size(const ecsim_grid* grid, int64_t np, int32_t pr
   if (check_prec(prec) != ECSIM_OK) return ECSIM_EINVAL;
   if (!bytes) return fail(ECSIM_EINVAL, "bytes is NULL");
   if (np < 0 || np >= ((int64_t)1 << 31)) return fail(ECSIM_EINVAL, "np out of range");
-  *bytes = sort_workspace_bytes(g, np);
+  const size_t a = sort_workspace_bytes(g, np), b = tiled_workspace_bytes(g, np);
+  *bytes = a > b ? a : b;
   return ECSIM_OK;
 }
 
@@ -121,38 +122,85 @@ ecsim_status ecsim_move(const ecsim_grid* grid, const ecsim_particles* sp, const
   return ECSIM_OK;
 }
 
+namespace {
+
+ecsim_status species_list(const ecsim_grid* grid, const ecsim_particles* species, int32_t nspecies, Grid& g,
+                          SpeciesArgs* a, const char* who, uint32_t flags, bool need_sorted) {
+  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
+  if (nspecies < 1 || nspecies > kMaxSpecies)
+    return fail(ECSIM_EINVAL, "%s: nspecies = %d not in 1..%d", who, nspecies, kMaxSpecies);
+  if (!species) return fail(ECSIM_EINVAL, "%s: species is NULL", who);
+  const int32_t prec = species[0].prec;
+  for (int s = 0; s < nspecies; ++s) {
+    if (make_species(&species[s], a[s], who) != ECSIM_OK) return ECSIM_EINVAL;
+    if (species[s].prec != prec) return fail(ECSIM_EINVAL, "%s: species have mixed precisions", who);
+    if ((need_sorted || (flags & ECSIM_SORTED)) && !species[s].cell_start)
+      return fail(ECSIM_EINVAL, "%s: cell_start is required for every species", who);
+  }
+  return ECSIM_OK;
+}
+
+}  // namespace
+
 ecsim_status ecsim_moments(const ecsim_grid* grid, const ecsim_particles* species, int32_t nspecies,
                            const void* B_node, void* J, void* M, void* ws, size_t ws_bytes, uint32_t flags,
                            void* stream) {
-  (void)ws;
-  (void)ws_bytes;
   Grid g;
-  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
-  if (nspecies < 1 || nspecies > kMaxSpecies) return fail(ECSIM_EINVAL, "ecsim_moments: nspecies = %d not in 1..%d", nspecies, kMaxSpecies);
-  if (!species) return fail(ECSIM_EINVAL, "ecsim_moments: species is NULL");
-  if (!B_node || !J || !M) return fail(ECSIM_EINVAL, "ecsim_moments: B_node, J and M are required");
-  if (flags & ~(uint32_t)(ECSIM_ACCUMULATE | ECSIM_SORTED)) return fail(ECSIM_EINVAL, "ecsim_moments: unknown flags 0x%x", flags);
   SpeciesArgs a[kMaxSpecies];
-  const int32_t prec = species[0].prec;
-  for (int s = 0; s < nspecies; ++s) {
-    if (make_species(&species[s], a[s], "ecsim_moments") != ECSIM_OK) return ECSIM_EINVAL;
-    if (species[s].prec != prec) return fail(ECSIM_EINVAL, "ecsim_moments: species have mixed precisions");
-    if ((flags & ECSIM_SORTED) && !species[s].cell_start)
-      return fail(ECSIM_EINVAL, "ecsim_moments: ECSIM_SORTED needs cell_start for every species");
-  }
-  const bool f32 = prec == ECSIM_F32;
+  if (flags & ~(uint32_t)(ECSIM_ACCUMULATE | ECSIM_SORTED)) return fail(ECSIM_EINVAL, "ecsim_moments: unknown flags 0x%x", flags);
+  if (species_list(grid, species, nspecies, g, a, "ecsim_moments", flags, false) != ECSIM_OK) return ECSIM_EINVAL;
+  if (!B_node || !J || !M) return fail(ECSIM_EINVAL, "ecsim_moments: B_node, J and M are required");
+  const bool f32 = species[0].prec == ECSIM_F32;
   const size_t esz = f32 ? 4 : 8;
+  const bool tiled = (flags & ECSIM_SORTED) && tiled_species_ok(a, nspecies);
+  int64_t np_total = 0;
+  for (int s = 0; s < nspecies; ++s) np_total += a[s].np;
+  if (tiled) {
+    const size_t need = tiled_workspace_bytes(g, np_total);
+    if (!ws || ws_bytes < need)
+      return fail(ECSIM_EWORKSPACE, "ecsim_moments: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
+  }
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   if (!(flags & ECSIM_ACCUMULATE)) {
     if ((e = launch_zero(J, esz * 3 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_moments zero J");
     if ((e = launch_zero(M, esz * 126 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_moments zero M");
   }
-  if ((flags & ECSIM_SORTED) && tiled_supported(g))
-    e = launch_deposit_tiled(g, f32, a, nspecies, B_node, J, M, st);
+  if (tiled)
+    e = launch_deposit_tiled(g, f32, a, nspecies, B_node, J, M, ws, st);
   else
     e = launch_deposit_atomic(g, f32, a, nspecies, B_node, J, M, st);
   if (e != hipSuccess) return hip_fail(e, "ecsim_moments");
+  return ECSIM_OK;
+}
+
+ecsim_status ecsim_move_moments(const ecsim_grid* grid, const ecsim_particles* species, int32_t nspecies,
+                                const void* E_node, const void* B_node, const void* B_next, void* J, void* M,
+                                double* ke_out, void* ws, size_t ws_bytes, uint32_t flags, void* stream) {
+  Grid g;
+  SpeciesArgs a[kMaxSpecies];
+  if (flags & ~(uint32_t)(ECSIM_ACCUMULATE | ECSIM_SORTED))
+    return fail(ECSIM_EINVAL, "ecsim_move_moments: unknown flags 0x%x", flags);
+  if (species_list(grid, species, nspecies, g, a, "ecsim_move_moments", flags, true) != ECSIM_OK) return ECSIM_EINVAL;
+  if (!E_node || !B_node || !B_next || !J || !M)
+    return fail(ECSIM_EINVAL, "ecsim_move_moments: E_node, B_node, B_next, J and M are required");
+  if (!tiled_species_ok(a, nspecies))
+    return fail(ECSIM_EINVAL, "ecsim_move_moments: at most 4 species of fewer than 2^28 particles each");
+  int64_t np_total = 0;
+  for (int s = 0; s < nspecies; ++s) np_total += a[s].np;
+  const size_t need = tiled_workspace_bytes(g, np_total);
+  if (!ws || ws_bytes < need)
+    return fail(ECSIM_EWORKSPACE, "ecsim_move_moments: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
+  const bool f32 = species[0].prec == ECSIM_F32;
+  const size_t esz = f32 ? 4 : 8;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (!(flags & ECSIM_ACCUMULATE)) {
+    if ((e = launch_zero(J, esz * 3 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_move_moments zero J");
+    if ((e = launch_zero(M, esz * 126 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_move_moments zero M");
+  }
+  e = launch_move_deposit(g, f32, a, nspecies, E_node, B_node, B_next, J, M, ke_out, ws, st);
+  if (e != hipSuccess) return hip_fail(e, "ecsim_move_moments");
   return ECSIM_OK;
 }
 

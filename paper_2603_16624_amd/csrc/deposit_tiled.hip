@@ -1,4 +1,5 @@
-// Tiled, LDS-binned moment deposit (Eqs. 1 and 3) over cell-sorted particles.
+// Tiled moment deposit (Eqs. 1 and 3) over cell-grouped particles, alone or
+// fused with the mover (Eqs. 4, 5, 8).
 //
 // Per cell the deposit is a small dense contraction. For corner pair (a, b)
 // the weight product W_a W_b depends only on the class c = a + b in {0,1,2}^3
@@ -11,17 +12,24 @@
 // at corner a is J_a = sum_b S[a+b][9..11].
 //
 // Structure. A workgroup owns a brick of TX x TY x TZ cells. Each wavefront
-// takes two cells at a time:
-//   1. particle lanes (lanes 0-31: cell A, 32-63: cell B) recompute the
-//      weights and alpha_p exactly as the mover does and write one record per
-//      particle to LDS: the 12 values and the 9 per-dimension weight factors;
+// takes two cells at a time (lanes 0-31: cell A, 32-63: cell B):
+//   1. particle lanes take one particle each -- in the fused form they first
+//      move it (E^{n+theta}, B^n at its old position) and write it back -- and
+//      write a record to LDS: the 12 values and the 27 class weights, computed
+//      with the same routines as the mover so alpha_p and W_pN agree bit for
+//      bit;
 //   2. the contraction runs on the matrix cores: v_mfma 16x16x4 with rows =
 //      the 12 values (padded to 16), columns = the 27 classes (two tiles of 16)
 //      and K = 4 particles per instruction; FP32 sums are formed in blocks of
 //      32 particles and the blocks combined with Kahan compensation;
-//   3. the per-cell sums go to LDS (one writer per entry, no atomics);
+//   3. per-cell sums go to LDS (one writer per entry, no atomics);
 // then, after a workgroup barrier, every (node, entry) of the brick gathers
 // its <= 8 cell contributions and is added to the global J and M once.
+//
+// Particles are grouped by cell ranges (cell_start) that may be stale: a
+// particle whose cell (after the move, in the fused form) is not its range's
+// cell is appended to a stray list. The strays are then counting-sorted by
+// cell and deposited by the same kernel reading them through the list.
 #include "internal.h"
 
 namespace ecsim {
@@ -29,7 +37,10 @@ namespace ecsim {
 namespace {
 
 constexpr int kMaxTiledSpecies = 4;
-constexpr int SCS = 268;        // per-cell sums: [27][9] mass-matrix classes, [8][3] corner currents, pad
+constexpr int kItemShift = 28;              // stray item = species << 28 | particle index
+constexpr int SCS = 268;                    // per-cell sums: [27][9] mass-matrix classes, [8][3] currents, pad
+
+enum Mode { kDeposit = 0, kMoveDeposit = 1, kIndirect = 2 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -53,13 +64,15 @@ template <> struct Mfma<double> {
 
 template <typename T>
 struct TSpecies {
-  const T* pos[3];
-  const T* vel[3];
+  T* pos[3];
+  T* vel[3];
+  int32_t* cell;
   const T* q;
   T q_const;
   T beta;
   T beta_V;      // beta / V
   T inv_V;       // 1 / V
+  double inv_qom;
   const int32_t* cell_start;
 };
 
@@ -67,6 +80,16 @@ template <typename T>
 struct TArgs {
   TSpecies<T> s[kMaxTiledSpecies];
   int ns;
+  const T* Bdep;       // magnetic field of the deposit
+  const T* Emove;      // mover fields (fused form)
+  const T* Bmove;
+  T dth[3];            // dt / h
+  int* stray_count;
+  int* stray_item;
+  int* stray_cell;
+  const int* ind_start;   // indirect pass: sorted stray list
+  const int* ind_item;
+  double* ke;
 };
 
 // Kahan compensated summation: the true running sum is s - c.
@@ -87,23 +110,31 @@ __device__ __forceinline__ void wave_sync() {
 template <typename T>
 struct PData {       // one particle's inputs, loaded ahead of use
   T x0, x1, x2, v0, v1, v2, q;
-  int s;
+  int c;             // stored cell (FP32 form)
+  int s, p;
   bool ok;
 };
 
-template <typename T>
-__device__ __forceinline__ PData<T> load_particle(const TArgs<T>& args, const int* cnt, const int* beg, int total,
-                                                  int ip) {
+template <typename T, int MODE>
+__device__ __forceinline__ PData<T> load_particle(const TArgs<T>& args, const TSpecies<T>* lsp, const int* cnt,
+                                                  const int* beg, int total, int ip) {
   PData<T> d{};
   d.ok = ip < total;
   if (d.ok) {
-    int s = 0, idx = ip;
+    int s = 0, idx = ip, p;
+    if constexpr (MODE == kIndirect) {
+      const int item = args.ind_item[beg[0] + ip];
+      s = item >> kItemShift;
+      p = item & ((1 << kItemShift) - 1);
+    } else {
 #pragma unroll
-    for (int k = 0; k < kMaxTiledSpecies - 1; ++k)
-      if (s == k && idx >= cnt[k]) { idx -= cnt[k]; s = k + 1; }
-    const TSpecies<T>& sp = args.s[s];
-    const int p = beg[s] + idx;
+      for (int k = 0; k < kMaxTiledSpecies - 1; ++k)
+        if (s == k && idx >= cnt[k]) { idx -= cnt[k]; s = k + 1; }
+      p = beg[s] + idx;
+    }
+    const TSpecies<T>& sp = lsp[s];   // LDS copy: a lane-dependent species costs no memory round trip
     d.s = s;
+    d.p = p;
     d.x0 = sp.pos[0][p];
     d.x1 = sp.pos[1][p];
     d.x2 = sp.pos[2][p];
@@ -111,8 +142,34 @@ __device__ __forceinline__ PData<T> load_particle(const TArgs<T>& args, const in
     d.v1 = sp.vel[1][p];
     d.v2 = sp.vel[2][p];
     d.q = sp.q ? sp.q[p] : sp.q_const;
+    if constexpr (sizeof(T) == 4) d.c = sp.cell[p];
   }
   return d;
+}
+
+template <typename T>
+__device__ __forceinline__ Stencil<T> particle_stencil(const Grid& g, T x0, T x1, T x2, int c);
+template <>
+__device__ __forceinline__ Stencil<float> particle_stencil<float>(const Grid& g, float x0, float x1, float x2, int c) {
+  return stencil_cell(g, c, x0, x1, x2);
+}
+template <>
+__device__ __forceinline__ Stencil<double> particle_stencil<double>(const Grid& g, double x0, double x1, double x2,
+                                                                   int) {
+  return stencil_abs(g, x0, x1, x2);
+}
+
+// F_p = sum_a W_a F_a over staged corner values [3][8], in the order of gather().
+template <typename T>
+__device__ __forceinline__ Vec3<T> gather_staged(const T W[8], const T* F) {
+  Vec3<T> r{T(0), T(0), T(0)};
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    r.x = fma(W[a], F[a], r.x);
+    r.y = fma(W[a], F[8 + a], r.y);
+    r.z = fma(W[a], F[16 + a], r.z);
+  }
+  return r;
 }
 
 // stored block k: offset o_k (same order as the C ABI)
@@ -132,16 +189,17 @@ __host__ __device__ constexpr int pair_class(int k, int a) {
 
 // Records in LDS are stored transposed, rec[row][slot] with a row stride of
 // 66 slots (64 particles + 2): the MFMA operand reads of 16 lanes with
-// consecutive rows and 2 lane groups then hit 32 different banks.
+// consecutive rows and 2 lane groups then hit 32 different banks. Rows 39-43
+// are not read as used operands; they stage the cells' corner fields
+// (during phase 1) and the current class sums (during phase 3).
 constexpr int kSlots = 66;
-constexpr int kRows = 44;       // 12 values, 27 class weights, 5 spare rows
-constexpr int kRowB = 39;       // spare row: corner magnetic field of the two cells
-constexpr int kRowT = 40;       // spare rows 40..42: current class sums of the two cells
+constexpr int kRows = 44;
+constexpr int kStage = 39 * kSlots;        // [2 cells][72]: deposit B, mover E, mover B (24 each)
+constexpr int kTcur = 39 * kSlots;         // [2 cells][84]: current class sums (phase 3 only)
 
-template <typename T, int TX, int TY, int TZ, int NW>
-__global__ void __launch_bounds__(NW * 64) k_deposit_tiled(Grid g, TArgs<T> args, int ntx, int nty, int ntz,
-                                                          const T* __restrict__ B, T* __restrict__ J,
-                                                          T* __restrict__ M) {
+template <typename T, int TX, int TY, int TZ, int NW, int MODE>
+__global__ void __launch_bounds__(NW * 64) k_tiled(Grid g, TArgs<T> args, int ntx, int nty, int ntz,
+                                                   T* __restrict__ J, T* __restrict__ M) {
   using MF = Mfma<T>;
   using acc_t = typename MF::acc;
   constexpr int NX = TX + 1, NY = TY + 1, NZ = TZ + 1, NN = NX * NY * NZ;
@@ -151,6 +209,8 @@ __global__ void __launch_bounds__(NW * 64) k_deposit_tiled(Grid g, TArgs<T> args
   // one LDS block: the wavefront records first (so that their offsets fit the
   // 16-bit immediate of ds_read), then the per-cell sums
   __shared__ __attribute__((aligned(16))) T smem[NW * WREC + NCELL * SCS];
+  __shared__ double red[NW];
+  __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
   T* const scell = smem + NW * WREC;
 
   const int tid = threadIdx.x;
@@ -172,13 +232,28 @@ __global__ void __launch_bounds__(NW * 64) k_deposit_tiled(Grid g, TArgs<T> args
   const int tx = b % ntx, ty = (b / ntx) % nty, tz = b / (ntx * nty);
   const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
 
+  if constexpr (MODE == kIndirect) {
+    // most bricks hold no stray: leave at once
+    int any = 0;
+    for (int lc = tid; lc < NCELL; lc += NW * 64) {
+      const int cx = x0 + lc % TX, cy = y0 + (lc / TX) % TY, cz = z0 + lc / (TX * TY);
+      if (cx < g.nx && cy < g.ny && cz < g.nz) {
+        const int64_t c = cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz);
+        any |= args.ind_start[c + 1] > args.ind_start[c];
+      }
+    }
+    if (!__syncthreads_or(any)) return;
+  }
+
   for (int i = tid; i < NCELL * SCS; i += NW * 64) scell[i] = T(0);
   for (int i = tid; i < NW * WREC; i += NW * 64) smem[i] = T(0);
+  if (tid < kMaxTiledSpecies) lsp[tid] = args.s[tid < args.ns ? tid : 0];
   __syncthreads();
 
   T* const wrec = smem + wave * WREC;
   // this lane's MFMA operand base: row col, slot grp (cell A) / 32 + grp (cell B)
   const T* const opnd = wrec + col * kSlots + grp;
+  double kel = 0.0;
 
   for (int pair = wave; pair < NPAIR; pair += NW) {
     // my half's cell
@@ -186,7 +261,7 @@ __global__ void __launch_bounds__(NW * 64) k_deposit_tiled(Grid g, TArgs<T> args
     const int lx = lc % TX, ly = (lc / TX) % TY, lz = lc / (TX * TY);
     const int cx = x0 + lx, cy = y0 + ly, cz = z0 + lz;
     const bool valid = (lc < NCELL) && cx < g.nx && cy < g.ny && cz < g.nz;
-    const int64_t cell = valid ? cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz) : 0;
+    const int cell = valid ? cx + g.nx * (cy + g.ny * cz) : -1;
     int cnt[kMaxTiledSpecies];
     int beg[kMaxTiledSpecies];
     int total = 0;
@@ -194,16 +269,36 @@ __global__ void __launch_bounds__(NW * 64) k_deposit_tiled(Grid g, TArgs<T> args
     for (int s = 0; s < kMaxTiledSpecies; ++s) {
       cnt[s] = 0;
       beg[s] = 0;
-      if (s < args.ns && valid) {
-        beg[s] = args.s[s].cell_start[cell];
-        cnt[s] = args.s[s].cell_start[cell + 1] - beg[s];
-      }
-      total += cnt[s];
     }
+    {
+      // all range loads are issued before any is used
+      const int cl = valid ? cell : 0;
+      if constexpr (MODE == kIndirect) {
+        const int b0 = args.ind_start[cl], b1 = args.ind_start[cl + 1];
+        beg[0] = b0;
+        cnt[0] = valid ? b1 - b0 : 0;
+      } else {
+        int lo[kMaxTiledSpecies], hi[kMaxTiledSpecies];
+#pragma unroll
+        for (int s = 0; s < kMaxTiledSpecies; ++s) {
+          const int32_t* cs = lsp[s].cell_start;   // unused species alias species 0
+          lo[s] = cs[cl];
+          hi[s] = cs[cl + 1];
+        }
+#pragma unroll
+        for (int s = 0; s < kMaxTiledSpecies; ++s) {
+          beg[s] = lo[s];
+          cnt[s] = (valid && s < args.ns) ? hi[s] - lo[s] : 0;
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kMaxTiledSpecies; ++s) total += cnt[s];
     const int cntA = __builtin_amdgcn_readfirstlane(__shfl(total, 0));
     const int cntB = __builtin_amdgcn_readfirstlane(__shfl(total, 32));
     const int cmax = cntA > cntB ? cntA : cntB;
-    // corner nodes of the cell; lanes 0..23 of each half fetch the magnetic field
+    if (cmax == 0) continue;   // wave-uniform: both cells empty
+    // corner nodes of the cell; lanes of each half stage the corner fields
     Stencil<T> st{};
     st.i[0] = valid ? cx : 0;
     st.i[1] = valid ? cy : 0;
@@ -211,13 +306,17 @@ __global__ void __launch_bounds__(NW * 64) k_deposit_tiled(Grid g, TArgs<T> args
     st.ip[0] = wrap_up(st.i[0], g.nx);
     st.ip[1] = wrap_up(st.i[1], g.ny);
     st.ip[2] = wrap_up(st.i[2], g.nz);
-    T* const myB = wrec + kRowB * kSlots + 24 * half;
-    if (hl < 24) myB[hl] = B[(hl >> 3) * g.nn + corner_node(g, st, hl & 7)];
-    PData<T> pd = load_particle(args, cnt, beg, total, hl);
+    T* const stage = wrec + kStage + 72 * half;
+    if (hl < 24) {
+      const int64_t nd = (hl >> 3) * g.nn + corner_node(g, st, hl & 7);
+      stage[hl] = args.Bdep[nd];
+      if constexpr (MODE == kMoveDeposit) {
+        stage[24 + hl] = args.Emove[nd];
+        stage[48 + hl] = args.Bmove[nd];
+      }
+    }
+    PData<T> pd = load_particle<T, MODE>(args, lsp, cnt, beg, total, hl);
     wave_sync();
-    T Bn[3][8];
-#pragma unroll
-    for (int i = 0; i < 24; ++i) Bn[i >> 3][i & 7] = myB[i];
 
     // running sums of the two cells: [cell][tile][reg]
     T S[2][2][4], C[2][2][4];
@@ -229,57 +328,135 @@ __global__ void __launch_bounds__(NW * 64) k_deposit_tiled(Grid g, TArgs<T> args
         for (int r = 0; r < 4; ++r) { S[h][t][r] = T(0); C[h][t][r] = T(0); }
 
     for (int ch = 0; ch < cmax; ch += 32) {
-      // ---- 1. particle lanes: one record column per lane ----
+      // ---- 1. particle lanes: (move and) one record column per lane ----
       T r[39];
 #pragma unroll
       for (int i = 0; i < 39; ++i) r[i] = T(0);
+      bool stray = false;
+      int new_cell = 0;
+      // moved state, written back after the next block's loads are issued
+      T mv0 = T(0), mv1 = T(0), mv2 = T(0), mx0 = T(0), mx1 = T(0), mx2 = T(0);
+      int mcell = 0;
+      const bool moved = (MODE == kMoveDeposit) && pd.ok;
+      const int ms = pd.s, mp = pd.p;
       if (pd.ok) {
-        const TSpecies<T>& sp = args.s[pd.s];
-        Stencil<T> ps = st;
-        if constexpr (sizeof(T) == 4) {
-          ps.w1[0] = pd.x0; ps.w1[1] = pd.x1; ps.w1[2] = pd.x2;
-          ps.w0[0] = T(1) - pd.x0; ps.w0[1] = T(1) - pd.x1; ps.w0[2] = T(1) - pd.x2;
+        const TSpecies<T>& sp = lsp[pd.s];
+        Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
+        int pcell = ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]);
+        Vec3<T> v{pd.v0, pd.v1, pd.v2};
+        if constexpr (MODE == kMoveDeposit) {
+          T W[8];
+          int64_t nd[8];
+          Vec3<T> Ep, Bp;
+          if (pcell == cell) {
+#pragma unroll
+            for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
+            Ep = gather_staged(W, stage + 24);
+            Bp = gather_staged(W, stage + 48);
+          } else {
+            corners(g, ps, W, nd);
+            Ep = gather(args.Emove, g.nn, W, nd);
+            Bp = gather(args.Bmove, g.nn, W, nd);
+          }
+          T a0[9];
+          rotation(Bp, sp.beta, a0);
+          Vec3<T> u;
+          v = velocity_update(a0, v, Ep, sp.beta, u);
+          mv0 = v.x;
+          mv1 = v.y;
+          mv2 = v.z;
+          if constexpr (sizeof(T) == 4) {
+            int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
+            const float ox = push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx);
+            const float oy = push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny);
+            const float oz = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
+            pcell = ix + g.nx * (iy + g.ny * iz);
+            mx0 = ox;
+            mx1 = oy;
+            mx2 = oz;
+            mcell = pcell;
+            ps.i[0] = ix; ps.i[1] = iy; ps.i[2] = iz;
+            ps.ip[0] = wrap_up(ix, g.nx); ps.ip[1] = wrap_up(iy, g.ny); ps.ip[2] = wrap_up(iz, g.nz);
+            ps.w1[0] = ox; ps.w1[1] = oy; ps.w1[2] = oz;
+            ps.w0[0] = 1.0f - ox; ps.w0[1] = 1.0f - oy; ps.w0[2] = 1.0f - oz;
+          } else {
+            const double nx0 = push_abs(pd.x0, g.dt, v.x, g.nx * g.hx);
+            const double nx1 = push_abs(pd.x1, g.dt, v.y, g.ny * g.hy);
+            const double nx2 = push_abs(pd.x2, g.dt, v.z, g.nz * g.hz);
+            mx0 = nx0;
+            mx1 = nx1;
+            mx2 = nx2;
+            ps = stencil_abs(g, nx0, nx1, nx2);
+            pcell = ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]);
+          }
+          if (args.ke) {
+            const double vx = v.x, vy = v.y, vz = v.z;
+            kel += 0.5 * ((double)pd.q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz);
+          }
+        }
+        if (pcell != cell) {
+          stray = true;
+          new_cell = pcell;
         } else {
-          // the cell of a sorted particle is its range's cell
-          Stencil<double> s2 = stencil_abs(g, pd.x0, pd.x1, pd.x2);
+          T W[8];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) { ps.w0[d] = s2.w0[d]; ps.w1[d] = s2.w1[d]; }
+          for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
+          const Vec3<T> B1 = gather_staged(W, stage);
+          T al[9];
+          rotation(B1, sp.beta, al);
+          const Vec3<T> vh = matvec(al, v);
+          const T cm = pd.q * sp.beta_V;
+          const T cj = pd.q * sp.inv_V;
+#pragma unroll
+          for (int i = 0; i < 9; ++i) r[i] = cm * al[i];
+          r[9] = cj * vh.x;
+          r[10] = cj * vh.y;
+          r[11] = cj * vh.z;
+          T f[3][3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            f[d][0] = ps.w0[d] * ps.w0[d];
+            f[d][1] = ps.w0[d] * ps.w1[d];
+            f[d][2] = ps.w1[d] * ps.w1[d];
+          }
+#pragma unroll
+          for (int c = 0; c < 27; ++c) r[12 + c] = (f[0][c % 3] * f[1][(c / 3) % 3]) * f[2][c / 9];
         }
-        T W[8];
-#pragma unroll
-        for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
-        Vec3<T> Bp{T(0), T(0), T(0)};
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          Bp.x = fma(W[a], Bn[0][a], Bp.x);
-          Bp.y = fma(W[a], Bn[1][a], Bp.y);
-          Bp.z = fma(W[a], Bn[2][a], Bp.z);
+      }
+      if constexpr (MODE != kIndirect) {
+        // strays: one atomic per wavefront reserves their slots in the list
+        const unsigned long long m = __ballot(stray);
+        if (m) {
+          const int leader = __ffsll((unsigned long long)m) - 1;
+          int base = 0;
+          if (lane == leader) base = atomicAdd(args.stray_count, __popcll(m));
+          base = __shfl(base, leader);
+          if (stray) {
+            const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+            args.stray_item[pos] = (pd.s << kItemShift) | pd.p;
+            args.stray_cell[pos] = new_cell;
+          }
         }
-        T al[9];
-        rotation(Bp, sp.beta, al);
-        Vec3<T> vh = matvec(al, Vec3<T>{pd.v0, pd.v1, pd.v2});
-        const T cm = pd.q * sp.beta_V;
-        const T cj = pd.q * sp.inv_V;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) r[i] = cm * al[i];
-        r[9] = cj * vh.x;
-        r[10] = cj * vh.y;
-        r[11] = cj * vh.z;
-        T f[3][3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          f[d][0] = ps.w0[d] * ps.w0[d];
-          f[d][1] = ps.w0[d] * ps.w1[d];
-          f[d][2] = ps.w1[d] * ps.w1[d];
-        }
-#pragma unroll
-        for (int c = 0; c < 27; ++c) r[12 + c] = (f[0][c % 3] * f[1][(c / 3) % 3]) * f[2][c / 9];
       }
 #pragma unroll
       for (int i = 0; i < 39; ++i) wrec[i * kSlots + lane] = r[i];
       wave_sync();
-      // prefetch the next block's particles while this block is reduced
-      if (ch + 32 < cmax) pd = load_particle(args, cnt, beg, total, ch + 32 + hl);
+      // prefetch the next block's particles while this block is reduced; the
+      // loads are issued before the write-back so that waiting for them does
+      // not wait for the stores
+      if (ch + 32 < cmax) pd = load_particle<T, MODE>(args, lsp, cnt, beg, total, ch + 32 + hl);
+      if constexpr (MODE == kMoveDeposit) {
+        if (moved) {
+          const TSpecies<T>& sp = lsp[ms];
+          sp.vel[0][mp] = mv0;
+          sp.vel[1][mp] = mv1;
+          sp.vel[2][mp] = mv2;
+          sp.pos[0][mp] = mx0;
+          sp.pos[1][mp] = mx1;
+          sp.pos[2][mp] = mx2;
+          if constexpr (sizeof(T) == 4) sp.cell[mp] = mcell;
+        }
+      }
 
       // ---- 2. matrix cores: S[value][class] += sum over 4 particles per step ----
       // records past a cell's count are zero, so all 8 steps of a block run
@@ -315,7 +492,7 @@ __global__ void __launch_bounds__(NW * 64) k_deposit_tiled(Grid g, TArgs<T> args
     }
 
     // ---- 3. per-cell sums to LDS: mass-matrix classes, current classes ----
-    T* const tcur = wrec + kRowT * kSlots;     // [2][84]
+    T* const tcur = wrec + kTcur;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int lch = 2 * pair + h;
@@ -351,7 +528,20 @@ __global__ void __launch_bounds__(NW * 64) k_deposit_tiled(Grid g, TArgs<T> args
     }
     wave_sync();
   }
+  if constexpr (MODE == kMoveDeposit) {
+    if (args.ke) {
+      for (int off = 32; off > 0; off >>= 1) kel += __shfl_down(kel, off);
+      if (lane == 0) red[wave] = kel;
+    }
+  }
   __syncthreads();
+  if constexpr (MODE == kMoveDeposit) {
+    if (args.ke && tid == 0) {
+      double s = 0.0;
+      for (int w = 0; w < NW; ++w) s += red[w];
+      unsafeAtomicAdd(args.ke, s);
+    }
+  }
 
   // ---- gather every (entry, node) of the brick and add it to J and M ----
   // items: (ij, node) for the mass matrix, then (component, node) for J
@@ -400,38 +590,165 @@ __global__ void __launch_bounds__(NW * 64) k_deposit_tiled(Grid g, TArgs<T> args
   }
 }
 
-template <typename T, int TX, int TY, int TZ, int NW>
-hipError_t launch_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* B, void* J, void* M, hipStream_t st) {
+// ---------------------------------------------------------------------------
+// stray list: rank by cell, then scatter into cell order
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_stray_rank(const int* __restrict__ count, const int* __restrict__ cellv,
+                                                    int* __restrict__ counts, int* __restrict__ ranks) {
+  const int n = *count;
+  const int lane = threadIdx.x & 63;
+  for (int base = blockIdx.x * 256; base < n; base += gridDim.x * 256) {
+    const int i = base + threadIdx.x;
+    const bool active = i < n;
+    const int key = active ? cellv[i] : -1;
+    unsigned long long pending = __ballot(active);
+    int my_rank = 0;
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const int lkey = __shfl(key, leader);
+      const unsigned long long grp = __ballot(key == lkey) & pending;
+      int b0 = 0;
+      if (lane == leader) b0 = atomicAdd(&counts[lkey], __popcll(grp));
+      b0 = __shfl(b0, leader);
+      if ((grp >> lane) & 1ull) my_rank = b0 + __popcll(grp & ((1ull << lane) - 1ull));
+      pending &= ~grp;
+    }
+    if (active) ranks[i] = my_rank;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_stray_scatter(const int* __restrict__ count, const int* __restrict__ cellv,
+                                                       const int* __restrict__ ranks, const int* __restrict__ start,
+                                                       const int* __restrict__ item, int* __restrict__ sorted) {
+  const int n = *count;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    sorted[start[cellv[i]] + ranks[i]] = item[i];
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct StrayWs {
+  int* count;
+  int* item;
+  int* cell;
+  int* rank;
+  int* sorted;
+  int* counts;
+  int* start;
+  int* scan_sums;
+};
+
+StrayWs carve(const Grid& g, int64_t cap, void* ws) {
+  char* w = (char*)ws;
+  StrayWs s;
+  s.count = (int*)w;
+  w += 256;
+  s.item = (int*)w;
+  w += align256(sizeof(int) * (size_t)cap);
+  s.cell = (int*)w;
+  w += align256(sizeof(int) * (size_t)cap);
+  s.rank = (int*)w;
+  w += align256(sizeof(int) * (size_t)cap);
+  s.sorted = (int*)w;
+  w += align256(sizeof(int) * (size_t)cap);
+  s.counts = (int*)w;
+  w += align256(sizeof(int) * (size_t)g.nn);
+  s.start = (int*)w;
+  w += align256(sizeof(int) * (size_t)(g.nn + 1));
+  s.scan_sums = (int*)w;
+  return s;
+}
+
+template <typename T>
+TArgs<T> make_args(const Grid& g, const SpeciesArgs* sp, int ns) {
   TArgs<T> a{};
   a.ns = ns;
   for (int s = 0; s < ns; ++s) {
     for (int d = 0; d < 3; ++d) {
-      a.s[s].pos[d] = (const T*)sp[s].pos[d];
-      a.s[s].vel[d] = (const T*)sp[s].vel[d];
+      a.s[s].pos[d] = (T*)sp[s].pos[d];
+      a.s[s].vel[d] = (T*)sp[s].vel[d];
     }
+    a.s[s].cell = sp[s].cell;
     a.s[s].q = (const T*)sp[s].q;
     a.s[s].q_const = (T)sp[s].q_const;
     a.s[s].beta = (T)(sp[s].qom * g.dt / 2.0);
     a.s[s].beta_V = (T)(sp[s].qom * g.dt / 2.0 / g.V);
     a.s[s].inv_V = (T)(1.0 / g.V);
+    a.s[s].inv_qom = 1.0 / sp[s].qom;
     a.s[s].cell_start = sp[s].cell_start;
   }
+  a.dth[0] = (T)(g.dt / g.hx);
+  a.dth[1] = (T)(g.dt / g.hy);
+  a.dth[2] = (T)(g.dt / g.hz);
+  return a;
+}
+
+template <typename T, int TX, int TY, int TZ, int NW>
+hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove, const void* Bmove,
+                 const void* Bdep, void* J, void* M, double* ke, bool move, void* ws, hipStream_t st) {
   const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
   const int ntiles = ntx * nty * ntz;
-  hipLaunchKernelGGL((k_deposit_tiled<T, TX, TY, TZ, NW>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty, ntz,
-                     (const T*)B, (T*)J, (T*)M);
+  int64_t cap = 0;
+  for (int s = 0; s < ns; ++s) cap += sp[s].np;
+  StrayWs w = carve(g, cap, ws);
+  hipError_t e = launch_zero(w.count, sizeof(int), st);
+  if (e != hipSuccess) return e;
+  TArgs<T> a = make_args<T>(g, sp, ns);
+  a.Bdep = (const T*)Bdep;
+  a.Emove = (const T*)Emove;
+  a.Bmove = (const T*)Bmove;
+  a.stray_count = w.count;
+  a.stray_item = w.item;
+  a.stray_cell = w.cell;
+  a.ke = ke;
+  if (move)
+    hipLaunchKernelGGL((k_tiled<T, TX, TY, TZ, NW, kMoveDeposit>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx,
+                       nty, ntz, (T*)J, (T*)M);
+  else
+    hipLaunchKernelGGL((k_tiled<T, TX, TY, TZ, NW, kDeposit>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty,
+                       ntz, (T*)J, (T*)M);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // strays: counting sort by cell, then the indirect pass
+  if ((e = launch_zero(w.counts, sizeof(int) * (size_t)g.nn, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_stray_rank, dim3(1024), dim3(256), 0, st, (const int*)w.count, (const int*)w.cell, w.counts,
+                     w.rank);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_exclusive_scan(w.counts, g.nn, w.start, w.scan_sums, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_stray_scatter, dim3(1024), dim3(256), 0, st, (const int*)w.count, (const int*)w.cell,
+                     (const int*)w.rank, (const int*)w.start, (const int*)w.item, w.sorted);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  a.ind_start = w.start;
+  a.ind_item = w.sorted;
+  hipLaunchKernelGGL((k_tiled<T, TX, TY, TZ, NW, kIndirect>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty,
+                     ntz, (T*)J, (T*)M);
   return hipGetLastError();
 }
 
 }  // namespace
 
-bool tiled_supported(const Grid& g) { return g.nn > 0; }
+size_t tiled_workspace_bytes(const Grid& g, int64_t np_total) {
+  const int64_t nscan = (g.nn + 1023) / 1024 + 1;
+  return 256 + 4 * align256(sizeof(int) * (size_t)np_total) + align256(sizeof(int) * (size_t)g.nn) +
+         align256(sizeof(int) * (size_t)(g.nn + 1)) + align256(sizeof(int) * (size_t)nscan);
+}
+
+bool tiled_species_ok(const SpeciesArgs* sp, int ns) {
+  if (ns > kMaxTiledSpecies) return false;
+  for (int s = 0; s < ns; ++s)
+    if (sp[s].np >= (1 << kItemShift)) return false;
+  return true;
+}
 
 hipError_t launch_deposit_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* B, void* J,
-                                void* M, hipStream_t st) {
-  if (ns > kMaxTiledSpecies) return launch_deposit_atomic(g, f32, sp, ns, B, J, M, st);
-  if (f32) return launch_T<float, 4, 4, 4, 8>(g, sp, ns, B, J, M, st);
-  return launch_T<double, 4, 4, 2, 4>(g, sp, ns, B, J, M, st);
+                                void* M, void* ws, hipStream_t st) {
+  if (f32) return run_T<float, 4, 4, 4, 8>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
+  return run_T<double, 4, 4, 2, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
+}
+
+hipError_t launch_move_deposit(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* E, const void* B,
+                               const void* Bnext, void* J, void* M, double* ke, void* ws, hipStream_t st) {
+  if (f32) return run_T<float, 4, 4, 4, 8>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st);
+  return run_T<double, 4, 4, 2, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st);
 }
 
 }  // namespace ecsim

@@ -29,11 +29,19 @@ hipError_t launch_move(const Grid& g, bool f32, const SpeciesArgs& sp, const voi
 hipError_t launch_deposit_atomic(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* B,
                                  void* J, void* M, hipStream_t st);
 
-// Tiled deposit over cell-sorted particles; returns hipErrorInvalidValue if
-// the grid does not admit the tiling.
+// Tiled deposit over particles grouped by cell ranges (cell_start); particles
+// outside their range's cell are handled through a stray list in `ws`.
+size_t tiled_workspace_bytes(const Grid& g, int64_t np_total);
+bool tiled_species_ok(const SpeciesArgs* sp, int ns);
 hipError_t launch_deposit_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* B,
-                                void* J, void* M, hipStream_t st);
-bool tiled_supported(const Grid& g);
+                                void* J, void* M, void* ws, hipStream_t st);
+// Fused mover + deposit: moves every species with (E, B) and deposits the
+// moments at the new positions with Bnext.
+hipError_t launch_move_deposit(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* E,
+                               const void* B, const void* Bnext, void* J, void* M, double* ke, void* ws,
+                               hipStream_t st);
+// exclusive scan of n ints into out[0..n], out[n] = total; sums: >= n/1024 + 2 ints
+hipError_t launch_exclusive_scan(const int* in, int64_t n, int* out, int* sums, hipStream_t st);
 
 size_t sort_workspace_bytes(const Grid& g, int64_t np);
 hipError_t launch_sort(const Grid& g, bool f32, const SpeciesArgs& src, const SpeciesArgs& dst,

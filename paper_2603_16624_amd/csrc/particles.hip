@@ -324,6 +324,15 @@ size_t sort_workspace_bytes(const Grid& g, int64_t np) {
          align256(sizeof(int) * (size_t)(ntiles + 1));
 }
 
+hipError_t launch_exclusive_scan(const int* in, int64_t n, int* out, int* sums, hipStream_t st) {
+  const int ntiles = (int)((n + kScanTile - 1) / kScanTile);
+  if (ntiles > kScanTile) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kScanBlock), 0, st, in, (int)n, out, sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, sums, ntiles, out + n);
+  hipLaunchKernelGGL(k_scan_add, dim3(ntiles), dim3(kScanBlock), 0, st, out, (int)n, sums);
+  return hipGetLastError();
+}
+
 hipError_t launch_sort(const Grid& g, bool f32, const SpeciesArgs& src, const SpeciesArgs& dst,
                        int32_t* cell_start, int32_t* perm, void* ws, hipStream_t st) {
   const int64_t nc = g.nn;
@@ -349,9 +358,9 @@ hipError_t launch_sort(const Grid& g, bool f32, const SpeciesArgs& src, const Sp
                          (const double*)src.pos[0], (const double*)src.pos[1], (const double*)src.pos[2],
                          (const int32_t*)nullptr, counts, keys, ranks);
   }
-  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kScanBlock), 0, st, counts, (int)nc, cell_start, sums);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, sums, ntiles, cell_start + nc);
-  hipLaunchKernelGGL(k_scan_add, dim3(ntiles), dim3(kScanBlock), 0, st, cell_start, (int)nc, sums);
+  (void)ntiles;
+  e = launch_exclusive_scan(counts, nc, cell_start, sums, st);
+  if (e != hipSuccess) return e;
   if (np > 0) {
     if (f32)
       hipLaunchKernelGGL((k_sort_scatter<float, true>), dim3(nblocks(np, kBlock)), dim3(kBlock), 0, st, np, keys,

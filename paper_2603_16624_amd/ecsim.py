@@ -59,6 +59,8 @@ def lib():
             "ecsim_workspace_size": [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, P],
             "ecsim_move": [P, P, P, P, P, P],
             "ecsim_moments": [P, P, ctypes.c_int32, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32, P],
+            "ecsim_move_moments": [P, P, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32,
+                                   P],
             "ecsim_mass_apply": [P, ctypes.c_int32, P, P, ctypes.c_double, ctypes.c_double, P, P],
             "ecsim_moments_backward": [P, P, P, P, P, P, P, P, P, P, ctypes.c_uint32, P],
             "ecsim_sort": [P, P, P, P, P, P, ctypes.c_size_t, P],
@@ -78,6 +80,7 @@ def lib():
 
 
 EXPORTED = ["ecsim_last_error", "ecsim_version", "ecsim_workspace_size", "ecsim_move", "ecsim_moments",
+            "ecsim_move_moments",
             "ecsim_mass_apply", "ecsim_moments_backward", "ecsim_sort", "ecsim_centres_to_nodes", "ecsim_to_f32",
             "ecsim_solve_workspace_size", "ecsim_field_solve", "ecsim_field_energy"]
 
@@ -217,13 +220,32 @@ def move(grid: Grid, sp: Species, E: torch.Tensor, B: torch.Tensor, ke: Optional
     _check(lib().ecsim_move(ctypes.byref(grid.c()), ctypes.byref(c), _ptr(E), _ptr(B), _ptr(ke), _stream(stream)))
 
 
+def _total(species):
+    return sum(s.np for s in species)
+
+
 def moments(grid: Grid, species: Sequence[Species], B: torch.Tensor, J: torch.Tensor, M: torch.Tensor,
             flags: int = 0, ws: Optional[torch.Tensor] = None, stream=None):
     """Moment gather (Eqs. 1, 3) summed over species into J (3, Nn) and M (14, 9, Nn)."""
     arr = (_Particles * len(species))(*[s.c() for s in species])
+    if ws is None and (flags & SORTED):
+        ws = torch.empty(workspace_size(grid, _total(species), species[0].prec), dtype=torch.uint8,
+                         device=J.device)
     nbytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(lib().ecsim_moments(ctypes.byref(grid.c()), arr, len(species), _ptr(B), _ptr(J), _ptr(M), _ptr(ws),
                                nbytes, int(flags), _stream(stream)))
+
+
+def move_moments(grid: Grid, species: Sequence[Species], E: torch.Tensor, B: torch.Tensor, B_next: torch.Tensor,
+                 J: torch.Tensor, M: torch.Tensor, ke: Optional[torch.Tensor] = None, flags: int = 0,
+                 ws: Optional[torch.Tensor] = None, stream=None):
+    """Fused mover (E, B) then moment gather at the new positions with B_next; species need cell_start."""
+    arr = (_Particles * len(species))(*[s.c() for s in species])
+    if ws is None:
+        ws = torch.empty(workspace_size(grid, _total(species), species[0].prec), dtype=torch.uint8,
+                         device=J.device)
+    _check(lib().ecsim_move_moments(ctypes.byref(grid.c()), arr, len(species), _ptr(E), _ptr(B), _ptr(B_next),
+                                    _ptr(J), _ptr(M), _ptr(ke), _ptr(ws), ws.numel(), int(flags), _stream(stream)))
 
 
 def mass_apply(grid: Grid, M: torch.Tensor, x: torch.Tensor, y: torch.Tensor, a: float = 1.0, b: float = 0.0,
@@ -310,13 +332,17 @@ class Simulation:
     """
 
     def __init__(self, plasma, prec: int = F64, device="cuda", tol: float = 1e-10, restart: int = 30,
-                 sort: bool = True):
+                 sort: bool = True, fused: bool = False, sort_every: int = 4):
         from . import inputs as I
         self.grid = Grid(plasma.n, plasma.h, plasma.dt)
         self.prec = prec
         self.tol = tol
         self.restart = restart
-        self.do_sort = sort
+        self.do_sort = sort or fused
+        self.fused = fused
+        self.sort_every = max(1, int(sort_every))
+        self.nstep = 0
+        self.primed = False
         self.device = device
         nn = self.grid.nn
         self.species: List[Species] = []
@@ -343,7 +369,12 @@ class Simulation:
         self._spare = [s.empty_like() for s in self.species]
         self._cell_start = [torch.empty(nn + 1, dtype=torch.int32, device=device) for _ in self.species]
         np_max = max(s.np for s in self.species)
-        self.sort_ws = torch.empty(max(workspace_size(self.grid, np_max, prec), 1), dtype=torch.uint8, device=device)
+        np_tot = sum(s.np for s in self.species)
+        self.ws = torch.empty(max(workspace_size(self.grid, max(np_tot, np_max), prec), 1), dtype=torch.uint8,
+                              device=device)
+        self.sort_ws = self.ws
+        self.BN_next = torch.empty((3, nn), dtype=torch.float64, device=device)
+        self.BN_next_p = torch.empty((3, nn), dtype=dt, device=device) if prec == F32 else self.BN_next
         self.last_iters = 0
         self.last_resid = 0.0
 
@@ -360,7 +391,7 @@ class Simulation:
 
     def deposit(self):
         flags = SORTED if (self.do_sort and all(s.cell_start is not None for s in self.species)) else 0
-        moments(self.grid, self.species, self.BN_p, self.J, self.M, flags)
+        moments(self.grid, self.species, self.BN_p, self.J, self.M, flags, ws=self.ws)
 
     def solve(self):
         it, res = field_solve(self.grid, self.M, self.J, self.E, self.BC, self.E_theta, self.E_next, self.BC_next,
@@ -381,7 +412,43 @@ class Simulation:
         self.E, self.E_next = self.E_next, self.E
         self.BC, self.BC_next = self.BC_next, self.BC
 
+    def prime(self):
+        """Fused loop: sort, then the moments of the initial state."""
+        self.sort_particles()
+        self.node_B()
+        self.deposit()
+        self.primed = True
+
+    def fused_pass(self, ke: Optional[torch.Tensor] = None):
+        """Mover with (E^{n+theta}, B^n), then the moments at x^{n+1/2} with B^{n+1}."""
+        centres_to_nodes(self.grid, self.BC_next, self.BN_next, self.BN_next_p if self.prec == F32 else None)
+        if self.prec == F32:
+            to_f32(self.E_theta, self.Et_p)
+            Et = self.Et_p
+        else:
+            Et = self.E_theta
+        move_moments(self.grid, self.species, Et, self.BN_p, self.BN_next_p, self.J, self.M, ke, ws=self.ws)
+
+    def advance_fused(self):
+        self.advance_fields()
+        self.BN, self.BN_next = self.BN_next, self.BN
+        if self.prec == F32:
+            self.BN_p, self.BN_next_p = self.BN_next_p, self.BN_p
+        else:
+            self.BN_p, self.BN_next_p = self.BN, self.BN_next
+        self.nstep += 1
+        if self.nstep % self.sort_every == 0:
+            self.sort_particles()
+
     def step(self):
+        if self.fused:
+            if not self.primed:
+                self.prime()
+            self.solve()
+            self.scal[0] = 0.0
+            self.fused_pass(self.scal[0:1])
+            self.advance_fused()
+            return
         if self.do_sort:
             self.sort_particles()
         self.node_B()

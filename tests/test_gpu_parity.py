@@ -164,12 +164,15 @@ def test_moments_f32_any_order(E, O, I, n, ppc):
     assert rel(host(M), Mo) < TOL32
 
 
-def sorted_species(E, grid, sp):
+def sorted_species(E, grid, sp, perms=None):
     out = []
     for s in sp:
         d = s.empty_like()
         cs = torch.empty(grid.nn + 1, dtype=torch.int32, device="cuda")
-        E.sort(grid, s, d, cs)
+        perm = torch.empty(max(s.np, 1), dtype=torch.int32, device="cuda")
+        E.sort(grid, s, d, cs, perm[: s.np] if s.np else None)
+        if perms is not None:
+            perms.append(host(perm)[: s.np].astype(np.int64))
         out.append(d)
     return out
 
@@ -195,6 +198,97 @@ def test_moments_sorted_tiled(E, O, I, n, ppc, prec):
     M = torch.full((14, 9, p.nn), 7.0, dtype=tdt, device="cuda")
     E.moments(grid, sp, dev(B, tdt), J, M, flags=E.SORTED)
     Jo, Mo = oracle_moments(O, p, xs, vs, qs, B)
+    assert rel(host(J), Jo) < tol
+    assert rel(host(M), Mo) < tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,ppc,vscale", [((8, 8, 8), 27, 1.0), ((6, 5, 4), 9, 40.0), ((2, 3, 2), 7, 20.0),
+                                           ((13, 7, 5), 3, 5.0)])
+def test_move_moments_fused(E, O, I, prec, n, ppc, vscale):
+    """Fused mover + deposit (two passes on one stale grouping) against the oracle's move then moments.
+
+    Scaled velocities make many particles leave their cell (the stray path),
+    some by more than one cell."""
+    say("move+moments fused", prec, n, ppc, vscale)
+    p, En, BN = make_case(I, n, ppc, 17)
+    for s in p.species:
+        s.v = s.v * vscale
+    rng = np.random.default_rng(18)
+    Bnext = BN + 0.01 * rng.standard_normal(BN.shape)
+    grid = E.Grid(p.n, p.h, p.dt)
+    if prec == "f64":
+        sp = [E.Species.from_f64(s.qom, s.x, s.v, s.q) for s in p.species]
+        xs, vs, qs = [s.x for s in p.species], [s.v for s in p.species], [s.q for s in p.species]
+        Ec, Bc, Bnc = En, BN, Bnext
+        tdt, tol = torch.float64, TOL64
+    else:
+        st = I.to_f32_state(p)
+        sp = [E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"]) for s, f in zip(p.species, st)]
+        xs, vs, qs = [f["x64"] for f in st], [f["v64"] for f in st], [f["q64"] for f in st]
+        Ec, Bc, Bnc = round32(En), round32(BN), round32(Bnext)
+        tdt, tol = torch.float32, TOL32
+    perms = []
+    sp = sorted_species(E, grid, sp, perms)
+    J = torch.empty((3, p.nn), dtype=tdt, device="cuda")
+    M = torch.empty((14, 9, p.nn), dtype=tdt, device="cuda")
+    ke = torch.zeros(1, dtype=torch.float64, device="cuda")
+    # the oracle follows every particle through the same two passes
+    for it in range(2):
+        E.move_moments(grid, sp, dev(Ec, tdt), dev(Bc, tdt), dev(Bnc, tdt), J, M, ke if it == 1 else None)
+        x1s, v1s = [], []
+        for s, x, v in zip(p.species, xs, vs):
+            x1, v1 = O.move(p.n, p.h, p.dt, x, v, s.qom, Ec, Bc)
+            x1s.append(x1)
+            v1s.append(v1)
+        xs, vs = x1s, v1s
+        Jo, Mo = oracle_moments(O, p, xs, vs, qs, Bnc)
+        assert rel(host(J), Jo) < tol
+        assert rel(host(M), Mo) < tol
+    # the particle states themselves, matched through the sort permutation
+    K = 0.0
+    for s, sd, x, v, q, perm in zip(p.species, sp, xs, vs, qs, perms):
+        K += O.kinetic(v, q, s.qom)
+        assert rel(host(sd.vel), v[:, perm]) < tol
+        if prec == "f64":
+            xd = host(sd.pos)
+        else:
+            xd = I.decode_f32(host(sd.cell), host(sd.pos), p.n, p.h)
+        assert periodic_rel(xd, x[:, perm], p.L) < tol
+    assert abs(host(ke)[0] - K) <= (1e-12 if prec == "f64" else 1e-6) * K
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_moments_stale_grouping(E, O, I, prec):
+    """ecsim_moments with a cell_start left stale by a move (the stray path of the plain deposit)."""
+    say("moments stale grouping", prec)
+    p, En, BN = make_case(I, (6, 6, 5), 10, 19)
+    for s in p.species:
+        s.v = s.v * 30.0
+    grid = E.Grid(p.n, p.h, p.dt)
+    if prec == "f64":
+        sp = [E.Species.from_f64(s.qom, s.x, s.v, s.q) for s in p.species]
+        xs, vs, qs = [s.x for s in p.species], [s.v for s in p.species], [s.q for s in p.species]
+        Ec, Bc, tdt, tol = En, BN, torch.float64, TOL64
+    else:
+        st = I.to_f32_state(p)
+        sp = [E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"]) for s, f in zip(p.species, st)]
+        xs, vs, qs = [f["x64"] for f in st], [f["v64"] for f in st], [f["q64"] for f in st]
+        Ec, Bc, tdt, tol = round32(En), round32(BN), torch.float32, TOL32
+    sp = sorted_species(E, grid, sp)
+    for s in sp:
+        cs = s.cell_start
+        E.move(grid, s, dev(Ec, tdt), dev(Bc, tdt))
+        s.cell_start = cs          # keep the pre-move grouping
+    J = torch.empty((3, p.nn), dtype=tdt, device="cuda")
+    M = torch.empty((14, 9, p.nn), dtype=tdt, device="cuda")
+    E.moments(grid, sp, dev(Bc, tdt), J, M, flags=E.SORTED)
+    x1s, v1s = [], []
+    for s, x, v in zip(p.species, xs, vs):
+        x1, v1 = O.move(p.n, p.h, p.dt, x, v, s.qom, Ec, Bc)
+        x1s.append(x1)
+        v1s.append(v1)
+    Jo, Mo = oracle_moments(O, p, x1s, v1s, qs, Bc)
     assert rel(host(J), Jo) < tol
     assert rel(host(M), Mo) < tol
 
@@ -359,13 +453,16 @@ def test_centres_to_nodes_and_energy(E, O, I):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("sort", [False, True])
+@pytest.mark.parametrize("sort", [False, True, "fused"])
 def test_small_workload_ten_steps(E, O, I, prec, sort):
     """8^3 cells, 27 ppc x 2 species, 10 steps: state parity and energy drift."""
-    say("config-0 ten steps", prec, "sorted" if sort else "unsorted")
+    say("config-0 ten steps", prec, sort)
     p = I.config0()
     P = E.F64 if prec == "f64" else E.F32
-    sim = E.Simulation(p, prec=P, tol=1e-10, sort=sort)
+    if sort == "fused":
+        sim = E.Simulation(p, prec=P, tol=1e-10, fused=True, sort_every=3)
+    else:
+        sim = E.Simulation(p, prec=P, tol=1e-10, sort=sort)
     if prec == "f32":
         st = I.to_f32_state(p)
         for s, f in zip(p.species, st):
