@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8, help="oracle runs on 1/cpu-sample of the particles")
     ap.add_argument("--sort-every", type=int, default=4)
+    ap.add_argument("--no-error", action="store_true", help="skip the FP32-vs-FP64 error measurement")
+    ap.add_argument("--calib-copy", action="store_true", help="end with a 1 GiB device copy (byte-counter reference)")
+    ap.add_argument("--path", choices=("fused", "split"), default="fused",
+                    help="fused: one mover+moments kernel; split: mover, then the tiled deposit")
     return ap.parse_args()
 
 
@@ -56,36 +60,62 @@ def algorithmic_bytes(prec, nparticles, nn):
     return 2 * part * nparticles + fld * (9 + 3 + 126) * nn
 
 
+def _median(a):
+    a = sorted(a)
+    n = len(a)
+    return 0.5 * (a[(n - 1) // 2] + a[n // 2]) if n else 0.0
+
+
 def run_form(prec, args, plasma):
     import torch
     from paper_2603_16624_amd import ecsim as E
     P = E.F32 if prec == "f32" else E.F64
-    sim = E.Simulation(plasma, prec=P, tol=1e-10, fused=True, sort_every=args.sort_every)
-    sim.prime()
+    fused = args.path == "fused"
+    sim = E.Simulation(plasma, prec=P, tol=1e-10, fused=fused, sort=True, sort_every=args.sort_every)
     st = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)
+    if fused:
+        sim.prime()
+    else:
+        sim.sort_particles()
+        sim.node_B()
+        sim.deposit()
 
+    # events: 0 solve 1 | 2 field prep 3 particle kernels 4 | re-sort 5 | 6 (split: moments) 7
     def one_step(record):
-        e = [ev() for _ in range(6)]
+        e = [ev() for _ in range(8)]
         e[0].record(st)
         sim.solve()
         e[1].record(st)
         sim.scal[0] = 0.0
         e[2].record(st)
-        sim.fused_pass(sim.scal[0:1])
-        e[3].record(st)
-        sim.advance_fields()
-        sim.BN, sim.BN_next = sim.BN_next, sim.BN
-        if sim.prec == E.F32:
-            sim.BN_p, sim.BN_next_p = sim.BN_next_p, sim.BN_p
+        if fused:
+            sim.fused_fields()
+            e[3].record(st)
+            sim.fused_particles(sim.scal[0:1])
         else:
-            sim.BN_p, sim.BN_next_p = sim.BN, sim.BN_next
+            if sim.prec == E.F32:
+                E.to_f32(sim.E_theta, sim.Et_p)
+            e[3].record(st)
+            sim.push(sim.scal[0:1])
+        e[4].record(st)
+        sim.advance_fields()
+        if fused:
+            sim.BN, sim.BN_next = sim.BN_next, sim.BN
+            if sim.prec == E.F32:
+                sim.BN_p, sim.BN_next_p = sim.BN_next_p, sim.BN_p
+            else:
+                sim.BN_p, sim.BN_next_p = sim.BN, sim.BN_next
         sim.nstep += 1
         sorted_now = sim.nstep % sim.sort_every == 0
         if sorted_now:
             sim.sort_particles()
-        e[4].record(st)
         e[5].record(st)
+        e[6].record(st)
+        if not fused:
+            sim.node_B()
+            sim.deposit()
+        e[7].record(st)
         if record is not None:
             record.append((e, sorted_now))
 
@@ -98,21 +128,67 @@ def run_form(prec, args, plasma):
         one_step(rec)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    mean = lambda a: sum(a) / len(a)
-    solve_ms = mean([e[0].elapsed_time(e[1]) for e, _ in rec])
-    fused_ms = mean([e[2].elapsed_time(e[3]) for e, _ in rec])
-    resort = [e[3].elapsed_time(e[4]) for e, s_ in rec if s_]
-    sort_ms = mean(resort) if resort else 0.0
-    full_ms = mean([e[0].elapsed_time(e[5]) for e, _ in rec])
-    pass_ms = fused_ms + sort_ms / args.sort_every
+    el = lambda i, j: [e[i].elapsed_time(e[j]) for e, _ in rec]
+    solve_ms = _median(el(0, 1))
+    fields_ms = _median(el(2, 3))
+    kernel_ms = _median(el(3, 4))            # fused: the ecsim_move_moments call; split: the mover
+    moments_ms = 0.0 if fused else _median(el(6, 7))
+    resort = [e[4].elapsed_time(e[5]) for e, s_ in rec if s_]
+    sort_ms = _median(resort) if resort else 0.0
+    full_ms = _median(el(0, 7))
+    pass_ms = fields_ms + kernel_ms + moments_ms + sort_ms / args.sort_every
     npart = plasma.n_particles
     nbytes = algorithmic_bytes(prec, npart, plasma.nn)
-    return dict(prec=prec, particles=npart, pass_ms=pass_ms, fused_ms=fused_ms, sort_ms=sort_ms,
-                sort_every=args.sort_every, solve_ms=solve_ms, full_step_ms=full_ms, wall_s=wall,
-                gmres_iters=sim.last_iters, gmres_resid=sim.last_resid,
-                particles_per_s=npart / (pass_ms * 1e-3), bytes_per_step=nbytes,
-                hbm_frac_pass=nbytes / (pass_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
-                fused_gbs=nbytes / (fused_ms * 1e-3) / 1e9)
+    out = dict(prec=prec, path=args.path, particles=npart, pass_ms=pass_ms, fields_ms=fields_ms, kernel_ms=kernel_ms,
+               moments_ms=moments_ms, sort_ms=sort_ms, sort_every=args.sort_every, solve_ms=solve_ms,
+               full_step_ms=full_ms, wall_s=wall, gmres_iters=sim.last_iters, gmres_resid=sim.last_resid,
+               particles_per_s=npart / (pass_ms * 1e-3), particles_per_s_with_sort_every_step=npart / (
+                   (pass_ms - sort_ms / args.sort_every + sort_ms) * 1e-3) if sort_ms else None,
+               bytes_per_step=nbytes, hbm_frac_pass=nbytes / (pass_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+               kernel_gbs=nbytes / (kernel_ms * 1e-3) / 1e9 if fused else None)
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def fixed_error(plasma):
+    """FP32-form error against the FP64 path on the full workload.
+
+    Both forms start from the same state (the FP32 form is the FP64 state
+    encoded as cell + offset), take the moments of the initial state, one
+    field solve and one fused pass. Relative max-norm differences of J-hat,
+    M (after the pass) and E^{n+theta} (the solve) are reported; the FP64
+    path itself agrees with the FP64 oracle to 1e-12.
+    """
+    import torch
+    from paper_2603_16624_amd import ecsim as E
+    sims = {}
+    for P in (E.F64, E.F32):
+        sim = E.Simulation(plasma, prec=P, tol=1e-10, fused=True, sort_every=4)
+        sim.prime()
+        sim.solve()
+        sim.fused_pass(None)
+        torch.cuda.synchronize()
+        sims[P] = (sim.J.double().cpu(), sim.M.double().cpu(), sim.E_theta.cpu())
+        del sim
+        torch.cuda.empty_cache()
+    rel = lambda a, b: float((a - b).abs().max() / b.abs().max())
+    (J64, M64, E64), (J32, M32, E32) = sims[E.F64], sims[E.F32]
+    return {"J": rel(J32, J64), "M": rel(M32, M64), "E_theta": rel(E32, E64), "bound": 1e-5,
+            "against": "FP64 path (same state, one solve + fused pass)"}
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of 1 GiB, three times: the reference for the HBM byte counters."""
+    import torch
+    x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    torch.cuda.empty_cache()
 
 
 def cpu_baseline(plasma, sample):
@@ -170,7 +246,22 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(plasma, args.cpu_sample)
         print(f"[bench] cpu: {json.dumps(cpu)}", file=sys.stderr, flush=True)
-    achieved = r32["fused_gbs"]
+    err = None
+    if not args.no_error:
+        err = fixed_error(plasma)
+        print(f"[bench] fixed error: {json.dumps(err)}", file=sys.stderr, flush=True)
+    if args.calib_copy:
+        calibrate_copy()
+        print("[bench] copy calibration done", file=sys.stderr, flush=True)
+    nbytes = r32["bytes_per_step"]
+    if args.path == "fused":
+        kname = "ecsim_move_moments (FP32): fused mover + moment gather, incl. its stray passes"
+        kms = r32["kernel_ms"]
+    else:
+        kname = "ecsim_move + ecsim_moments (FP32, tiled, stale grouping)"
+        kms = r32["kernel_ms"] + r32["moments_ms"]
+    achieved = nbytes / (kms * 1e-3) / 1e9
+    keys = ("fields_ms", "kernel_ms", "moments_ms", "sort_ms", "solve_ms", "full_step_ms")
     out = {
         "metric": "particles/s through mover+moments (FP32 vs FP64) at fixed error; % HBM peak",
         "value": r32["particles_per_s"],
@@ -186,19 +277,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{plasma.name}; FP32 offset+cell storage, FP32 mover and deposit "
                                f"(Kahan-combined MFMA block sums), FP64 GMRES (tol 1e-10), "
-                               f"re-sort every {args.sort_every} steps",
+                               f"{args.path} path, re-sort every {args.sort_every} steps",
                    "cells": list(plasma.n), "particles": plasma.n_particles, "ppc_per_species": args.ppc,
                    "parallelism": "single GPU"},
         "hbm_frac": r32["hbm_frac_pass"],
-        "breakdown_ms": {k: r32[k] for k in ("fused_ms", "sort_ms", "solve_ms", "full_step_ms")},
+        "breakdown_ms": {k: r32[k] for k in keys},
         "sort_every": args.sort_every,
+        "particles_per_s_with_sort_every_step": r32["particles_per_s_with_sort_every_step"],
         "gmres": {"iters_last": r32["gmres_iters"], "rel_resid_last": r32["gmres_resid"]},
+        "fixed_error": err,
         "fp64": None if r64 is None else {
             "value": r64["particles_per_s"], "ms_per_step": r64["pass_ms"], "hbm_frac": r64["hbm_frac_pass"],
-            "breakdown_ms": {k: r64[k] for k in ("fused_ms", "sort_ms", "solve_ms", "full_step_ms")}},
-        "roofline": {"kernel": "ecsim_move_moments (FP32): fused mover + moment gather", "bound": "hbm",
-                     "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+            "breakdown_ms": {k: r64[k] for k in keys}},
+        "roofline": {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes": nbytes, "launch_ms": kms},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

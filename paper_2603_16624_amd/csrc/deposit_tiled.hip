@@ -38,6 +38,8 @@ namespace {
 
 constexpr int kMaxTiledSpecies = 4;
 constexpr int kItemShift = 28;              // stray item = species << 28 | particle index
+constexpr int kUnmoved = 1 << 30;           // flag: listed before the move (fused form)
+constexpr int kIndexMask = (1 << kItemShift) - 1;
 constexpr int SCS = 268;                    // per-cell sums: [27][9] mass-matrix classes, [8][3] currents, pad
 
 enum Mode { kDeposit = 0, kMoveDeposit = 1, kIndirect = 2 };
@@ -107,6 +109,64 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Writes the strays a wavefront keeps (per lane: slot 0 if k0, slot 1 if k1)
+// to the list at base, or, for base < 0, at a place reserved with one atomic.
+// Reached by the whole wavefront.
+template <typename TA>
+__device__ __forceinline__ void write_strays(const TA& args, int lane, int base, bool k0, int i0, int c0, bool k1,
+                                             int i1, int c1) {
+  const unsigned long long b0 = __ballot(k0), b1 = __ballot(k1);
+  if (base < 0) {
+    int r = 0;
+    if (lane == 0) r = atomicAdd(args.stray_count, __popcll(b0) + __popcll(b1));
+    base = __shfl(r, 0);
+  }
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int pos = base + __popcll(b0 & below) + __popcll(b1 & below);
+  if (k0) {
+    args.stray_item[pos] = i0;
+    args.stray_cell[pos] = c0;
+    ++pos;
+  }
+  if (k1) {
+    args.stray_item[pos] = i1;
+    args.stray_cell[pos] = c1;
+  }
+}
+
+// Per-lane holding slots for strays (item, cell). When a lane needs a third
+// slot the whole wavefront empties its slots into the list.
+struct StrayBuf {
+  int n = 0;
+  int item0 = 0, cell0 = 0, item1 = 0, cell1 = 0;
+  __device__ __forceinline__ void push(int item, int cell) {
+    if (n == 0) {
+      item0 = item;
+      cell0 = cell;
+    } else {
+      item1 = item;
+      cell1 = cell;
+    }
+    ++n;
+  }
+  template <typename TA>
+  __device__ __forceinline__ void flush(const TA& args, int lane) {
+    write_strays(args, lane, -1, n >= 1, item0, cell0, n >= 2, item1, cell1);
+    n = 0;
+  }
+};
+
+// Particle arrays are addressed through pointers held in LDS; these casts
+// give the compiler the global address space (global_load/store, not flat).
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
 template <typename T>
 struct PData {       // one particle's inputs, loaded ahead of use
   T x0, x1, x2, v0, v1, v2, q;
@@ -124,25 +184,29 @@ __device__ __forceinline__ PData<T> load_particle(const TArgs<T>& args, const TS
     int s = 0, idx = ip, p;
     if constexpr (MODE == kIndirect) {
       const int item = args.ind_item[beg[0] + ip];
-      s = item >> kItemShift;
-      p = item & ((1 << kItemShift) - 1);
+      s = (item >> kItemShift) & (kMaxTiledSpecies - 1);
+      p = item & kIndexMask;
     } else {
+      p = beg[0] + idx;
 #pragma unroll
       for (int k = 0; k < kMaxTiledSpecies - 1; ++k)
-        if (s == k && idx >= cnt[k]) { idx -= cnt[k]; s = k + 1; }
-      p = beg[s] + idx;
+        if (s == k && idx >= cnt[k]) {   // constant indices only: no private memory
+          idx -= cnt[k];
+          s = k + 1;
+          p = beg[k + 1] + idx;
+        }
     }
     const TSpecies<T>& sp = lsp[s];   // LDS copy: a lane-dependent species costs no memory round trip
     d.s = s;
     d.p = p;
-    d.x0 = sp.pos[0][p];
-    d.x1 = sp.pos[1][p];
-    d.x2 = sp.pos[2][p];
-    d.v0 = sp.vel[0][p];
-    d.v1 = sp.vel[1][p];
-    d.v2 = sp.vel[2][p];
-    d.q = sp.q ? sp.q[p] : sp.q_const;
-    if constexpr (sizeof(T) == 4) d.c = sp.cell[p];
+    d.x0 = gld(sp.pos[0] + p);
+    d.x1 = gld(sp.pos[1] + p);
+    d.x2 = gld(sp.pos[2] + p);
+    d.v0 = gld(sp.vel[0] + p);
+    d.v1 = gld(sp.vel[1] + p);
+    d.v2 = gld(sp.vel[2] + p);
+    d.q = sp.q ? gld(sp.q + p) : sp.q_const;
+    if constexpr (sizeof(T) == 4) d.c = gld(sp.cell + p);
   }
   return d;
 }
@@ -187,6 +251,116 @@ __host__ __device__ constexpr int pair_class(int k, int a) {
              : (2 * (a & 1) + koff(k, 0)) + 3 * (2 * ((a >> 1) & 1) + koff(k, 1)) + 9 * (2 * ((a >> 2) & 1) + koff(k, 2));
 }
 
+// One half-wavefront's cell of a pair (local index lc in the brick).
+struct PairCell {
+  int lc, cell, cx, cy, cz;
+  bool valid;
+};
+
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ PairCell pair_cell(const Grid& g, int x0, int y0, int z0, int pair, int half) {
+  PairCell c;
+  c.lc = 2 * pair + half;
+  c.cx = x0 + c.lc % TX;
+  c.cy = y0 + (c.lc / TX) % TY;
+  c.cz = z0 + c.lc / (TX * TY);
+  c.valid = c.lc < TX * TY * TZ && c.cx < g.nx && c.cy < g.ny && c.cz < g.nz;
+  c.cell = c.valid ? c.cx + g.nx * (c.cy + g.ny * c.cz) : -1;
+  return c;
+}
+
+// cell range loads, issued one pair ahead of their use
+struct RangeLd {
+  int lo[kMaxTiledSpecies], hi[kMaxTiledSpecies];
+};
+struct Ranges {
+  int cnt[kMaxTiledSpecies], beg[kMaxTiledSpecies], total;
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ RangeLd load_ranges(const TArgs<T>& args, const TSpecies<T>* lsp, const PairCell& c) {
+  RangeLd r{};
+  const int cl = c.valid ? c.cell : 0;
+  if constexpr (MODE == kIndirect) {
+    r.lo[0] = args.ind_start[cl];
+    r.hi[0] = args.ind_start[cl + 1];
+  } else {
+#pragma unroll
+    for (int s = 0; s < kMaxTiledSpecies; ++s) {
+      const int32_t* cs = lsp[s].cell_start;   // unused species alias species 0
+      r.lo[s] = cs[cl];
+      r.hi[s] = cs[cl + 1];
+    }
+  }
+  return r;
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ Ranges make_ranges(const TArgs<T>& args, const RangeLd& r, const PairCell& c) {
+  Ranges q{};
+#pragma unroll
+  for (int s = 0; s < kMaxTiledSpecies; ++s) {
+    const bool used = MODE == kIndirect ? s == 0 : s < args.ns;
+    q.beg[s] = r.lo[s];
+    q.cnt[s] = (c.valid && used) ? r.hi[s] - r.lo[s] : 0;
+    q.total += q.cnt[s];
+  }
+  return q;
+}
+
+// corner fields of a cell: lane hl < 24 holds component hl / 8 at corner hl % 8
+template <typename T>
+struct StageLd {
+  T b, e, m;
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ StageLd<T> load_stage(const Grid& g, const TArgs<T>& args, const PairCell& c, int hl) {
+  StageLd<T> r{};
+  if (hl < 24) {
+    Stencil<T> st{};
+    st.i[0] = c.valid ? c.cx : 0;
+    st.i[1] = c.valid ? c.cy : 0;
+    st.i[2] = c.valid ? c.cz : 0;
+    st.ip[0] = wrap_up(st.i[0], g.nx);
+    st.ip[1] = wrap_up(st.i[1], g.ny);
+    st.ip[2] = wrap_up(st.i[2], g.nz);
+    const int64_t nd = (hl >> 3) * g.nn + corner_node(g, st, hl & 7);
+    r.b = args.Bdep[nd];
+    if constexpr (MODE == kMoveDeposit) {
+      r.e = args.Emove[nd];
+      r.m = args.Bmove[nd];
+    }
+  }
+  return r;
+}
+
+// A particle's record: the 12 values ((q beta / V) alpha, (q / V) alpha v)
+// and its 27 class weights, from the deposit field B1 at its position.
+template <typename T>
+__device__ __forceinline__ void particle_record(const Stencil<T>& ps, const Vec3<T>& B1, const Vec3<T>& v, T q,
+                                                const TSpecies<T>& sp, T r[39]) {
+  T al[9];
+  rotation(B1, sp.beta, al);
+  const Vec3<T> vh = matvec(al, v);
+  const T cm = q * sp.beta_V;
+  const T cj = q * sp.inv_V;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) r[i] = cm * al[i];
+  r[9] = cj * vh.x;
+  r[10] = cj * vh.y;
+  r[11] = cj * vh.z;
+  T f[3][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    f[d][0] = ps.w0[d] * ps.w0[d];
+    f[d][1] = ps.w0[d] * ps.w1[d];
+    f[d][2] = ps.w1[d] * ps.w1[d];
+  }
+#pragma unroll
+  for (int c = 0; c < 27; ++c) r[12 + c] = (f[0][c % 3] * f[1][(c / 3) % 3]) * f[2][c / 9];
+}
+
 // Records in LDS are stored transposed, rec[row][slot] with a row stride of
 // 66 slots (64 particles + 2): the MFMA operand reads of 16 lanes with
 // consecutive rows and 2 lane groups then hit 32 different banks. Rows 39-43
@@ -211,6 +385,7 @@ __global__ void __launch_bounds__(NW * 64) k_tiled(Grid g, TArgs<T> args, int nt
   __shared__ __attribute__((aligned(16))) T smem[NW * WREC + NCELL * SCS];
   __shared__ double red[NW];
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
+  __shared__ int wst[NW];
   T* const scell = smem + NW * WREC;
 
   const int tid = threadIdx.x;
@@ -253,69 +428,49 @@ __global__ void __launch_bounds__(NW * 64) k_tiled(Grid g, TArgs<T> args, int nt
   T* const wrec = smem + wave * WREC;
   // this lane's MFMA operand base: row col, slot grp (cell A) / 32 + grp (cell B)
   const T* const opnd = wrec + col * kSlots + grp;
+  T* const stage = wrec + kStage + 72 * half;
   double kel = 0.0;
+  StrayBuf sb;
+
+  // Pair pipeline: while a pair of cells is processed, the next pair's cell
+  // ranges and corner fields, and then its first particle block, are loaded.
+  PairCell pc = pair_cell<TX, TY, TZ>(g, x0, y0, z0, wave, half);
+  StageLd<T> sl = load_stage<T, MODE>(g, args, pc, hl);
+  Ranges rg = make_ranges<T, MODE>(args, load_ranges<T, MODE>(args, lsp, pc), pc);
+  PData<T> pd = load_particle<T, MODE>(args, lsp, rg.cnt, rg.beg, rg.total, hl);
 
   for (int pair = wave; pair < NPAIR; pair += NW) {
-    // my half's cell
-    const int lc = 2 * pair + half;
-    const int lx = lc % TX, ly = (lc / TX) % TY, lz = lc / (TX * TY);
-    const int cx = x0 + lx, cy = y0 + ly, cz = z0 + lz;
-    const bool valid = (lc < NCELL) && cx < g.nx && cy < g.ny && cz < g.nz;
-    const int cell = valid ? cx + g.nx * (cy + g.ny * cz) : -1;
-    int cnt[kMaxTiledSpecies];
-    int beg[kMaxTiledSpecies];
-    int total = 0;
-#pragma unroll
-    for (int s = 0; s < kMaxTiledSpecies; ++s) {
-      cnt[s] = 0;
-      beg[s] = 0;
+    const bool has_next = pair + NW < NPAIR;   // wave-uniform
+    const PairCell nc = pair_cell<TX, TY, TZ>(g, x0, y0, z0, has_next ? pair + NW : pair, half);
+    RangeLd nrl{};
+    StageLd<T> nsl{};
+    if (has_next) {
+      nrl = load_ranges<T, MODE>(args, lsp, nc);
+      nsl = load_stage<T, MODE>(g, args, nc, hl);
     }
-    {
-      // all range loads are issued before any is used
-      const int cl = valid ? cell : 0;
-      if constexpr (MODE == kIndirect) {
-        const int b0 = args.ind_start[cl], b1 = args.ind_start[cl + 1];
-        beg[0] = b0;
-        cnt[0] = valid ? b1 - b0 : 0;
-      } else {
-        int lo[kMaxTiledSpecies], hi[kMaxTiledSpecies];
-#pragma unroll
-        for (int s = 0; s < kMaxTiledSpecies; ++s) {
-          const int32_t* cs = lsp[s].cell_start;   // unused species alias species 0
-          lo[s] = cs[cl];
-          hi[s] = cs[cl + 1];
-        }
-#pragma unroll
-        for (int s = 0; s < kMaxTiledSpecies; ++s) {
-          beg[s] = lo[s];
-          cnt[s] = (valid && s < args.ns) ? hi[s] - lo[s] : 0;
-        }
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < kMaxTiledSpecies; ++s) total += cnt[s];
-    const int cntA = __builtin_amdgcn_readfirstlane(__shfl(total, 0));
-    const int cntB = __builtin_amdgcn_readfirstlane(__shfl(total, 32));
+    const Ranges cr = rg;
+    const int lc = pc.lc;
+    const int cell = pc.cell;
+    const int cntA = __builtin_amdgcn_readfirstlane(__shfl(cr.total, 0));
+    const int cntB = __builtin_amdgcn_readfirstlane(__shfl(cr.total, 32));
     const int cmax = cntA > cntB ? cntA : cntB;
-    if (cmax == 0) continue;   // wave-uniform: both cells empty
-    // corner nodes of the cell; lanes of each half stage the corner fields
-    Stencil<T> st{};
-    st.i[0] = valid ? cx : 0;
-    st.i[1] = valid ? cy : 0;
-    st.i[2] = valid ? cz : 0;
-    st.ip[0] = wrap_up(st.i[0], g.nx);
-    st.ip[1] = wrap_up(st.i[1], g.ny);
-    st.ip[2] = wrap_up(st.i[2], g.nz);
-    T* const stage = wrec + kStage + 72 * half;
+    if (cmax == 0) {   // wave-uniform: both cells empty
+      if (has_next) {
+        rg = make_ranges<T, MODE>(args, nrl, nc);
+        pd = load_particle<T, MODE>(args, lsp, rg.cnt, rg.beg, rg.total, hl);
+      }
+      pc = nc;
+      sl = nsl;
+      continue;
+    }
+    // corner fields of the cell, staged for the lanes of this half
     if (hl < 24) {
-      const int64_t nd = (hl >> 3) * g.nn + corner_node(g, st, hl & 7);
-      stage[hl] = args.Bdep[nd];
+      stage[hl] = sl.b;
       if constexpr (MODE == kMoveDeposit) {
-        stage[24 + hl] = args.Emove[nd];
-        stage[48 + hl] = args.Bmove[nd];
+        stage[24 + hl] = sl.e;
+        stage[48 + hl] = sl.m;
       }
     }
-    PData<T> pd = load_particle<T, MODE>(args, lsp, cnt, beg, total, hl);
     wave_sync();
 
     // running sums of the two cells: [cell][tile][reg]
@@ -329,132 +484,92 @@ __global__ void __launch_bounds__(NW * 64) k_tiled(Grid g, TArgs<T> args, int nt
 
     for (int ch = 0; ch < cmax; ch += 32) {
       // ---- 1. particle lanes: (move and) one record column per lane ----
-      T r[39];
+      // Every lane runs the same arithmetic; lanes whose particle is not
+      // deposited here carry zero charge, so their record values are zero.
+      const TSpecies<T>& sp = lsp[pd.s];
+      Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
+      const int pcell0 = ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]);
+      // in its range's cell: moved (fused form) and deposited with staged fields
+      const bool here = pd.ok && pcell0 == cell;
+      int pcell = pcell0;
+      Vec3<T> v{pd.v0, pd.v1, pd.v2};
+      T mx0 = T(0), mx1 = T(0), mx2 = T(0);
+      if constexpr (MODE == kMoveDeposit) {
+        T W[8];
 #pragma unroll
-      for (int i = 0; i < 39; ++i) r[i] = T(0);
-      bool stray = false;
-      int new_cell = 0;
-      // moved state, written back after the next block's loads are issued
-      T mv0 = T(0), mv1 = T(0), mv2 = T(0), mx0 = T(0), mx1 = T(0), mx2 = T(0);
-      int mcell = 0;
-      const bool moved = (MODE == kMoveDeposit) && pd.ok;
-      const int ms = pd.s, mp = pd.p;
-      if (pd.ok) {
-        const TSpecies<T>& sp = lsp[pd.s];
-        Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
-        int pcell = ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]);
-        Vec3<T> v{pd.v0, pd.v1, pd.v2};
-        if constexpr (MODE == kMoveDeposit) {
-          T W[8];
-          int64_t nd[8];
-          Vec3<T> Ep, Bp;
-          if (pcell == cell) {
-#pragma unroll
-            for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
-            Ep = gather_staged(W, stage + 24);
-            Bp = gather_staged(W, stage + 48);
-          } else {
-            corners(g, ps, W, nd);
-            Ep = gather(args.Emove, g.nn, W, nd);
-            Bp = gather(args.Bmove, g.nn, W, nd);
-          }
-          T a0[9];
-          rotation(Bp, sp.beta, a0);
-          Vec3<T> u;
-          v = velocity_update(a0, v, Ep, sp.beta, u);
-          mv0 = v.x;
-          mv1 = v.y;
-          mv2 = v.z;
-          if constexpr (sizeof(T) == 4) {
-            int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
-            const float ox = push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx);
-            const float oy = push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny);
-            const float oz = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
-            pcell = ix + g.nx * (iy + g.ny * iz);
-            mx0 = ox;
-            mx1 = oy;
-            mx2 = oz;
-            mcell = pcell;
-            ps.i[0] = ix; ps.i[1] = iy; ps.i[2] = iz;
-            ps.ip[0] = wrap_up(ix, g.nx); ps.ip[1] = wrap_up(iy, g.ny); ps.ip[2] = wrap_up(iz, g.nz);
-            ps.w1[0] = ox; ps.w1[1] = oy; ps.w1[2] = oz;
-            ps.w0[0] = 1.0f - ox; ps.w0[1] = 1.0f - oy; ps.w0[2] = 1.0f - oz;
-          } else {
-            const double nx0 = push_abs(pd.x0, g.dt, v.x, g.nx * g.hx);
-            const double nx1 = push_abs(pd.x1, g.dt, v.y, g.ny * g.hy);
-            const double nx2 = push_abs(pd.x2, g.dt, v.z, g.nz * g.hz);
-            mx0 = nx0;
-            mx1 = nx1;
-            mx2 = nx2;
-            ps = stencil_abs(g, nx0, nx1, nx2);
-            pcell = ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]);
-          }
-          if (args.ke) {
-            const double vx = v.x, vy = v.y, vz = v.z;
-            kel += 0.5 * ((double)pd.q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz);
-          }
-        }
-        if (pcell != cell) {
-          stray = true;
-          new_cell = pcell;
+        for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
+        const Vec3<T> Ep = gather_staged(W, stage + 24);
+        const Vec3<T> Bp = gather_staged(W, stage + 48);
+        T a0[9];
+        rotation(Bp, sp.beta, a0);
+        Vec3<T> u;
+        v = velocity_update(a0, v, Ep, sp.beta, u);
+        if constexpr (sizeof(T) == 4) {
+          int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
+          const float ox = push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx);
+          const float oy = push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny);
+          const float oz = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
+          pcell = ix + g.nx * (iy + g.ny * iz);
+          mx0 = ox;
+          mx1 = oy;
+          mx2 = oz;
+          ps.i[0] = ix; ps.i[1] = iy; ps.i[2] = iz;
+          ps.ip[0] = wrap_up(ix, g.nx); ps.ip[1] = wrap_up(iy, g.ny); ps.ip[2] = wrap_up(iz, g.nz);
+          ps.w1[0] = ox; ps.w1[1] = oy; ps.w1[2] = oz;
+          ps.w0[0] = 1.0f - ox; ps.w0[1] = 1.0f - oy; ps.w0[2] = 1.0f - oz;
         } else {
-          T W[8];
-#pragma unroll
-          for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
-          const Vec3<T> B1 = gather_staged(W, stage);
-          T al[9];
-          rotation(B1, sp.beta, al);
-          const Vec3<T> vh = matvec(al, v);
-          const T cm = pd.q * sp.beta_V;
-          const T cj = pd.q * sp.inv_V;
-#pragma unroll
-          for (int i = 0; i < 9; ++i) r[i] = cm * al[i];
-          r[9] = cj * vh.x;
-          r[10] = cj * vh.y;
-          r[11] = cj * vh.z;
-          T f[3][3];
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            f[d][0] = ps.w0[d] * ps.w0[d];
-            f[d][1] = ps.w0[d] * ps.w1[d];
-            f[d][2] = ps.w1[d] * ps.w1[d];
-          }
-#pragma unroll
-          for (int c = 0; c < 27; ++c) r[12 + c] = (f[0][c % 3] * f[1][(c / 3) % 3]) * f[2][c / 9];
+          mx0 = push_abs(pd.x0, g.dt, v.x, g.nx * g.hx);
+          mx1 = push_abs(pd.x1, g.dt, v.y, g.ny * g.hy);
+          mx2 = push_abs(pd.x2, g.dt, v.z, g.nz * g.hz);
+          ps = stencil_abs(g, mx0, mx1, mx2);
+          pcell = ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]);
         }
+        if (args.ke && here) {
+          const double vx = v.x, vy = v.y, vz = v.z;
+          kel += 0.5 * ((double)pd.q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz);
+        }
+      }
+      const bool keep = here && pcell == cell;   // deposited by this block
+      {
+        T W[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
+        const Vec3<T> B1 = gather_staged(W, stage);
+        T r[39];
+        particle_record(ps, B1, v, keep ? pd.q : T(0), sp, r);
+#pragma unroll
+        for (int i = 0; i < 39; ++i) wrec[i * kSlots + lane] = r[i];
       }
       if constexpr (MODE != kIndirect) {
-        // strays: one atomic per wavefront reserves their slots in the list
-        const unsigned long long m = __ballot(stray);
-        if (m) {
-          const int leader = __ffsll((unsigned long long)m) - 1;
-          int base = 0;
-          if (lane == leader) base = atomicAdd(args.stray_count, __popcll(m));
-          base = __shfl(base, leader);
-          if (stray) {
-            const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
-            args.stray_item[pos] = (pd.s << kItemShift) | pd.p;
-            args.stray_cell[pos] = new_cell;
-          }
-        }
+        // Strays wait in two register slots per lane. In the fused form a
+        // particle found outside its range's cell (the grouping is stale) is
+        // listed unmoved, to be moved by the stray mover.
+        const bool stray = pd.ok && !keep;
+        const int item = (pd.s << kItemShift) | pd.p | ((MODE == kMoveDeposit && !here) ? kUnmoved : 0);
+        if (__ballot(stray && sb.n == 2)) sb.flush(args, lane);
+        if (stray) sb.push(item, here ? pcell : pcell0);
       }
-#pragma unroll
-      for (int i = 0; i < 39; ++i) wrec[i * kSlots + lane] = r[i];
       wave_sync();
-      // prefetch the next block's particles while this block is reduced; the
-      // loads are issued before the write-back so that waiting for them does
-      // not wait for the stores
-      if (ch + 32 < cmax) pd = load_particle<T, MODE>(args, lsp, cnt, beg, total, ch + 32 + hl);
+      // prefetch the next block (of this pair, else of the next pair) while
+      // this block is reduced; the loads are issued before the write-back so
+      // that waiting for them does not wait for the stores
+      const int ms = pd.s, mp = pd.p;
+      if (ch + 32 < cmax) {
+        pd = load_particle<T, MODE>(args, lsp, cr.cnt, cr.beg, cr.total, ch + 32 + hl);
+      } else if (has_next) {
+        rg = make_ranges<T, MODE>(args, nrl, nc);
+        pd = load_particle<T, MODE>(args, lsp, rg.cnt, rg.beg, rg.total, hl);
+      }
       if constexpr (MODE == kMoveDeposit) {
-        if (moved) {
-          const TSpecies<T>& sp = lsp[ms];
-          sp.vel[0][mp] = mv0;
-          sp.vel[1][mp] = mv1;
-          sp.vel[2][mp] = mv2;
-          sp.pos[0][mp] = mx0;
-          sp.pos[1][mp] = mx1;
-          sp.pos[2][mp] = mx2;
-          if constexpr (sizeof(T) == 4) sp.cell[mp] = mcell;
+        if (here) {
+          const TSpecies<T>& spm = lsp[ms];
+          gst(spm.vel[0] + mp, v.x);
+          gst(spm.vel[1] + mp, v.y);
+          gst(spm.vel[2] + mp, v.z);
+          gst(spm.pos[0] + mp, mx0);
+          gst(spm.pos[1] + mp, mx1);
+          gst(spm.pos[2] + mp, mx2);
+          if constexpr (sizeof(T) == 4) gst(spm.cell + mp, pcell);
         }
       }
 
@@ -527,6 +642,8 @@ __global__ void __launch_bounds__(NW * 64) k_tiled(Grid g, TArgs<T> args, int nt
       scell[lc * SCS + 243 + 3 * a + comp] = s;
     }
     wave_sync();
+    pc = nc;
+    sl = nsl;
   }
   if constexpr (MODE == kMoveDeposit) {
     if (args.ke) {
@@ -534,7 +651,26 @@ __global__ void __launch_bounds__(NW * 64) k_tiled(Grid g, TArgs<T> args, int nt
       if (lane == 0) red[wave] = kel;
     }
   }
-  __syncthreads();
+  __syncthreads();   // the per-cell sums are complete
+  if constexpr (MODE != kIndirect) {
+    // the strays still held take one reservation of the workgroup in the list
+    const bool k0 = sb.n >= 1, k1 = sb.n >= 2;
+    const int wtot = __popcll(__ballot(k0)) + __popcll(__ballot(k1));
+    if (lane == 0) wst[wave] = wtot;
+    __syncthreads();
+    if (tid == 0) {
+      int tot = 0;
+      for (int w = 0; w < NW; ++w) tot += wst[w];
+      int base = tot ? atomicAdd(args.stray_count, tot) : 0;
+      for (int w = 0; w < NW; ++w) {
+        const int c = wst[w];
+        wst[w] = base;
+        base += c;
+      }
+    }
+    __syncthreads();
+    write_strays(args, lane, wst[wave], k0, sb.item0, sb.cell0, k1, sb.item1, sb.cell1);
+  }
   if constexpr (MODE == kMoveDeposit) {
     if (args.ke && tid == 0) {
       double s = 0.0;
@@ -586,6 +722,79 @@ __global__ void __launch_bounds__(NW * 64) k_tiled(Grid g, TArgs<T> args, int nt
         }
       }
       if (v != T(0)) unsafeAtomicAdd(J + (int64_t)sub * g.nn + gn, v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stray mover (fused form): particles listed before their move -- found
+// outside their range's cell -- are moved here with fields read from memory,
+// in the same arithmetic as the tiled kernel, and their new cell recorded.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
+  __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
+  __shared__ double red[4];
+  if (threadIdx.x < kMaxTiledSpecies) lsp[threadIdx.x] = args.s[threadIdx.x < args.ns ? threadIdx.x : 0];
+  __syncthreads();
+  const int n = *args.stray_count;
+  double kel = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const int item = args.stray_item[i];
+    if (!(item & kUnmoved)) continue;
+    const int s = (item >> kItemShift) & (kMaxTiledSpecies - 1);
+    const int p = item & kIndexMask;
+    const TSpecies<T>& sp = lsp[s];
+    const T q = sp.q ? gld(sp.q + p) : sp.q_const;
+    int c = 0;
+    if constexpr (sizeof(T) == 4) c = gld(sp.cell + p);
+    const T x0 = gld(sp.pos[0] + p), x1 = gld(sp.pos[1] + p), x2 = gld(sp.pos[2] + p);
+    Stencil<T> ps = particle_stencil<T>(g, x0, x1, x2, c);
+    T W[8];
+    int64_t nd[8];
+    corners(g, ps, W, nd);
+    const Vec3<T> Ep = gather(args.Emove, g.nn, W, nd);
+    const Vec3<T> Bp = gather(args.Bmove, g.nn, W, nd);
+    T a0[9];
+    rotation(Bp, sp.beta, a0);
+    Vec3<T> u;
+    const Vec3<T> v = velocity_update(a0, Vec3<T>{gld(sp.vel[0] + p), gld(sp.vel[1] + p), gld(sp.vel[2] + p)}, Ep,
+                                      sp.beta, u);
+    int ncell;
+    if constexpr (sizeof(T) == 4) {
+      int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
+      gst(sp.pos[0] + p, push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx));
+      gst(sp.pos[1] + p, push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny));
+      gst(sp.pos[2] + p, push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz));
+      ncell = ix + g.nx * (iy + g.ny * iz);
+      gst(sp.cell + p, ncell);
+    } else {
+      const double n0 = push_abs(x0, g.dt, v.x, g.nx * g.hx);
+      const double n1 = push_abs(x1, g.dt, v.y, g.ny * g.hy);
+      const double n2 = push_abs(x2, g.dt, v.z, g.nz * g.hz);
+      gst(sp.pos[0] + p, (T)n0);
+      gst(sp.pos[1] + p, (T)n1);
+      gst(sp.pos[2] + p, (T)n2);
+      const Stencil<double> nps = stencil_abs(g, n0, n1, n2);
+      ncell = nps.i[0] + g.nx * (nps.i[1] + g.ny * nps.i[2]);
+    }
+    gst(sp.vel[0] + p, v.x);
+    gst(sp.vel[1] + p, v.y);
+    gst(sp.vel[2] + p, v.z);
+    args.stray_cell[i] = ncell;
+    args.stray_item[i] = item & ~kUnmoved;
+    if (args.ke) {
+      const double vx = v.x, vy = v.y, vz = v.z;
+      kel += 0.5 * ((double)q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz);
+    }
+  }
+  if (args.ke) {
+    for (int off = 32; off > 0; off >>= 1) kel += __shfl_down(kel, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = kel;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double t = (red[0] + red[1]) + (red[2] + red[3]);
+      if (t != 0.0) unsafeAtomicAdd(args.ke, t);
     }
   }
 }
@@ -708,6 +917,10 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
     hipLaunchKernelGGL((k_tiled<T, TX, TY, TZ, NW, kDeposit>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty,
                        ntz, (T*)J, (T*)M);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (move) {
+    hipLaunchKernelGGL(k_move_strays<T>, dim3(1024), dim3(256), 0, st, g, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   // strays: counting sort by cell, then the indirect pass
   if ((e = launch_zero(w.counts, sizeof(int) * (size_t)g.nn, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_stray_rank, dim3(1024), dim3(256), 0, st, (const int*)w.count, (const int*)w.cell, w.counts,

@@ -328,7 +328,9 @@ class Simulation:
     Particles stay on the device in the requested precision; the fields E, B_C,
     the GMRES solve and the energy diagnostic are FP64. With ``sort=True`` the
     particles are re-sorted by cell before each deposit and the tiled deposit
-    is used.
+    is used; between re-sorts (every ``sort_every`` steps) the cell ranges
+    are a stale grouping that the deposit corrects for. With ``fused=True``
+    the mover and the next step's moments run as one pass.
     """
 
     def __init__(self, plasma, prec: int = F64, device="cuda", tol: float = 1e-10, restart: int = 30,
@@ -405,8 +407,9 @@ class Simulation:
         else:
             Et = self.E_theta
         for s in self.species:
+            # the cell ranges stay a valid (stale) grouping: the tiled deposit
+            # takes particles that left their range through its stray list
             move(self.grid, s, Et, self.BN_p, ke)
-            s.cell_start = None
 
     def advance_fields(self):
         self.E, self.E_next = self.E_next, self.E
@@ -419,15 +422,21 @@ class Simulation:
         self.deposit()
         self.primed = True
 
-    def fused_pass(self, ke: Optional[torch.Tensor] = None):
-        """Mover with (E^{n+theta}, B^n), then the moments at x^{n+1/2} with B^{n+1}."""
+    def fused_fields(self):
+        """Node fields of the fused pass: B^{n+1} at the nodes, E^{n+theta} in particle precision."""
         centres_to_nodes(self.grid, self.BC_next, self.BN_next, self.BN_next_p if self.prec == F32 else None)
         if self.prec == F32:
             to_f32(self.E_theta, self.Et_p)
-            Et = self.Et_p
-        else:
-            Et = self.E_theta
+
+    def fused_particles(self, ke: Optional[torch.Tensor] = None):
+        """The fused particle pass proper (fused_fields() first)."""
+        Et = self.Et_p if self.prec == F32 else self.E_theta
         move_moments(self.grid, self.species, Et, self.BN_p, self.BN_next_p, self.J, self.M, ke, ws=self.ws)
+
+    def fused_pass(self, ke: Optional[torch.Tensor] = None):
+        """Mover with (E^{n+theta}, B^n), then the moments at x^{n+1/2} with B^{n+1}."""
+        self.fused_fields()
+        self.fused_particles(ke)
 
     def advance_fused(self):
         self.advance_fields()
@@ -449,7 +458,7 @@ class Simulation:
             self.fused_pass(self.scal[0:1])
             self.advance_fused()
             return
-        if self.do_sort:
+        if self.do_sort and (self.nstep % self.sort_every == 0 or any(s.cell_start is None for s in self.species)):
             self.sort_particles()
         self.node_B()
         self.deposit()
@@ -457,6 +466,7 @@ class Simulation:
         self.scal[0] = 0.0
         self.push(self.scal[0:1])
         self.advance_fields()
+        self.nstep += 1
 
     def energy(self):
         """(W_E, W_B) of the current fields on the host (FP64 device reductions)."""
