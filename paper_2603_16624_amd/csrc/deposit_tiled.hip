@@ -1,5 +1,5 @@
-// Tiled moment deposit (Eqs. 1 and 3) over cell-grouped particles, alone or
-// fused with the mover (Eqs. 4, 5, 8).
+// Tiled moment deposit (Eqs. 1 and 3) over cell-grouped particles, and the
+// grouped mover (Eqs. 4, 5, 8) that feeds it.
 //
 // Per cell the deposit is a small dense contraction. For corner pair (a, b)
 // the weight product W_a W_b depends only on the class c = a + b in {0,1,2}^3
@@ -11,13 +11,21 @@
 // receives S[a+b][0..8]; by the partition of unity sum_b W_b = 1 the current
 // at corner a is J_a = sum_b S[a+b][9..11].
 //
-// Structure. A workgroup owns a brick of TX x TY x TZ cells. Each wavefront
-// takes two cells at a time (lanes 0-31: cell A, 32-63: cell B):
-//   1. particle lanes take one particle each -- in the fused form they first
-//      move it (E^{n+theta}, B^n at its old position) and write it back -- and
-//      write a record to LDS: the 12 values and the 27 class weights, computed
-//      with the same routines as the mover so alpha_p and W_pN agree bit for
-//      bit;
+// Particles are grouped by per-species cell ranges (cell_start) that may be
+// stale. One pass, per brick of cells, runs over the ranges first: the
+// grouped mover moves every particle with the corner fields of its range's
+// cell staged in LDS (a particle already outside that cell is left to a small
+// kernel that reads its fields from memory), or, for a deposit alone, the
+// ranges are only checked. Every particle that is not in its range's cell
+// afterwards goes to a stray list, which is counting-sorted by cell.
+//
+// The deposit kernel: a workgroup owns a brick of TX x TY x TZ cells; each
+// cell's particles are its species ranges (entries outside the cell carry
+// zero charge) followed by its entries of the sorted stray list. Each
+// wavefront takes two cells at a time (lanes 0-31: cell A, 32-63: cell B):
+//   1. particle lanes take one particle each and write a record to LDS: the
+//      12 values and the 27 class weights, computed with the same routines as
+//      the mover so alpha_p and W_pN agree bit for bit;
 //   2. the contraction runs on the matrix cores: v_mfma 16x16x4 with rows =
 //      the 12 values (padded to 16), columns = the 27 classes (two tiles of 16)
 //      and K = 4 particles per instruction; FP32 sums are formed in blocks of
@@ -25,11 +33,6 @@
 //   3. per-cell sums go to LDS (one writer per entry, no atomics);
 // then, after a workgroup barrier, every (node, entry) of the brick gathers
 // its <= 8 cell contributions and is added to the global J and M once.
-//
-// Particles are grouped by cell ranges (cell_start) that may be stale: a
-// particle whose cell (after the move, in the fused form) is not its range's
-// cell is appended to a stray list. The strays are then counting-sorted by
-// cell and deposited by the same kernel reading them through the list.
 #include "internal.h"
 
 namespace ecsim {
@@ -37,12 +40,12 @@ namespace ecsim {
 namespace {
 
 constexpr int kMaxTiledSpecies = 4;
+constexpr int kStraySlot = kMaxTiledSpecies;  // range slot of the sorted stray list
+constexpr int kSlots5 = kMaxTiledSpecies + 1;
 constexpr int kItemShift = 28;              // stray item = species << 28 | particle index
-constexpr int kUnmoved = 1 << 30;           // flag: listed before the move (fused form)
+constexpr int kUnmoved = 1 << 30;           // flag: listed before its move
 constexpr int kIndexMask = (1 << kItemShift) - 1;
 constexpr int SCS = 268;                    // per-cell sums: [27][9] mass-matrix classes, [8][3] currents, pad
-
-enum Mode { kDeposit = 0, kMoveDeposit = 1, kIndirect = 2 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -83,13 +86,13 @@ struct TArgs {
   TSpecies<T> s[kMaxTiledSpecies];
   int ns;
   const T* Bdep;       // magnetic field of the deposit
-  const T* Emove;      // mover fields (fused form)
+  const T* Emove;      // mover fields
   const T* Bmove;
   T dth[3];            // dt / h
   int* stray_count;
   int* stray_item;
   int* stray_cell;
-  const int* ind_start;   // indirect pass: sorted stray list
+  const int* ind_start;   // the stray list sorted by cell: ranges and items
   const int* ind_item;
   double* ke;
 };
@@ -175,26 +178,26 @@ struct PData {       // one particle's inputs, loaded ahead of use
   bool ok;
 };
 
-template <typename T, int MODE>
+// Particle ip of a cell whose particles are the ranges cnt/beg of slots
+// 0..NSLOT-1 in turn (species, then, in the deposit, the sorted stray list).
+template <typename T, int NSLOT>
 __device__ __forceinline__ PData<T> load_particle(const TArgs<T>& args, const TSpecies<T>* lsp, const int* cnt,
                                                   const int* beg, int total, int ip) {
   PData<T> d{};
   d.ok = ip < total;
   if (d.ok) {
-    int s = 0, idx = ip, p;
-    if constexpr (MODE == kIndirect) {
-      const int item = args.ind_item[beg[0] + ip];
+    int s = 0, idx = ip, p = beg[0] + ip;
+#pragma unroll
+    for (int k = 0; k < NSLOT - 1; ++k)
+      if (s == k && idx >= cnt[k]) {   // constant indices only: no private memory
+        idx -= cnt[k];
+        s = k + 1;
+        p = beg[k + 1] + idx;
+      }
+    if (NSLOT > kStraySlot && s == kStraySlot) {
+      const int item = args.ind_item[p];
       s = (item >> kItemShift) & (kMaxTiledSpecies - 1);
       p = item & kIndexMask;
-    } else {
-      p = beg[0] + idx;
-#pragma unroll
-      for (int k = 0; k < kMaxTiledSpecies - 1; ++k)
-        if (s == k && idx >= cnt[k]) {   // constant indices only: no private memory
-          idx -= cnt[k];
-          s = k + 1;
-          p = beg[k + 1] + idx;
-        }
     }
     const TSpecies<T>& sp = lsp[s];   // LDS copy: a lane-dependent species costs no memory round trip
     d.s = s;
@@ -251,56 +254,69 @@ __host__ __device__ constexpr int pair_class(int k, int a) {
              : (2 * (a & 1) + koff(k, 0)) + 3 * (2 * ((a >> 1) & 1) + koff(k, 1)) + 9 * (2 * ((a >> 2) & 1) + koff(k, 2));
 }
 
-// One half-wavefront's cell of a pair (local index lc in the brick).
-struct PairCell {
+// A cell of a brick (local index lc).
+struct BrickCell {
   int lc, cell, cx, cy, cz;
   bool valid;
 };
 
 template <int TX, int TY, int TZ>
-__device__ __forceinline__ PairCell pair_cell(const Grid& g, int x0, int y0, int z0, int pair, int half) {
-  PairCell c;
-  c.lc = 2 * pair + half;
-  c.cx = x0 + c.lc % TX;
-  c.cy = y0 + (c.lc / TX) % TY;
-  c.cz = z0 + c.lc / (TX * TY);
-  c.valid = c.lc < TX * TY * TZ && c.cx < g.nx && c.cy < g.ny && c.cz < g.nz;
+__device__ __forceinline__ BrickCell brick_cell(const Grid& g, int x0, int y0, int z0, int lc) {
+  BrickCell c;
+  c.lc = lc;
+  c.cx = x0 + lc % TX;
+  c.cy = y0 + (lc / TX) % TY;
+  c.cz = z0 + lc / (TX * TY);
+  c.valid = lc < TX * TY * TZ && c.cx < g.nx && c.cy < g.ny && c.cz < g.nz;
   c.cell = c.valid ? c.cx + g.nx * (c.cy + g.ny * c.cz) : -1;
   return c;
 }
 
-// cell range loads, issued one pair ahead of their use
+// Brick origin of workgroup blockIdx.x; blocks are spread so that each XCD
+// gets contiguous bricks.
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ void brick_origin(int ntx, int nty, int ntz, int& x0, int& y0, int& z0) {
+  const int ntiles = ntx * nty * ntz;
+  int b = blockIdx.x;
+  constexpr int nxcd = 8;
+  const int per = ntiles / nxcd;
+  if (per * nxcd == ntiles) b = (b % nxcd) * per + b / nxcd;
+  x0 = (b % ntx) * TX;
+  y0 = ((b / ntx) % nty) * TY;
+  z0 = (b / (ntx * nty)) * TZ;
+}
+
+// cell range loads, issued one cell (pair) ahead of their use
 struct RangeLd {
-  int lo[kMaxTiledSpecies], hi[kMaxTiledSpecies];
+  int lo[kSlots5], hi[kSlots5];
 };
 struct Ranges {
-  int cnt[kMaxTiledSpecies], beg[kMaxTiledSpecies], total;
+  int cnt[kSlots5], beg[kSlots5], total;
 };
 
-template <typename T, int MODE>
-__device__ __forceinline__ RangeLd load_ranges(const TArgs<T>& args, const TSpecies<T>* lsp, const PairCell& c) {
+template <typename T, int NSLOT>
+__device__ __forceinline__ RangeLd load_ranges(const TArgs<T>& args, const TSpecies<T>* lsp, const BrickCell& c) {
   RangeLd r{};
   const int cl = c.valid ? c.cell : 0;
-  if constexpr (MODE == kIndirect) {
-    r.lo[0] = args.ind_start[cl];
-    r.hi[0] = args.ind_start[cl + 1];
-  } else {
 #pragma unroll
-    for (int s = 0; s < kMaxTiledSpecies; ++s) {
-      const int32_t* cs = lsp[s].cell_start;   // unused species alias species 0
-      r.lo[s] = cs[cl];
-      r.hi[s] = cs[cl + 1];
-    }
+  for (int s = 0; s < kMaxTiledSpecies; ++s) {
+    const int32_t* cs = lsp[s].cell_start;   // unused species alias species 0
+    r.lo[s] = cs[cl];
+    r.hi[s] = cs[cl + 1];
+  }
+  if constexpr (NSLOT > kStraySlot) {
+    r.lo[kStraySlot] = args.ind_start[cl];
+    r.hi[kStraySlot] = args.ind_start[cl + 1];
   }
   return r;
 }
 
-template <typename T, int MODE>
-__device__ __forceinline__ Ranges make_ranges(const TArgs<T>& args, const RangeLd& r, const PairCell& c) {
+template <typename T, int NSLOT>
+__device__ __forceinline__ Ranges make_ranges(const TArgs<T>& args, const RangeLd& r, const BrickCell& c) {
   Ranges q{};
 #pragma unroll
-  for (int s = 0; s < kMaxTiledSpecies; ++s) {
-    const bool used = MODE == kIndirect ? s == 0 : s < args.ns;
+  for (int s = 0; s < NSLOT; ++s) {
+    const bool used = s == kStraySlot || s < args.ns;
     q.beg[s] = r.lo[s];
     q.cnt[s] = (c.valid && used) ? r.hi[s] - r.lo[s] : 0;
     q.total += q.cnt[s];
@@ -308,31 +324,17 @@ __device__ __forceinline__ Ranges make_ranges(const TArgs<T>& args, const RangeL
   return q;
 }
 
-// corner fields of a cell: lane hl < 24 holds component hl / 8 at corner hl % 8
+// corner nodes of a cell
 template <typename T>
-struct StageLd {
-  T b, e, m;
-};
-
-template <typename T, int MODE>
-__device__ __forceinline__ StageLd<T> load_stage(const Grid& g, const TArgs<T>& args, const PairCell& c, int hl) {
-  StageLd<T> r{};
-  if (hl < 24) {
-    Stencil<T> st{};
-    st.i[0] = c.valid ? c.cx : 0;
-    st.i[1] = c.valid ? c.cy : 0;
-    st.i[2] = c.valid ? c.cz : 0;
-    st.ip[0] = wrap_up(st.i[0], g.nx);
-    st.ip[1] = wrap_up(st.i[1], g.ny);
-    st.ip[2] = wrap_up(st.i[2], g.nz);
-    const int64_t nd = (hl >> 3) * g.nn + corner_node(g, st, hl & 7);
-    r.b = args.Bdep[nd];
-    if constexpr (MODE == kMoveDeposit) {
-      r.e = args.Emove[nd];
-      r.m = args.Bmove[nd];
-    }
-  }
-  return r;
+__device__ __forceinline__ Stencil<T> cell_stencil(const Grid& g, const BrickCell& c) {
+  Stencil<T> st{};
+  st.i[0] = c.valid ? c.cx : 0;
+  st.i[1] = c.valid ? c.cy : 0;
+  st.i[2] = c.valid ? c.cz : 0;
+  st.ip[0] = wrap_up(st.i[0], g.nx);
+  st.ip[1] = wrap_up(st.i[1], g.ny);
+  st.ip[2] = wrap_up(st.i[2], g.nz);
+  return st;
 }
 
 // A particle's record: the 12 values ((q beta / V) alpha, (q / V) alpha v)
@@ -361,6 +363,59 @@ __device__ __forceinline__ void particle_record(const Stencil<T>& ps, const Vec3
   for (int c = 0; c < 27; ++c) r[12 + c] = (f[0][c % 3] * f[1][(c / 3) % 3]) * f[2][c / 9];
 }
 
+// Every (entry, node) of the brick at (x0, y0, z0) gathers its <= 8 cell
+// contributions from the per-cell sums and is added to the global J and M
+// once (entries that are exactly zero are skipped).
+template <typename T, int TX, int TY, int TZ>
+__device__ __forceinline__ void flush_brick(const Grid& g, const T* scell, int x0, int y0, int z0, T* __restrict__ J,
+                                            T* __restrict__ M, int tid, int nthr) {
+  constexpr int NX = TX + 1, NY = TY + 1, NZ = TZ + 1, NN = NX * NY * NZ;
+  // items: (ij, node) for the mass matrix, then (component, node) for J
+  constexpr int NITEM = 9 * NN + 3 * NN;
+  for (int it = tid; it < NITEM; it += nthr) {
+    const bool is_m = it < 9 * NN;
+    const int ln = is_m ? it % NN : (it - 9 * NN) % NN;
+    const int sub = is_m ? it / NN : (it - 9 * NN) / NN;   // ij, or the current component
+    const int nx_ = ln % NX, ny_ = (ln / NX) % NY, nz_ = ln / (NX * NY);
+    // cells n - a that exist in this brick
+    int vmask = 0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int lcx = nx_ - (a & 1), lcy = ny_ - ((a >> 1) & 1), lcz = nz_ - ((a >> 2) & 1);
+      if (lcx >= 0 && lcx < TX && lcy >= 0 && lcy < TY && lcz >= 0 && lcz < TZ) vmask |= 1 << a;
+    }
+    const int cbase = nx_ + TX * (ny_ + TY * nz_);          // cell index of n (may lie outside)
+    const int gx = (x0 + nx_) % g.nx, gy = (y0 + ny_) % g.ny, gz = (z0 + nz_) % g.nz;
+    const int64_t gn = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
+    if (is_m) {
+#pragma unroll
+      for (int k = 0; k < 14; ++k) {
+        T v = T(0);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const int cls = pair_class(k, a);
+          if (cls < 0) continue;
+          if (vmask & (1 << a)) {
+            const int cidx = cbase - ((a & 1) + TX * (((a >> 1) & 1) + TY * ((a >> 2) & 1)));
+            v += scell[cidx * SCS + cls * 9 + sub];
+          }
+        }
+        if (v != T(0)) unsafeAtomicAdd(M + (int64_t)(k * 9 + sub) * g.nn + gn, v);
+      }
+    } else {
+      T v = T(0);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        if (vmask & (1 << a)) {
+          const int cidx = cbase - ((a & 1) + TX * (((a >> 1) & 1) + TY * ((a >> 2) & 1)));
+          v += scell[cidx * SCS + 243 + 3 * a + sub];
+        }
+      }
+      if (v != T(0)) unsafeAtomicAdd(J + (int64_t)sub * g.nn + gn, v);
+    }
+  }
+}
+
 // Records in LDS are stored transposed, rec[row][slot] with a row stride of
 // 66 slots (64 particles + 2): the MFMA operand reads of 16 lanes with
 // consecutive rows and 2 lane groups then hit 32 different banks. Rows 39-43
@@ -368,24 +423,190 @@ __device__ __forceinline__ void particle_record(const Stencil<T>& ps, const Vec3
 // (during phase 1) and the current class sums (during phase 3).
 constexpr int kSlots = 66;
 constexpr int kRows = 44;
-constexpr int kStage = 39 * kSlots;        // [2 cells][72]: deposit B, mover E, mover B (24 each)
+constexpr int kStage = 39 * kSlots;        // [2 cells][24]: deposit B at the corners
 constexpr int kTcur = 39 * kSlots;         // [2 cells][84]: current class sums (phase 3 only)
 
-template <typename T, int TX, int TY, int TZ, int NW, int MODE>
-__global__ void __launch_bounds__(NW * 64) k_tiled(Grid g, TArgs<T> args, int ntx, int nty, int ntz,
-                                                   T* __restrict__ J, T* __restrict__ M) {
+
+// ---------------------------------------------------------------------------
+// grouped pass over the cell ranges: with MOVE the mover, else a check
+// ---------------------------------------------------------------------------
+// Wavefront w of a workgroup takes cells w, w + NW, ... of the brick, 64
+// particles at a time; the next cell's ranges and corner fields and then its
+// first particle block are loaded while a cell is processed. With MOVE a
+// particle in its range's cell is moved with the staged E^{n+theta}, B^n
+// (the same gathers, rotation and push as everywhere else) and written back;
+// one already outside the cell is listed unmoved; one that leaves the cell is
+// listed with its new cell. Without MOVE a particle outside its range's cell
+// is listed with its cell.
+template <typename T, int TX, int TY, int TZ, int NW, bool MOVE>
+__global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
+  constexpr int NCELL = TX * TY * TZ;
+  __shared__ T stage_all[NW][48];
+  __shared__ double red[NW];
+  __shared__ int wst[NW];
+  __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  int x0, y0, z0;
+  brick_origin<TX, TY, TZ>(ntx, nty, ntz, x0, y0, z0);
+  if (tid < kMaxTiledSpecies) lsp[tid] = args.s[tid < args.ns ? tid : 0];
+  __syncthreads();
+  T* const stage = stage_all[wave];
+  double kel = 0.0;
+  StrayBuf sb;
+
+  // lanes 0..47 stage field lane / 24 (E, B), component (lane / 8) % 3, corner lane % 8
+  auto load_stage = [&](const BrickCell& c) -> T {
+    T r = T(0);
+    if (MOVE && lane < 48) {
+      const Stencil<T> st = cell_stencil<T>(g, c);
+      const int64_t nd = ((lane >> 3) % 3) * g.nn + corner_node(g, st, lane & 7);
+      r = lane < 24 ? args.Emove[nd] : args.Bmove[nd];
+    }
+    return r;
+  };
+
+  BrickCell cc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, wave);
+  T sv = load_stage(cc);
+  Ranges rg = make_ranges<T, kMaxTiledSpecies>(args, load_ranges<T, kMaxTiledSpecies>(args, lsp, cc), cc);
+  PData<T> pd = load_particle<T, kMaxTiledSpecies>(args, lsp, rg.cnt, rg.beg, rg.total, lane);
+
+  for (int lc = wave; lc < NCELL; lc += NW) {
+    const bool has_next = lc + NW < NCELL;   // wave-uniform
+    const BrickCell nc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, has_next ? lc + NW : lc);
+    RangeLd nrl{};
+    T nsv = T(0);
+    if (has_next) {
+      nrl = load_ranges<T, kMaxTiledSpecies>(args, lsp, nc);
+      nsv = load_stage(nc);
+    }
+    const Ranges cr = rg;
+    const int cell = cc.cell;
+    const int total = __builtin_amdgcn_readfirstlane(cr.total);
+    if (MOVE && total > 0) {
+      if (lane < 48) stage[lane] = sv;
+      wave_sync();
+    }
+    for (int ch = 0; ch < total; ch += 64) {
+      const TSpecies<T>& sp = lsp[pd.s];
+      Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
+      const int pcell0 = ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]);
+      const bool here = pd.ok && pcell0 == cell;
+      int pcell = pcell0;
+      Vec3<T> v{pd.v0, pd.v1, pd.v2};
+      T mx0 = T(0), mx1 = T(0), mx2 = T(0);
+      if constexpr (MOVE) {
+        T W[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
+        const Vec3<T> Ep = gather_staged(W, stage);
+        const Vec3<T> Bp = gather_staged(W, stage + 24);
+        T a0[9];
+        rotation(Bp, sp.beta, a0);
+        Vec3<T> u;
+        v = velocity_update(a0, v, Ep, sp.beta, u);
+        if constexpr (sizeof(T) == 4) {
+          int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
+          mx0 = push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx);
+          mx1 = push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny);
+          mx2 = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
+          pcell = ix + g.nx * (iy + g.ny * iz);
+        } else {
+          mx0 = push_abs(pd.x0, g.dt, v.x, g.nx * g.hx);
+          mx1 = push_abs(pd.x1, g.dt, v.y, g.ny * g.hy);
+          mx2 = push_abs(pd.x2, g.dt, v.z, g.nz * g.hz);
+          const Stencil<T> nps = stencil_abs(g, mx0, mx1, mx2);
+          pcell = nps.i[0] + g.nx * (nps.i[1] + g.ny * nps.i[2]);
+        }
+        if (args.ke && here) {
+          const double vx = v.x, vy = v.y, vz = v.z;
+          kel += 0.5 * ((double)pd.q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz);
+        }
+      }
+      // listed: outside the range's cell before the move (unmoved, with the
+      // range's cell), or after it (with its new cell)
+      const bool stray = pd.ok && !(here && pcell == cell);
+      const int item = (pd.s << kItemShift) | pd.p | ((MOVE && !here) ? kUnmoved : 0);
+      if (__ballot(stray && sb.n == 2)) sb.flush(args, lane);
+      if (stray) sb.push(item, here ? pcell : (MOVE ? cell : pcell0));
+      // prefetch the next block (of this cell, else of the next cell) before
+      // the write-back, so that waiting for the loads does not wait for stores
+      const int ms = pd.s, mp = pd.p;
+      if (ch + 64 < total) {
+        pd = load_particle<T, kMaxTiledSpecies>(args, lsp, cr.cnt, cr.beg, cr.total, ch + 64 + lane);
+      } else if (has_next) {
+        rg = make_ranges<T, kMaxTiledSpecies>(args, nrl, nc);
+        pd = load_particle<T, kMaxTiledSpecies>(args, lsp, rg.cnt, rg.beg, rg.total, lane);
+      }
+      if constexpr (MOVE) {
+        if (here) {
+          const TSpecies<T>& spm = lsp[ms];
+          gst(spm.vel[0] + mp, v.x);
+          gst(spm.vel[1] + mp, v.y);
+          gst(spm.vel[2] + mp, v.z);
+          gst(spm.pos[0] + mp, mx0);
+          gst(spm.pos[1] + mp, mx1);
+          gst(spm.pos[2] + mp, mx2);
+          if constexpr (sizeof(T) == 4) gst(spm.cell + mp, pcell);
+        }
+      }
+    }
+    if (total == 0 && has_next) {
+      rg = make_ranges<T, kMaxTiledSpecies>(args, nrl, nc);
+      pd = load_particle<T, kMaxTiledSpecies>(args, lsp, rg.cnt, rg.beg, rg.total, lane);
+    }
+    if (MOVE) wave_sync();   // the stage is rewritten for the next cell
+    cc = nc;
+    sv = nsv;
+  }
+  if constexpr (MOVE) {
+    if (args.ke) {
+      for (int off = 32; off > 0; off >>= 1) kel += __shfl_down(kel, off);
+      if (lane == 0) red[wave] = kel;
+    }
+  }
+  // the strays still held take one reservation of the workgroup in the list
+  const bool k0 = sb.n >= 1, k1 = sb.n >= 2;
+  const int wtot = __popcll(__ballot(k0)) + __popcll(__ballot(k1));
+  if (lane == 0) wst[wave] = wtot;
+  __syncthreads();
+  if (tid == 0) {
+    int tot = 0;
+    for (int w = 0; w < NW; ++w) tot += wst[w];
+    int base = tot ? atomicAdd(args.stray_count, tot) : 0;
+    for (int w = 0; w < NW; ++w) {
+      const int c = wst[w];
+      wst[w] = base;
+      base += c;
+    }
+    if constexpr (MOVE) {
+      if (args.ke) {
+        double s = 0.0;
+        for (int w = 0; w < NW; ++w) s += red[w];
+        if (s != 0.0) unsafeAtomicAdd(args.ke, s);
+      }
+    }
+  }
+  __syncthreads();
+  write_strays(args, lane, wst[wave], k0, sb.item0, sb.cell0, k1, sb.item1, sb.cell1);
+}
+
+// ---------------------------------------------------------------------------
+// tiled deposit
+// ---------------------------------------------------------------------------
+template <typename T, int TX, int TY, int TZ, int NW>
+__global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz,
+                                                     T* __restrict__ J, T* __restrict__ M) {
   using MF = Mfma<T>;
   using acc_t = typename MF::acc;
-  constexpr int NX = TX + 1, NY = TY + 1, NZ = TZ + 1, NN = NX * NY * NZ;
   constexpr int NCELL = TX * TY * TZ;
   constexpr int NPAIR = (NCELL + 1) / 2;
   constexpr int WREC = kRows * kSlots;
   // one LDS block: the wavefront records first (so that their offsets fit the
   // 16-bit immediate of ds_read), then the per-cell sums
   __shared__ __attribute__((aligned(16))) T smem[NW * WREC + NCELL * SCS];
-  __shared__ double red[NW];
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
-  __shared__ int wst[NW];
   T* const scell = smem + NW * WREC;
 
   const int tid = threadIdx.x;
@@ -395,30 +616,8 @@ __global__ void __launch_bounds__(NW * 64) k_tiled(Grid g, TArgs<T> args, int nt
   const int hl = lane & 31;
   const int col = lane & 15;                    // MFMA column (class) of this lane
   const int grp = lane >> 4;                    // MFMA k-group of this lane
-
-  // tile coordinates; blocks are spread so that each XCD gets contiguous tiles
-  const int ntiles = ntx * nty * ntz;
-  int b = blockIdx.x;
-  {
-    constexpr int nxcd = 8;
-    const int per = ntiles / nxcd;
-    if (per * nxcd == ntiles) b = (b % nxcd) * per + b / nxcd;
-  }
-  const int tx = b % ntx, ty = (b / ntx) % nty, tz = b / (ntx * nty);
-  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
-
-  if constexpr (MODE == kIndirect) {
-    // most bricks hold no stray: leave at once
-    int any = 0;
-    for (int lc = tid; lc < NCELL; lc += NW * 64) {
-      const int cx = x0 + lc % TX, cy = y0 + (lc / TX) % TY, cz = z0 + lc / (TX * TY);
-      if (cx < g.nx && cy < g.ny && cz < g.nz) {
-        const int64_t c = cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz);
-        any |= args.ind_start[c + 1] > args.ind_start[c];
-      }
-    }
-    if (!__syncthreads_or(any)) return;
-  }
+  int x0, y0, z0;
+  brick_origin<TX, TY, TZ>(ntx, nty, ntz, x0, y0, z0);
 
   for (int i = tid; i < NCELL * SCS; i += NW * 64) scell[i] = T(0);
   for (int i = tid; i < NW * WREC; i += NW * 64) smem[i] = T(0);
@@ -428,25 +627,32 @@ __global__ void __launch_bounds__(NW * 64) k_tiled(Grid g, TArgs<T> args, int nt
   T* const wrec = smem + wave * WREC;
   // this lane's MFMA operand base: row col, slot grp (cell A) / 32 + grp (cell B)
   const T* const opnd = wrec + col * kSlots + grp;
-  T* const stage = wrec + kStage + 72 * half;
-  double kel = 0.0;
-  StrayBuf sb;
+  T* const stage = wrec + kStage + 24 * half;
+  // lanes 0..23 of each half stage component hl / 8 of B at corner hl % 8
+  auto load_stage = [&](const BrickCell& c) -> T {
+    T r = T(0);
+    if (hl < 24) {
+      const Stencil<T> st = cell_stencil<T>(g, c);
+      r = args.Bdep[(hl >> 3) * g.nn + corner_node(g, st, hl & 7)];
+    }
+    return r;
+  };
 
   // Pair pipeline: while a pair of cells is processed, the next pair's cell
   // ranges and corner fields, and then its first particle block, are loaded.
-  PairCell pc = pair_cell<TX, TY, TZ>(g, x0, y0, z0, wave, half);
-  StageLd<T> sl = load_stage<T, MODE>(g, args, pc, hl);
-  Ranges rg = make_ranges<T, MODE>(args, load_ranges<T, MODE>(args, lsp, pc), pc);
-  PData<T> pd = load_particle<T, MODE>(args, lsp, rg.cnt, rg.beg, rg.total, hl);
+  BrickCell pc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, 2 * wave + half);
+  T sv = load_stage(pc);
+  Ranges rg = make_ranges<T, kSlots5>(args, load_ranges<T, kSlots5>(args, lsp, pc), pc);
+  PData<T> pd = load_particle<T, kSlots5>(args, lsp, rg.cnt, rg.beg, rg.total, hl);
 
   for (int pair = wave; pair < NPAIR; pair += NW) {
     const bool has_next = pair + NW < NPAIR;   // wave-uniform
-    const PairCell nc = pair_cell<TX, TY, TZ>(g, x0, y0, z0, has_next ? pair + NW : pair, half);
+    const BrickCell nc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, 2 * (has_next ? pair + NW : pair) + half);
     RangeLd nrl{};
-    StageLd<T> nsl{};
+    T nsv = T(0);
     if (has_next) {
-      nrl = load_ranges<T, MODE>(args, lsp, nc);
-      nsl = load_stage<T, MODE>(g, args, nc, hl);
+      nrl = load_ranges<T, kSlots5>(args, lsp, nc);
+      nsv = load_stage(nc);
     }
     const Ranges cr = rg;
     const int lc = pc.lc;
@@ -456,21 +662,15 @@ __global__ void __launch_bounds__(NW * 64) k_tiled(Grid g, TArgs<T> args, int nt
     const int cmax = cntA > cntB ? cntA : cntB;
     if (cmax == 0) {   // wave-uniform: both cells empty
       if (has_next) {
-        rg = make_ranges<T, MODE>(args, nrl, nc);
-        pd = load_particle<T, MODE>(args, lsp, rg.cnt, rg.beg, rg.total, hl);
+        rg = make_ranges<T, kSlots5>(args, nrl, nc);
+        pd = load_particle<T, kSlots5>(args, lsp, rg.cnt, rg.beg, rg.total, hl);
       }
       pc = nc;
-      sl = nsl;
+      sv = nsv;
       continue;
     }
-    // corner fields of the cell, staged for the lanes of this half
-    if (hl < 24) {
-      stage[hl] = sl.b;
-      if constexpr (MODE == kMoveDeposit) {
-        stage[24 + hl] = sl.e;
-        stage[48 + hl] = sl.m;
-      }
-    }
+    // corner B of the cell, staged for the lanes of this half
+    if (hl < 24) stage[hl] = sv;
     wave_sync();
 
     // running sums of the two cells: [cell][tile][reg]
@@ -483,94 +683,30 @@ __global__ void __launch_bounds__(NW * 64) k_tiled(Grid g, TArgs<T> args, int nt
         for (int r = 0; r < 4; ++r) { S[h][t][r] = T(0); C[h][t][r] = T(0); }
 
     for (int ch = 0; ch < cmax; ch += 32) {
-      // ---- 1. particle lanes: (move and) one record column per lane ----
-      // Every lane runs the same arithmetic; lanes whose particle is not
-      // deposited here carry zero charge, so their record values are zero.
-      const TSpecies<T>& sp = lsp[pd.s];
-      Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
-      const int pcell0 = ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]);
-      // in its range's cell: moved (fused form) and deposited with staged fields
-      const bool here = pd.ok && pcell0 == cell;
-      int pcell = pcell0;
-      Vec3<T> v{pd.v0, pd.v1, pd.v2};
-      T mx0 = T(0), mx1 = T(0), mx2 = T(0);
-      if constexpr (MODE == kMoveDeposit) {
-        T W[8];
-#pragma unroll
-        for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
-        const Vec3<T> Ep = gather_staged(W, stage + 24);
-        const Vec3<T> Bp = gather_staged(W, stage + 48);
-        T a0[9];
-        rotation(Bp, sp.beta, a0);
-        Vec3<T> u;
-        v = velocity_update(a0, v, Ep, sp.beta, u);
-        if constexpr (sizeof(T) == 4) {
-          int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
-          const float ox = push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx);
-          const float oy = push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny);
-          const float oz = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
-          pcell = ix + g.nx * (iy + g.ny * iz);
-          mx0 = ox;
-          mx1 = oy;
-          mx2 = oz;
-          ps.i[0] = ix; ps.i[1] = iy; ps.i[2] = iz;
-          ps.ip[0] = wrap_up(ix, g.nx); ps.ip[1] = wrap_up(iy, g.ny); ps.ip[2] = wrap_up(iz, g.nz);
-          ps.w1[0] = ox; ps.w1[1] = oy; ps.w1[2] = oz;
-          ps.w0[0] = 1.0f - ox; ps.w0[1] = 1.0f - oy; ps.w0[2] = 1.0f - oz;
-        } else {
-          mx0 = push_abs(pd.x0, g.dt, v.x, g.nx * g.hx);
-          mx1 = push_abs(pd.x1, g.dt, v.y, g.ny * g.hy);
-          mx2 = push_abs(pd.x2, g.dt, v.z, g.nz * g.hz);
-          ps = stencil_abs(g, mx0, mx1, mx2);
-          pcell = ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]);
-        }
-        if (args.ke && here) {
-          const double vx = v.x, vy = v.y, vz = v.z;
-          kel += 0.5 * ((double)pd.q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz);
-        }
-      }
-      const bool keep = here && pcell == cell;   // deposited by this block
+      // ---- 1. particle lanes: one record column per lane ----
+      // Every lane runs the same arithmetic; lanes whose particle is not in
+      // the cell (or that hold none) carry zero charge, so zero values.
       {
+        const TSpecies<T>& sp = lsp[pd.s];
+        const Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
+        const bool keep = pd.ok && ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]) == cell;
         T W[8];
 #pragma unroll
         for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
         const Vec3<T> B1 = gather_staged(W, stage);
         T r[39];
-        particle_record(ps, B1, v, keep ? pd.q : T(0), sp, r);
+        particle_record(ps, B1, Vec3<T>{pd.v0, pd.v1, pd.v2}, keep ? pd.q : T(0), sp, r);
 #pragma unroll
         for (int i = 0; i < 39; ++i) wrec[i * kSlots + lane] = r[i];
       }
-      if constexpr (MODE != kIndirect) {
-        // Strays wait in two register slots per lane. In the fused form a
-        // particle found outside its range's cell (the grouping is stale) is
-        // listed unmoved, to be moved by the stray mover.
-        const bool stray = pd.ok && !keep;
-        const int item = (pd.s << kItemShift) | pd.p | ((MODE == kMoveDeposit && !here) ? kUnmoved : 0);
-        if (__ballot(stray && sb.n == 2)) sb.flush(args, lane);
-        if (stray) sb.push(item, here ? pcell : pcell0);
-      }
       wave_sync();
       // prefetch the next block (of this pair, else of the next pair) while
-      // this block is reduced; the loads are issued before the write-back so
-      // that waiting for them does not wait for the stores
-      const int ms = pd.s, mp = pd.p;
+      // this block is reduced
       if (ch + 32 < cmax) {
-        pd = load_particle<T, MODE>(args, lsp, cr.cnt, cr.beg, cr.total, ch + 32 + hl);
+        pd = load_particle<T, kSlots5>(args, lsp, cr.cnt, cr.beg, cr.total, ch + 32 + hl);
       } else if (has_next) {
-        rg = make_ranges<T, MODE>(args, nrl, nc);
-        pd = load_particle<T, MODE>(args, lsp, rg.cnt, rg.beg, rg.total, hl);
-      }
-      if constexpr (MODE == kMoveDeposit) {
-        if (here) {
-          const TSpecies<T>& spm = lsp[ms];
-          gst(spm.vel[0] + mp, v.x);
-          gst(spm.vel[1] + mp, v.y);
-          gst(spm.vel[2] + mp, v.z);
-          gst(spm.pos[0] + mp, mx0);
-          gst(spm.pos[1] + mp, mx1);
-          gst(spm.pos[2] + mp, mx2);
-          if constexpr (sizeof(T) == 4) gst(spm.cell + mp, pcell);
-        }
+        rg = make_ranges<T, kSlots5>(args, nrl, nc);
+        pd = load_particle<T, kSlots5>(args, lsp, rg.cnt, rg.beg, rg.total, hl);
       }
 
       // ---- 2. matrix cores: S[value][class] += sum over 4 particles per step ----
@@ -643,93 +779,16 @@ __global__ void __launch_bounds__(NW * 64) k_tiled(Grid g, TArgs<T> args, int nt
     }
     wave_sync();
     pc = nc;
-    sl = nsl;
-  }
-  if constexpr (MODE == kMoveDeposit) {
-    if (args.ke) {
-      for (int off = 32; off > 0; off >>= 1) kel += __shfl_down(kel, off);
-      if (lane == 0) red[wave] = kel;
-    }
+    sv = nsv;
   }
   __syncthreads();   // the per-cell sums are complete
-  if constexpr (MODE != kIndirect) {
-    // the strays still held take one reservation of the workgroup in the list
-    const bool k0 = sb.n >= 1, k1 = sb.n >= 2;
-    const int wtot = __popcll(__ballot(k0)) + __popcll(__ballot(k1));
-    if (lane == 0) wst[wave] = wtot;
-    __syncthreads();
-    if (tid == 0) {
-      int tot = 0;
-      for (int w = 0; w < NW; ++w) tot += wst[w];
-      int base = tot ? atomicAdd(args.stray_count, tot) : 0;
-      for (int w = 0; w < NW; ++w) {
-        const int c = wst[w];
-        wst[w] = base;
-        base += c;
-      }
-    }
-    __syncthreads();
-    write_strays(args, lane, wst[wave], k0, sb.item0, sb.cell0, k1, sb.item1, sb.cell1);
-  }
-  if constexpr (MODE == kMoveDeposit) {
-    if (args.ke && tid == 0) {
-      double s = 0.0;
-      for (int w = 0; w < NW; ++w) s += red[w];
-      unsafeAtomicAdd(args.ke, s);
-    }
-  }
-
-  // ---- gather every (entry, node) of the brick and add it to J and M ----
-  // items: (ij, node) for the mass matrix, then (component, node) for J
-  constexpr int NITEM = 9 * NN + 3 * NN;
-  for (int it = tid; it < NITEM; it += NW * 64) {
-    const bool is_m = it < 9 * NN;
-    const int ln = is_m ? it % NN : (it - 9 * NN) % NN;
-    const int sub = is_m ? it / NN : (it - 9 * NN) / NN;   // ij, or the current component
-    const int nx_ = ln % NX, ny_ = (ln / NX) % NY, nz_ = ln / (NX * NY);
-    // cells n - a that exist in this brick
-    int vmask = 0;
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int lcx = nx_ - (a & 1), lcy = ny_ - ((a >> 1) & 1), lcz = nz_ - ((a >> 2) & 1);
-      if (lcx >= 0 && lcx < TX && lcy >= 0 && lcy < TY && lcz >= 0 && lcz < TZ) vmask |= 1 << a;
-    }
-    const int cbase = nx_ + TX * (ny_ + TY * nz_);          // cell index of n (may lie outside)
-    const int gx = (x0 + nx_) % g.nx, gy = (y0 + ny_) % g.ny, gz = (z0 + nz_) % g.nz;
-    const int64_t gn = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
-    if (is_m) {
-#pragma unroll
-      for (int k = 0; k < 14; ++k) {
-        T v = T(0);
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          const int cls = pair_class(k, a);
-          if (cls < 0) continue;
-          if (vmask & (1 << a)) {
-            const int cidx = cbase - ((a & 1) + TX * (((a >> 1) & 1) + TY * ((a >> 2) & 1)));
-            v += scell[cidx * SCS + cls * 9 + sub];
-          }
-        }
-        if (v != T(0)) unsafeAtomicAdd(M + (int64_t)(k * 9 + sub) * g.nn + gn, v);
-      }
-    } else {
-      T v = T(0);
-#pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        if (vmask & (1 << a)) {
-          const int cidx = cbase - ((a & 1) + TX * (((a >> 1) & 1) + TY * ((a >> 2) & 1)));
-          v += scell[cidx * SCS + 243 + 3 * a + sub];
-        }
-      }
-      if (v != T(0)) unsafeAtomicAdd(J + (int64_t)sub * g.nn + gn, v);
-    }
-  }
+  flush_brick<T, TX, TY, TZ>(g, scell, x0, y0, z0, J, M, tid, NW * 64);
 }
 
 // ---------------------------------------------------------------------------
-// stray mover (fused form): particles listed before their move -- found
-// outside their range's cell -- are moved here with fields read from memory,
-// in the same arithmetic as the tiled kernel, and their new cell recorded.
+// stray mover: particles listed before their move -- found outside their
+// range's cell -- are moved here with fields read from memory, in the same
+// arithmetic as the grouped mover, and their new cell recorded.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
@@ -781,7 +840,10 @@ __global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
     gst(sp.vel[0] + p, v.x);
     gst(sp.vel[1] + p, v.y);
     gst(sp.vel[2] + p, v.z);
-    args.stray_cell[i] = ncell;
+    // back in its range's cell: the deposit takes it from the range, so it
+    // leaves the list (cell -1)
+    const int range_cell = args.stray_cell[i];
+    args.stray_cell[i] = ncell == range_cell ? -1 : ncell;
     args.stray_item[i] = item & ~kUnmoved;
     if (args.ke) {
       const double vx = v.x, vy = v.y, vz = v.z;
@@ -808,8 +870,8 @@ __global__ void __launch_bounds__(256) k_stray_rank(const int* __restrict__ coun
   const int lane = threadIdx.x & 63;
   for (int base = blockIdx.x * 256; base < n; base += gridDim.x * 256) {
     const int i = base + threadIdx.x;
-    const bool active = i < n;
-    const int key = active ? cellv[i] : -1;
+    const int key = i < n ? cellv[i] : -1;
+    const bool active = key >= 0;   // entries with cell -1 have left the list
     unsigned long long pending = __ballot(active);
     int my_rank = 0;
     while (pending) {
@@ -830,8 +892,10 @@ __global__ void __launch_bounds__(256) k_stray_scatter(const int* __restrict__ c
                                                        const int* __restrict__ ranks, const int* __restrict__ start,
                                                        const int* __restrict__ item, int* __restrict__ sorted) {
   const int n = *count;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
-    sorted[start[cellv[i]] + ranks[i]] = item[i];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const int c = cellv[i];
+    if (c >= 0) sorted[start[c] + ranks[i]] = item[i];
+  }
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -892,6 +956,7 @@ TArgs<T> make_args(const Grid& g, const SpeciesArgs* sp, int ns) {
   return a;
 }
 
+// grouped pass (move or check) -> [stray mover] -> stray counting sort -> deposit
 template <typename T, int TX, int TY, int TZ, int NW>
 hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove, const void* Bmove,
                  const void* Bdep, void* J, void* M, double* ke, bool move, void* ws, hipStream_t st) {
@@ -910,18 +975,18 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
   a.stray_item = w.item;
   a.stray_cell = w.cell;
   a.ke = ke;
-  if (move)
-    hipLaunchKernelGGL((k_tiled<T, TX, TY, TZ, NW, kMoveDeposit>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx,
-                       nty, ntz, (T*)J, (T*)M);
-  else
-    hipLaunchKernelGGL((k_tiled<T, TX, TY, TZ, NW, kDeposit>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty,
-                       ntz, (T*)J, (T*)M);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  constexpr int kGroupWaves = 4;   // 4-wave workgroups: three fit a CU at the mover's register count
   if (move) {
-    hipLaunchKernelGGL(k_move_strays<T>, dim3(1024), dim3(256), 0, st, g, a);
+    hipLaunchKernelGGL((k_group<T, TX, TY, TZ, kGroupWaves, true>), dim3(ntiles), dim3(kGroupWaves * 64), 0, st, g,
+                       a, ntx, nty, ntz);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_move_strays<T>, dim3(1024), dim3(256), 0, st, g, a);
+  } else {
+    hipLaunchKernelGGL((k_group<T, TX, TY, TZ, kGroupWaves, false>), dim3(ntiles), dim3(kGroupWaves * 64), 0, st, g,
+                       a, ntx, nty, ntz);
   }
-  // strays: counting sort by cell, then the indirect pass
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // strays: counting sort by cell
   if ((e = launch_zero(w.counts, sizeof(int) * (size_t)g.nn, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_stray_rank, dim3(1024), dim3(256), 0, st, (const int*)w.count, (const int*)w.cell, w.counts,
                      w.rank);
@@ -932,8 +997,8 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
   if ((e = hipGetLastError()) != hipSuccess) return e;
   a.ind_start = w.start;
   a.ind_item = w.sorted;
-  hipLaunchKernelGGL((k_tiled<T, TX, TY, TZ, NW, kIndirect>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty,
-                     ntz, (T*)J, (T*)M);
+  hipLaunchKernelGGL((k_deposit<T, TX, TY, TZ, NW>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty, ntz,
+                     (T*)J, (T*)M);
   return hipGetLastError();
 }
 
