@@ -430,18 +430,27 @@ constexpr int kTcur = 39 * kSlots;         // [2 cells][84]: current class sums 
 // ---------------------------------------------------------------------------
 // grouped pass over the cell ranges: with MOVE the mover, else a check
 // ---------------------------------------------------------------------------
-// Wavefront w of a workgroup takes cells w, w + NW, ... of the brick, 64
-// particles at a time; the next cell's ranges and corner fields and then its
-// first particle block are loaded while a cell is processed. With MOVE a
-// particle in its range's cell is moved with the staged E^{n+theta}, B^n
-// (the same gathers, rotation and push as everywhere else) and written back;
-// one already outside the cell is listed unmoved; one that leaves the cell is
-// listed with its new cell. Without MOVE a particle outside its range's cell
-// is listed with its cell.
+// A workgroup owns a brick of TX x TY x TZ cells. It stages the mover fields
+// E^{n+theta}, B^n on the brick's nodes plus a one-cell halo in LDS, then its
+// wavefronts run through the brick's particles -- the species ranges of its
+// cells, taken as one list -- 64 at a time, the next block's loads issued
+// before the current block is computed. With MOVE a particle whose cell lies
+// in the halo'd box is moved with the staged fields (the same gathers,
+// rotation and push as everywhere else) and written back, and listed if it
+// is now outside its range's cell; a particle beyond the box is listed
+// unmoved (with its range's cell) for the stray mover. Without MOVE a
+// particle outside its range's cell is listed with its cell.
 template <typename T, int TX, int TY, int TZ, int NW, bool MOVE>
 __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   constexpr int NCELL = TX * TY * TZ;
-  __shared__ T stage_all[NW][48];
+  constexpr int HX = TX + 3, HY = TY + 3, HZ = TZ + 3, HN = HX * HY * HZ;   // halo'd node box
+  constexpr int NR = NCELL * kMaxTiledSpecies;                            // ranges: cell-major
+  constexpr int NT = NW * 64;
+  static_assert(NR <= NT, "one range per thread");
+  __shared__ T fld[MOVE ? 6 * HN : 1];
+  __shared__ int rbeg[NR];
+  __shared__ int roff[NR + 1];
+  __shared__ int wsum[NW];
   __shared__ double red[NW];
   __shared__ int wst[NW];
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
@@ -451,114 +460,155 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
   int x0, y0, z0;
   brick_origin<TX, TY, TZ>(ntx, nty, ntz, x0, y0, z0);
   if (tid < kMaxTiledSpecies) lsp[tid] = args.s[tid < args.ns ? tid : 0];
+  // range r = (cell lc = r / 4, species r % 4): start, and the flat offsets
+  int n = 0;
+  if (tid < NR) {
+    const int s = tid % kMaxTiledSpecies;
+    const BrickCell c = brick_cell<TX, TY, TZ>(g, x0, y0, z0, tid / kMaxTiledSpecies);
+    int b0 = 0;
+    if (c.valid && s < args.ns) {
+      const int32_t* cs = args.s[s].cell_start;
+      b0 = cs[c.cell];
+      n = cs[c.cell + 1] - b0;
+    }
+    rbeg[tid] = b0;
+  }
+  int incl = n;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  if constexpr (MOVE) {
+    for (int i = tid; i < 6 * HN; i += NT) {
+      const int f = i / HN, nl = i % HN;
+      const int gx = ((x0 - 1 + nl % HX) % g.nx + g.nx) % g.nx;
+      const int gy = ((y0 - 1 + (nl / HX) % HY) % g.ny + g.ny) % g.ny;
+      const int gz = ((z0 - 1 + nl / (HX * HY)) % g.nz + g.nz) % g.nz;
+      const int64_t gn = (f % 3) * g.nn + gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
+      fld[i] = f < 3 ? args.Emove[gn] : args.Bmove[gn];
+    }
+  }
   __syncthreads();
-  T* const stage = stage_all[wave];
+  {
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    if (tid < NR) roff[tid] = before + incl - n;
+    if (tid == NR - 1) roff[NR] = before + incl;
+  }
+  __syncthreads();
+  const int total = roff[NR];
   double kel = 0.0;
   StrayBuf sb;
 
-  // lanes 0..47 stage field lane / 24 (E, B), component (lane / 8) % 3, corner lane % 8
-  auto load_stage = [&](const BrickCell& c) -> T {
-    T r = T(0);
-    if (MOVE && lane < 48) {
-      const Stencil<T> st = cell_stencil<T>(g, c);
-      const int64_t nd = ((lane >> 3) % 3) * g.nn + corner_node(g, st, lane & 7);
-      r = lane < 24 ? args.Emove[nd] : args.Bmove[nd];
+  // flat index i -> (range, particle); the last range with roff <= i is the
+  // non-empty one holding i
+  auto locate = [&](int i, int& r) -> PData<T> {
+    PData<T> d{};
+    d.ok = i < total;
+    r = 0;
+    if (d.ok) {
+      int lo = 0, hi = NR - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (roff[mid] <= i) lo = mid;
+        else hi = mid - 1;
+      }
+      r = lo;
+      const int s = lo % kMaxTiledSpecies;
+      const int p = rbeg[lo] + (i - roff[lo]);
+      const TSpecies<T>& sp = lsp[s];
+      d.s = s;
+      d.p = p;
+      d.x0 = gld(sp.pos[0] + p);
+      d.x1 = gld(sp.pos[1] + p);
+      d.x2 = gld(sp.pos[2] + p);
+      d.v0 = gld(sp.vel[0] + p);
+      d.v1 = gld(sp.vel[1] + p);
+      d.v2 = gld(sp.vel[2] + p);
+      d.q = sp.q ? gld(sp.q + p) : sp.q_const;
+      if constexpr (sizeof(T) == 4) d.c = gld(sp.cell + p);
     }
-    return r;
+    return d;
   };
 
-  BrickCell cc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, wave);
-  T sv = load_stage(cc);
-  Ranges rg = make_ranges<T, kMaxTiledSpecies>(args, load_ranges<T, kMaxTiledSpecies>(args, lsp, cc), cc);
-  PData<T> pd = load_particle<T, kMaxTiledSpecies>(args, lsp, rg.cnt, rg.beg, rg.total, lane);
-
-  for (int lc = wave; lc < NCELL; lc += NW) {
-    const bool has_next = lc + NW < NCELL;   // wave-uniform
-    const BrickCell nc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, has_next ? lc + NW : lc);
-    RangeLd nrl{};
-    T nsv = T(0);
-    if (has_next) {
-      nrl = load_ranges<T, kMaxTiledSpecies>(args, lsp, nc);
-      nsv = load_stage(nc);
-    }
-    const Ranges cr = rg;
-    const int cell = cc.cell;
-    const int total = __builtin_amdgcn_readfirstlane(cr.total);
-    if (MOVE && total > 0) {
-      if (lane < 48) stage[lane] = sv;
-      wave_sync();
-    }
-    for (int ch = 0; ch < total; ch += 64) {
+  int r_cur;
+  PData<T> pd = locate(wave * 64 + lane, r_cur);
+  for (int base = wave * 64; base < total; base += NT) {
+    int r_nxt;
+    const PData<T> pn = locate(base + NT + lane, r_nxt);   // next block, in flight during this one
+    bool stray = false;
+    int item = 0, lcell = 0;
+    if (pd.ok) {
       const TSpecies<T>& sp = lsp[pd.s];
+      const BrickCell gc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, r_cur / kMaxTiledSpecies);
       Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
       const int pcell0 = ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]);
-      const bool here = pd.ok && pcell0 == cell;
-      int pcell = pcell0;
-      Vec3<T> v{pd.v0, pd.v1, pd.v2};
-      T mx0 = T(0), mx1 = T(0), mx2 = T(0);
+      item = (pd.s << kItemShift) | pd.p;
       if constexpr (MOVE) {
-        T W[8];
+        // local cell in the halo'd box (periodic)
+        const int dx = (ps.i[0] - x0 + 1 + g.nx) % g.nx;
+        const int dy = (ps.i[1] - y0 + 1 + g.ny) % g.ny;
+        const int dz = (ps.i[2] - z0 + 1 + g.nz) % g.nz;
+        if (dx <= TX + 1 && dy <= TY + 1 && dz <= TZ + 1) {
+          Vec3<T> Ep{T(0), T(0), T(0)}, Bp{T(0), T(0), T(0)};
 #pragma unroll
-        for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
-        const Vec3<T> Ep = gather_staged(W, stage);
-        const Vec3<T> Bp = gather_staged(W, stage + 24);
-        T a0[9];
-        rotation(Bp, sp.beta, a0);
-        Vec3<T> u;
-        v = velocity_update(a0, v, Ep, sp.beta, u);
-        if constexpr (sizeof(T) == 4) {
-          int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
-          mx0 = push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx);
-          mx1 = push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny);
-          mx2 = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
-          pcell = ix + g.nx * (iy + g.ny * iz);
+          for (int a = 0; a < 8; ++a) {
+            const T w = corner_weight(ps, a);
+            const int nl = (dx + (a & 1)) + HX * ((dy + ((a >> 1) & 1)) + HY * (dz + ((a >> 2) & 1)));
+            Ep.x = fma(w, fld[nl], Ep.x);
+            Ep.y = fma(w, fld[HN + nl], Ep.y);
+            Ep.z = fma(w, fld[2 * HN + nl], Ep.z);
+            Bp.x = fma(w, fld[3 * HN + nl], Bp.x);
+            Bp.y = fma(w, fld[4 * HN + nl], Bp.y);
+            Bp.z = fma(w, fld[5 * HN + nl], Bp.z);
+          }
+          T a0[9];
+          rotation(Bp, sp.beta, a0);
+          Vec3<T> u;
+          const Vec3<T> v = velocity_update(a0, Vec3<T>{pd.v0, pd.v1, pd.v2}, Ep, sp.beta, u);
+          int pcell;
+          if constexpr (sizeof(T) == 4) {
+            int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
+            gst(sp.pos[0] + pd.p, push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx));
+            gst(sp.pos[1] + pd.p, push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny));
+            gst(sp.pos[2] + pd.p, push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz));
+            pcell = ix + g.nx * (iy + g.ny * iz);
+            gst(sp.cell + pd.p, pcell);
+          } else {
+            const double n0 = push_abs(pd.x0, g.dt, v.x, g.nx * g.hx);
+            const double n1 = push_abs(pd.x1, g.dt, v.y, g.ny * g.hy);
+            const double n2 = push_abs(pd.x2, g.dt, v.z, g.nz * g.hz);
+            gst(sp.pos[0] + pd.p, (T)n0);
+            gst(sp.pos[1] + pd.p, (T)n1);
+            gst(sp.pos[2] + pd.p, (T)n2);
+            const Stencil<double> nps = stencil_abs(g, n0, n1, n2);
+            pcell = nps.i[0] + g.nx * (nps.i[1] + g.ny * nps.i[2]);
+          }
+          gst(sp.vel[0] + pd.p, v.x);
+          gst(sp.vel[1] + pd.p, v.y);
+          gst(sp.vel[2] + pd.p, v.z);
+          if (args.ke) {
+            const double vx = v.x, vy = v.y, vz = v.z;
+            kel += 0.5 * ((double)pd.q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz);
+          }
+          stray = pcell != gc.cell;   // the deposit takes the others from the range
+          lcell = pcell;
         } else {
-          mx0 = push_abs(pd.x0, g.dt, v.x, g.nx * g.hx);
-          mx1 = push_abs(pd.x1, g.dt, v.y, g.ny * g.hy);
-          mx2 = push_abs(pd.x2, g.dt, v.z, g.nz * g.hz);
-          const Stencil<T> nps = stencil_abs(g, mx0, mx1, mx2);
-          pcell = nps.i[0] + g.nx * (nps.i[1] + g.ny * nps.i[2]);
+          stray = true;               // beyond the box: moved by the stray mover
+          item |= kUnmoved;
+          lcell = gc.cell;
         }
-        if (args.ke && here) {
-          const double vx = v.x, vy = v.y, vz = v.z;
-          kel += 0.5 * ((double)pd.q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz);
-        }
-      }
-      // listed: outside the range's cell before the move (unmoved, with the
-      // range's cell), or after it (with its new cell)
-      const bool stray = pd.ok && !(here && pcell == cell);
-      const int item = (pd.s << kItemShift) | pd.p | ((MOVE && !here) ? kUnmoved : 0);
-      if (__ballot(stray && sb.n == 2)) sb.flush(args, lane);
-      if (stray) sb.push(item, here ? pcell : (MOVE ? cell : pcell0));
-      // prefetch the next block (of this cell, else of the next cell) before
-      // the write-back, so that waiting for the loads does not wait for stores
-      const int ms = pd.s, mp = pd.p;
-      if (ch + 64 < total) {
-        pd = load_particle<T, kMaxTiledSpecies>(args, lsp, cr.cnt, cr.beg, cr.total, ch + 64 + lane);
-      } else if (has_next) {
-        rg = make_ranges<T, kMaxTiledSpecies>(args, nrl, nc);
-        pd = load_particle<T, kMaxTiledSpecies>(args, lsp, rg.cnt, rg.beg, rg.total, lane);
-      }
-      if constexpr (MOVE) {
-        if (here) {
-          const TSpecies<T>& spm = lsp[ms];
-          gst(spm.vel[0] + mp, v.x);
-          gst(spm.vel[1] + mp, v.y);
-          gst(spm.vel[2] + mp, v.z);
-          gst(spm.pos[0] + mp, mx0);
-          gst(spm.pos[1] + mp, mx1);
-          gst(spm.pos[2] + mp, mx2);
-          if constexpr (sizeof(T) == 4) gst(spm.cell + mp, pcell);
-        }
+      } else {
+        stray = pcell0 != gc.cell;
+        lcell = pcell0;
       }
     }
-    if (total == 0 && has_next) {
-      rg = make_ranges<T, kMaxTiledSpecies>(args, nrl, nc);
-      pd = load_particle<T, kMaxTiledSpecies>(args, lsp, rg.cnt, rg.beg, rg.total, lane);
-    }
-    if (MOVE) wave_sync();   // the stage is rewritten for the next cell
-    cc = nc;
-    sv = nsv;
+    if (__ballot(stray && sb.n == 2)) sb.flush(args, lane);   // a lane needs a third slot
+    if (stray) sb.push(item, lcell);
+    pd = pn;
+    r_cur = r_nxt;
   }
   if constexpr (MOVE) {
     if (args.ke) {
@@ -574,11 +624,11 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
   if (tid == 0) {
     int tot = 0;
     for (int w = 0; w < NW; ++w) tot += wst[w];
-    int base = tot ? atomicAdd(args.stray_count, tot) : 0;
+    int b = tot ? atomicAdd(args.stray_count, tot) : 0;
     for (int w = 0; w < NW; ++w) {
       const int c = wst[w];
-      wst[w] = base;
-      base += c;
+      wst[w] = b;
+      b += c;
     }
     if constexpr (MOVE) {
       if (args.ke) {
