@@ -30,6 +30,24 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes of one FP32 ecsim_move_moments call on the 64^3 workload, from the
+# FETCH_SIZE and WRITE_SIZE passes summarised in the profile named below
+# (scaled by a 1 GiB device copy). Valid only for the kernel sources whose
+# hash is recorded; any change to them makes the figure stale (reported null).
+TRAFFIC = {"sources_sha256": None, "bytes_per_call": None,
+           "profile": "profiles/move_moments_64cubed_fp32.md"}
+
+
+def kernel_sources_sha256():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2603_16624_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -261,6 +279,9 @@ def main():
         kname = "ecsim_move + ecsim_moments (FP32, tiled, stale grouping)"
         kms = r32["kernel_ms"] + r32["moments_ms"]
     achieved = nbytes / (kms * 1e-3) / 1e9
+    traffic = None
+    if args.path == "fused" and TRAFFIC["bytes_per_call"] and TRAFFIC["sources_sha256"] == kernel_sources_sha256():
+        traffic = TRAFFIC["bytes_per_call"]
     keys = ("fields_ms", "kernel_ms", "moments_ms", "sort_ms", "solve_ms", "full_step_ms")
     out = {
         "metric": "particles/s through mover+moments (FP32 vs FP64) at fixed error; % HBM peak",
@@ -290,7 +311,7 @@ def main():
             "value": r64["particles_per_s"], "ms_per_step": r64["pass_ms"], "hbm_frac": r64["hbm_frac_pass"],
             "breakdown_ms": {k: r64[k] for k in keys}},
         "roofline": {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": nbytes, "launch_ms": kms},
         "cpu_baseline": cpu,
     }

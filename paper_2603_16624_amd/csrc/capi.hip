@@ -105,7 +105,7 @@ ecsim_status ecsim_workspace_size(const ecsim_grid* grid, int64_t np, int32_t pr
   if (check_prec(prec) != ECSIM_OK) return ECSIM_EINVAL;
   if (!bytes) return fail(ECSIM_EINVAL, "bytes is NULL");
   if (np < 0 || np >= ((int64_t)1 << 31)) return fail(ECSIM_EINVAL, "np out of range");
-  const size_t a = sort_workspace_bytes(g, np), b = tiled_workspace_bytes(g, np);
+  const size_t a = sort_workspace_bytes(g, np), b = tiled_workspace_bytes(g, np, prec == ECSIM_F32);
   *bytes = a > b ? a : b;
   return ECSIM_OK;
 }
@@ -156,7 +156,7 @@ ecsim_status ecsim_moments(const ecsim_grid* grid, const ecsim_particles* specie
   int64_t np_total = 0;
   for (int s = 0; s < nspecies; ++s) np_total += a[s].np;
   if (tiled) {
-    const size_t need = tiled_workspace_bytes(g, np_total);
+    const size_t need = tiled_workspace_bytes(g, np_total, f32);
     if (!ws || ws_bytes < need)
       return fail(ECSIM_EWORKSPACE, "ecsim_moments: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
   }
@@ -188,10 +188,10 @@ ecsim_status ecsim_move_moments(const ecsim_grid* grid, const ecsim_particles* s
     return fail(ECSIM_EINVAL, "ecsim_move_moments: at most 4 species of fewer than 2^28 particles each");
   int64_t np_total = 0;
   for (int s = 0; s < nspecies; ++s) np_total += a[s].np;
-  const size_t need = tiled_workspace_bytes(g, np_total);
+  const bool f32 = species[0].prec == ECSIM_F32;
+  const size_t need = tiled_workspace_bytes(g, np_total, f32);
   if (!ws || ws_bytes < need)
     return fail(ECSIM_EWORKSPACE, "ecsim_move_moments: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
-  const bool f32 = species[0].prec == ECSIM_F32;
   const size_t esz = f32 ? 4 : 8;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;

@@ -81,6 +81,17 @@ struct TSpecies {
   const int32_t* cell_start;
 };
 
+// The strays' state copied out of the species arrays in cell order (the
+// deposit reads it without indirection); sp holds each stray's species.
+template <typename T>
+struct StrayData {
+  T* pos[3];
+  T* vel[3];
+  T* q;
+  int32_t* cell;
+  int32_t* sp;
+};
+
 template <typename T>
 struct TArgs {
   TSpecies<T> s[kMaxTiledSpecies];
@@ -92,8 +103,10 @@ struct TArgs {
   int* stray_count;
   int* stray_item;
   int* stray_cell;
-  const int* ind_start;   // the stray list sorted by cell: ranges and items
-  const int* ind_item;
+  StrayData<T> ul;        // the listed strays' state, in list order
+  const int* ind_start;   // the stray list sorted by cell: ranges
+  StrayData<T> sd;        // ... and the strays' state in that order
+  const void* zero;       // 64 zero bytes: the load target of idle lanes
   double* ke;
 };
 
@@ -112,12 +125,35 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A stray's state as listed: position (FP32: in-cell offsets), velocity,
+// charge and cell.
+template <typename T>
+struct SRec {
+  T x0, x1, x2, v0, v1, v2, q;
+  int c;
+};
+
+template <typename TA, typename T>
+__device__ __forceinline__ void put_stray(const TA& args, int pos, int item, int cell, const SRec<T>& r) {
+  args.stray_item[pos] = item;
+  args.stray_cell[pos] = cell;
+  const StrayData<T>& u = args.ul;
+  u.pos[0][pos] = r.x0;
+  u.pos[1][pos] = r.x1;
+  u.pos[2][pos] = r.x2;
+  u.vel[0][pos] = r.v0;
+  u.vel[1][pos] = r.v1;
+  u.vel[2][pos] = r.v2;
+  u.q[pos] = r.q;
+  u.cell[pos] = r.c;
+}
+
 // Writes the strays a wavefront keeps (per lane: slot 0 if k0, slot 1 if k1)
 // to the list at base, or, for base < 0, at a place reserved with one atomic.
 // Reached by the whole wavefront.
-template <typename TA>
-__device__ __forceinline__ void write_strays(const TA& args, int lane, int base, bool k0, int i0, int c0, bool k1,
-                                             int i1, int c1) {
+template <typename TA, typename T>
+__device__ __forceinline__ void write_strays(const TA& args, int lane, int base, bool k0, int i0, int c0,
+                                             const SRec<T>& r0, bool k1, int i1, int c1, const SRec<T>& r1) {
   const unsigned long long b0 = __ballot(k0), b1 = __ballot(k1);
   if (base < 0) {
     int r = 0;
@@ -127,34 +163,34 @@ __device__ __forceinline__ void write_strays(const TA& args, int lane, int base,
   const unsigned long long below = (1ull << lane) - 1ull;
   int pos = base + __popcll(b0 & below) + __popcll(b1 & below);
   if (k0) {
-    args.stray_item[pos] = i0;
-    args.stray_cell[pos] = c0;
+    put_stray(args, pos, i0, c0, r0);
     ++pos;
   }
-  if (k1) {
-    args.stray_item[pos] = i1;
-    args.stray_cell[pos] = c1;
-  }
+  if (k1) put_stray(args, pos, i1, c1, r1);
 }
 
-// Per-lane holding slots for strays (item, cell). When a lane needs a third
-// slot the whole wavefront empties its slots into the list.
+// Per-lane holding slots for strays (item, cell, state). When a lane needs a
+// third slot the whole wavefront empties its slots into the list.
+template <typename T>
 struct StrayBuf {
   int n = 0;
   int item0 = 0, cell0 = 0, item1 = 0, cell1 = 0;
-  __device__ __forceinline__ void push(int item, int cell) {
+  SRec<T> r0{}, r1{};
+  __device__ __forceinline__ void push(int item, int cell, const SRec<T>& r) {
     if (n == 0) {
       item0 = item;
       cell0 = cell;
+      r0 = r;
     } else {
       item1 = item;
       cell1 = cell;
+      r1 = r;
     }
     ++n;
   }
   template <typename TA>
   __device__ __forceinline__ void flush(const TA& args, int lane) {
-    write_strays(args, lane, -1, n >= 1, item0, cell0, n >= 2, item1, cell1);
+    write_strays(args, lane, -1, n >= 1, item0, cell0, r0, n >= 2, item1, cell1, r1);
     n = 0;
   }
 };
@@ -177,42 +213,6 @@ struct PData {       // one particle's inputs, loaded ahead of use
   int s, p;
   bool ok;
 };
-
-// Particle ip of a cell whose particles are the ranges cnt/beg of slots
-// 0..NSLOT-1 in turn (species, then, in the deposit, the sorted stray list).
-template <typename T, int NSLOT>
-__device__ __forceinline__ PData<T> load_particle(const TArgs<T>& args, const TSpecies<T>* lsp, const int* cnt,
-                                                  const int* beg, int total, int ip) {
-  PData<T> d{};
-  d.ok = ip < total;
-  if (d.ok) {
-    int s = 0, idx = ip, p = beg[0] + ip;
-#pragma unroll
-    for (int k = 0; k < NSLOT - 1; ++k)
-      if (s == k && idx >= cnt[k]) {   // constant indices only: no private memory
-        idx -= cnt[k];
-        s = k + 1;
-        p = beg[k + 1] + idx;
-      }
-    if (NSLOT > kStraySlot && s == kStraySlot) {
-      const int item = args.ind_item[p];
-      s = (item >> kItemShift) & (kMaxTiledSpecies - 1);
-      p = item & kIndexMask;
-    }
-    const TSpecies<T>& sp = lsp[s];   // LDS copy: a lane-dependent species costs no memory round trip
-    d.s = s;
-    d.p = p;
-    d.x0 = gld(sp.pos[0] + p);
-    d.x1 = gld(sp.pos[1] + p);
-    d.x2 = gld(sp.pos[2] + p);
-    d.v0 = gld(sp.vel[0] + p);
-    d.v1 = gld(sp.vel[1] + p);
-    d.v2 = gld(sp.vel[2] + p);
-    d.q = sp.q ? gld(sp.q + p) : sp.q_const;
-    if constexpr (sizeof(T) == 4) d.c = gld(sp.cell + p);
-  }
-  return d;
-}
 
 template <typename T>
 __device__ __forceinline__ Stencil<T> particle_stencil(const Grid& g, T x0, T x1, T x2, int c);
@@ -252,6 +252,125 @@ __host__ __device__ constexpr int pair_class(int k, int a) {
           ((a >> 1) & 1) + koff(k, 1) > 1 || ((a >> 2) & 1) + koff(k, 2) < 0 || ((a >> 2) & 1) + koff(k, 2) > 1)
              ? -1
              : (2 * (a & 1) + koff(k, 0)) + 3 * (2 * ((a >> 1) & 1) + koff(k, 1)) + 9 * (2 * ((a >> 2) & 1) + koff(k, 2));
+}
+
+// Where a deposit lane reads its particle: slots 0..3 the species arrays,
+// kStraySlot the sorted strays, kZeroSlot a zero block (idle lanes). Every
+// pointer is valid, so the loads need no branch.
+constexpr int kZeroSlot = kStraySlot + 1;
+template <typename T>
+struct PtrSet {
+  const T* pos[3];
+  const T* vel[3];
+  const T* q;
+  const int32_t* cell;
+  const int32_t* sp;
+  T qconst;   // added to the loaded q: the charge of a constant-charge species
+  // index masks: all ones for a per-particle array, 0 for the zero block
+  int qmask, cmask, smask;
+};
+
+template <typename T>
+__device__ __forceinline__ PtrSet<T> ptr_set_species(const TSpecies<T>& sp, const void* zero) {
+  PtrSet<T> P;
+  for (int d = 0; d < 3; ++d) {
+    P.pos[d] = sp.pos[d];
+    P.vel[d] = sp.vel[d];
+  }
+  P.q = sp.q ? sp.q : (const T*)zero;
+  P.qconst = sp.q ? T(0) : sp.q_const;
+  P.cell = sp.cell ? sp.cell : (const int32_t*)zero;
+  P.sp = (const int32_t*)zero;
+  P.qmask = sp.q ? -1 : 0;
+  P.cmask = sp.cell ? -1 : 0;
+  P.smask = 0;
+  return P;
+}
+
+template <typename T>
+__device__ __forceinline__ PtrSet<T> ptr_set_strays(const StrayData<T>& sd) {
+  PtrSet<T> P;
+  for (int d = 0; d < 3; ++d) {
+    P.pos[d] = sd.pos[d];
+    P.vel[d] = sd.vel[d];
+  }
+  P.q = sd.q;
+  P.qconst = T(0);
+  P.cell = sd.cell;
+  P.sp = sd.sp;
+  P.qmask = P.cmask = P.smask = -1;
+  return P;
+}
+
+template <typename T>
+__device__ __forceinline__ PtrSet<T> ptr_set_zero(const void* zero) {
+  PtrSet<T> P;
+  const T* z = (const T*)zero;
+  for (int d = 0; d < 3; ++d) P.pos[d] = P.vel[d] = z;
+  P.q = z;
+  P.qconst = T(0);
+  P.cell = P.sp = (const int32_t*)zero;
+  P.qmask = P.cmask = P.smask = 0;
+  return P;
+}
+
+// Fills the LDS tables of species and read slots (constant kernel-argument
+// indices only, so nothing goes through private memory).
+template <typename T>
+__device__ __forceinline__ void fill_tables(const TArgs<T>& args, TSpecies<T>* lsp, PtrSet<T>* lptr, int tid) {
+#pragma unroll
+  for (int k = 0; k < kMaxTiledSpecies; ++k) {
+    if (tid == k) {
+      const TSpecies<T>& sp = k < args.ns ? args.s[k] : args.s[0];
+      lsp[k] = sp;
+      if (lptr) lptr[k] = ptr_set_species(sp, args.zero);
+    }
+  }
+  if (lptr && tid == kStraySlot) lptr[kStraySlot] = ptr_set_strays(args.sd);
+  if (lptr && tid == kZeroSlot) lptr[kZeroSlot] = ptr_set_zero<T>(args.zero);
+}
+
+// Particle ip of a cell whose particles are the ranges cnt/beg of the species
+// slots and then the stray slot, loaded without branches.
+template <typename T>
+__device__ __forceinline__ PData<T> load_dep(const PtrSet<T>* lptr, const int* cnt, const int* beg, int total,
+                                             int ip) {
+  PData<T> d;
+  d.ok = ip < total;
+  int slot = 0, idx = ip, p = beg[0] + ip;
+#pragma unroll
+  for (int k = 0; k < kSlots5 - 1; ++k)
+    if (slot == k && idx >= cnt[k]) {   // constant indices only: no private memory
+      idx -= cnt[k];
+      slot = k + 1;
+      p = beg[k + 1] + idx;
+    }
+  const int ts = d.ok ? slot : kZeroSlot;
+  const int pi = d.ok ? p : 0;
+  const PtrSet<T>& P = lptr[ts];
+  // raw loads only: nothing here may use a loaded value, or the compiler
+  // waits for the loads at once (see dep_species, dep_charge)
+  d.x0 = gld(P.pos[0] + pi);
+  d.x1 = gld(P.pos[1] + pi);
+  d.x2 = gld(P.pos[2] + pi);
+  d.v0 = gld(P.vel[0] + pi);
+  d.v1 = gld(P.vel[1] + pi);
+  d.v2 = gld(P.vel[2] + pi);
+  d.q = gld(P.q + (pi & P.qmask));
+  d.c = sizeof(T) == 4 ? gld(P.cell + (pi & P.cmask)) : 0;
+  d.s = gld(P.sp + (pi & P.smask));   // the species of a stray
+  d.p = ts;                           // the slot
+  return d;
+}
+
+// species and charge of a loaded deposit particle
+template <typename T>
+__device__ __forceinline__ int dep_species(const PData<T>& d) {
+  return d.p == kStraySlot ? d.s : (d.p < kMaxTiledSpecies ? d.p : 0);
+}
+template <typename T>
+__device__ __forceinline__ T dep_charge(const PData<T>& d, const PtrSet<T>* lptr) {
+  return d.q + lptr[d.p].qconst;
 }
 
 // A cell of a brick (local index lc).
@@ -459,7 +578,7 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
   const int wave = tid >> 6;
   int x0, y0, z0;
   brick_origin<TX, TY, TZ>(ntx, nty, ntz, x0, y0, z0);
-  if (tid < kMaxTiledSpecies) lsp[tid] = args.s[tid < args.ns ? tid : 0];
+  fill_tables<T>(args, lsp, nullptr, tid);
   // range r = (cell lc = r / 4, species r % 4): start, and the flat offsets
   int n = 0;
   if (tid < NR) {
@@ -500,7 +619,7 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
   __syncthreads();
   const int total = roff[NR];
   double kel = 0.0;
-  StrayBuf sb;
+  StrayBuf<T> sb;
 
   // flat index i -> (range, particle); the last range with roff <= i is the
   // non-empty one holding i
@@ -540,6 +659,8 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
     const PData<T> pn = locate(base + NT + lane, r_nxt);   // next block, in flight during this one
     bool stray = false;
     int item = 0, lcell = 0;
+    // the listed state: the particle as it is now (moved, when moved here)
+    SRec<T> rec{pd.x0, pd.x1, pd.x2, pd.v0, pd.v1, pd.v2, pd.q, pd.c};
     if (pd.ok) {
       const TSpecies<T>& sp = lsp[pd.s];
       const BrickCell gc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, r_cur / kMaxTiledSpecies);
@@ -571,21 +692,25 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
           int pcell;
           if constexpr (sizeof(T) == 4) {
             int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
-            gst(sp.pos[0] + pd.p, push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx));
-            gst(sp.pos[1] + pd.p, push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny));
-            gst(sp.pos[2] + pd.p, push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz));
+            rec.x0 = push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx);
+            rec.x1 = push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny);
+            rec.x2 = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
             pcell = ix + g.nx * (iy + g.ny * iz);
             gst(sp.cell + pd.p, pcell);
           } else {
-            const double n0 = push_abs(pd.x0, g.dt, v.x, g.nx * g.hx);
-            const double n1 = push_abs(pd.x1, g.dt, v.y, g.ny * g.hy);
-            const double n2 = push_abs(pd.x2, g.dt, v.z, g.nz * g.hz);
-            gst(sp.pos[0] + pd.p, (T)n0);
-            gst(sp.pos[1] + pd.p, (T)n1);
-            gst(sp.pos[2] + pd.p, (T)n2);
-            const Stencil<double> nps = stencil_abs(g, n0, n1, n2);
+            rec.x0 = push_abs(pd.x0, g.dt, v.x, g.nx * g.hx);
+            rec.x1 = push_abs(pd.x1, g.dt, v.y, g.ny * g.hy);
+            rec.x2 = push_abs(pd.x2, g.dt, v.z, g.nz * g.hz);
+            const Stencil<double> nps = stencil_abs(g, rec.x0, rec.x1, rec.x2);
             pcell = nps.i[0] + g.nx * (nps.i[1] + g.ny * nps.i[2]);
           }
+          rec.v0 = v.x;
+          rec.v1 = v.y;
+          rec.v2 = v.z;
+          rec.c = pcell;
+          gst(sp.pos[0] + pd.p, rec.x0);
+          gst(sp.pos[1] + pd.p, rec.x1);
+          gst(sp.pos[2] + pd.p, rec.x2);
           gst(sp.vel[0] + pd.p, v.x);
           gst(sp.vel[1] + pd.p, v.y);
           gst(sp.vel[2] + pd.p, v.z);
@@ -606,7 +731,7 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
       }
     }
     if (__ballot(stray && sb.n == 2)) sb.flush(args, lane);   // a lane needs a third slot
-    if (stray) sb.push(item, lcell);
+    if (stray) sb.push(item, lcell, rec);
     pd = pn;
     r_cur = r_nxt;
   }
@@ -639,7 +764,7 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
     }
   }
   __syncthreads();
-  write_strays(args, lane, wst[wave], k0, sb.item0, sb.cell0, k1, sb.item1, sb.cell1);
+  write_strays(args, lane, wst[wave], k0, sb.item0, sb.cell0, sb.r0, k1, sb.item1, sb.cell1, sb.r1);
 }
 
 // ---------------------------------------------------------------------------
@@ -657,6 +782,7 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
   // 16-bit immediate of ds_read), then the per-cell sums
   __shared__ __attribute__((aligned(16))) T smem[NW * WREC + NCELL * SCS];
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
+  __shared__ PtrSet<T> lptr[kZeroSlot + 1];
   T* const scell = smem + NW * WREC;
 
   const int tid = threadIdx.x;
@@ -671,7 +797,7 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
 
   for (int i = tid; i < NCELL * SCS; i += NW * 64) scell[i] = T(0);
   for (int i = tid; i < NW * WREC; i += NW * 64) smem[i] = T(0);
-  if (tid < kMaxTiledSpecies) lsp[tid] = args.s[tid < args.ns ? tid : 0];
+  fill_tables(args, lsp, lptr, tid);
   __syncthreads();
 
   T* const wrec = smem + wave * WREC;
@@ -693,7 +819,7 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
   BrickCell pc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, 2 * wave + half);
   T sv = load_stage(pc);
   Ranges rg = make_ranges<T, kSlots5>(args, load_ranges<T, kSlots5>(args, lsp, pc), pc);
-  PData<T> pd = load_particle<T, kSlots5>(args, lsp, rg.cnt, rg.beg, rg.total, hl);
+  PData<T> pd = load_dep<T>(lptr, rg.cnt, rg.beg, rg.total, hl);
 
   for (int pair = wave; pair < NPAIR; pair += NW) {
     const bool has_next = pair + NW < NPAIR;   // wave-uniform
@@ -713,7 +839,7 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
     if (cmax == 0) {   // wave-uniform: both cells empty
       if (has_next) {
         rg = make_ranges<T, kSlots5>(args, nrl, nc);
-        pd = load_particle<T, kSlots5>(args, lsp, rg.cnt, rg.beg, rg.total, hl);
+        pd = load_dep<T>(lptr, rg.cnt, rg.beg, rg.total, hl);
       }
       pc = nc;
       sv = nsv;
@@ -737,7 +863,7 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
       // Every lane runs the same arithmetic; lanes whose particle is not in
       // the cell (or that hold none) carry zero charge, so zero values.
       {
-        const TSpecies<T>& sp = lsp[pd.s];
+        const TSpecies<T>& sp = lsp[dep_species(pd)];
         const Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
         const bool keep = pd.ok && ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]) == cell;
         T W[8];
@@ -745,18 +871,19 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
         for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
         const Vec3<T> B1 = gather_staged(W, stage);
         T r[39];
-        particle_record(ps, B1, Vec3<T>{pd.v0, pd.v1, pd.v2}, keep ? pd.q : T(0), sp, r);
+        particle_record(ps, B1, Vec3<T>{pd.v0, pd.v1, pd.v2}, keep ? dep_charge(pd, lptr) : T(0), sp, r);
 #pragma unroll
         for (int i = 0; i < 39; ++i) wrec[i * kSlots + lane] = r[i];
       }
       wave_sync();
       // prefetch the next block (of this pair, else of the next pair) while
-      // this block is reduced
-      if (ch + 32 < cmax) {
-        pd = load_particle<T, kSlots5>(args, lsp, cr.cnt, cr.beg, cr.total, ch + 32 + hl);
-      } else if (has_next) {
-        rg = make_ranges<T, kSlots5>(args, nrl, nc);
-        pd = load_particle<T, kSlots5>(args, lsp, rg.cnt, rg.beg, rg.total, hl);
+      // this block is reduced: one unconditional load site, so that the
+      // loads stay in flight until the next block uses them
+      const bool same = ch + 32 < cmax;   // wave-uniform
+      if (!same && has_next) rg = make_ranges<T, kSlots5>(args, nrl, nc);
+      {
+        const Ranges& nr = same ? cr : rg;
+        pd = load_dep<T>(lptr, nr.cnt, nr.beg, nr.total, same ? ch + 32 + hl : hl);
       }
 
       // ---- 2. matrix cores: S[value][class] += sum over 4 particles per step ----
@@ -844,7 +971,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
   __shared__ double red[4];
-  if (threadIdx.x < kMaxTiledSpecies) lsp[threadIdx.x] = args.s[threadIdx.x < args.ns ? threadIdx.x : 0];
+  fill_tables<T>(args, lsp, nullptr, threadIdx.x);
   __syncthreads();
   const int n = *args.stray_count;
   double kel = 0.0;
@@ -854,11 +981,10 @@ __global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
     const int s = (item >> kItemShift) & (kMaxTiledSpecies - 1);
     const int p = item & kIndexMask;
     const TSpecies<T>& sp = lsp[s];
-    const T q = sp.q ? gld(sp.q + p) : sp.q_const;
-    int c = 0;
-    if constexpr (sizeof(T) == 4) c = gld(sp.cell + p);
-    const T x0 = gld(sp.pos[0] + p), x1 = gld(sp.pos[1] + p), x2 = gld(sp.pos[2] + p);
-    Stencil<T> ps = particle_stencil<T>(g, x0, x1, x2, c);
+    const StrayData<T>& ul = args.ul;   // the listed (current) state
+    const T q = ul.q[i];
+    const T x0 = ul.pos[0][i], x1 = ul.pos[1][i], x2 = ul.pos[2][i];
+    Stencil<T> ps = particle_stencil<T>(g, x0, x1, x2, ul.cell[i]);
     T W[8];
     int64_t nd[8];
     corners(g, ps, W, nd);
@@ -867,29 +993,36 @@ __global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
     T a0[9];
     rotation(Bp, sp.beta, a0);
     Vec3<T> u;
-    const Vec3<T> v = velocity_update(a0, Vec3<T>{gld(sp.vel[0] + p), gld(sp.vel[1] + p), gld(sp.vel[2] + p)}, Ep,
-                                      sp.beta, u);
+    const Vec3<T> v = velocity_update(a0, Vec3<T>{ul.vel[0][i], ul.vel[1][i], ul.vel[2][i]}, Ep, sp.beta, u);
+    T n0, n1, n2;
     int ncell;
     if constexpr (sizeof(T) == 4) {
       int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
-      gst(sp.pos[0] + p, push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx));
-      gst(sp.pos[1] + p, push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny));
-      gst(sp.pos[2] + p, push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz));
+      n0 = push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx);
+      n1 = push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny);
+      n2 = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
       ncell = ix + g.nx * (iy + g.ny * iz);
       gst(sp.cell + p, ncell);
     } else {
-      const double n0 = push_abs(x0, g.dt, v.x, g.nx * g.hx);
-      const double n1 = push_abs(x1, g.dt, v.y, g.ny * g.hy);
-      const double n2 = push_abs(x2, g.dt, v.z, g.nz * g.hz);
-      gst(sp.pos[0] + p, (T)n0);
-      gst(sp.pos[1] + p, (T)n1);
-      gst(sp.pos[2] + p, (T)n2);
+      n0 = push_abs(x0, g.dt, v.x, g.nx * g.hx);
+      n1 = push_abs(x1, g.dt, v.y, g.ny * g.hy);
+      n2 = push_abs(x2, g.dt, v.z, g.nz * g.hz);
       const Stencil<double> nps = stencil_abs(g, n0, n1, n2);
       ncell = nps.i[0] + g.nx * (nps.i[1] + g.ny * nps.i[2]);
     }
+    gst(sp.pos[0] + p, n0);
+    gst(sp.pos[1] + p, n1);
+    gst(sp.pos[2] + p, n2);
     gst(sp.vel[0] + p, v.x);
     gst(sp.vel[1] + p, v.y);
     gst(sp.vel[2] + p, v.z);
+    ul.pos[0][i] = n0;
+    ul.pos[1][i] = n1;
+    ul.pos[2][i] = n2;
+    ul.vel[0][i] = v.x;
+    ul.vel[1][i] = v.y;
+    ul.vel[2][i] = v.z;
+    ul.cell[i] = ncell;
     // back in its range's cell: the deposit takes it from the range, so it
     // leaves the list (cell -1)
     const int range_cell = args.stray_cell[i];
@@ -938,33 +1071,53 @@ __global__ void __launch_bounds__(256) k_stray_rank(const int* __restrict__ coun
   }
 }
 
-__global__ void __launch_bounds__(256) k_stray_scatter(const int* __restrict__ count, const int* __restrict__ cellv,
-                                                       const int* __restrict__ ranks, const int* __restrict__ start,
-                                                       const int* __restrict__ item, int* __restrict__ sorted) {
-  const int n = *count;
+template <typename T>
+__global__ void __launch_bounds__(256) k_stray_scatter(TArgs<T> args, const int* __restrict__ ranks) {
+  const int n = *args.stray_count;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const int c = cellv[i];
-    if (c >= 0) sorted[start[c] + ranks[i]] = item[i];
+    const int c = args.stray_cell[i];
+    if (c < 0) continue;
+    const int o = args.ind_start[c] + ranks[i];
+    const StrayData<T>& u = args.ul;
+    const StrayData<T>& d = args.sd;
+    for (int k = 0; k < 3; ++k) {
+      d.pos[k][o] = u.pos[k][i];
+      d.vel[k][o] = u.vel[k][i];
+    }
+    d.q[o] = u.q[i];
+    d.cell[o] = u.cell[i];
+    d.sp[o] = (args.stray_item[i] >> kItemShift) & (kMaxTiledSpecies - 1);
   }
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Workspace of the tiled path: the stray counter and a 64-byte zero block,
+// the stray list (item, cell, rank), the strays' state in list order (7
+// arrays of esz-byte values and the cell) and in cell order (the same and the
+// species), the per-cell stray counts and their scan. Laid out by carve();
+// tiled_workspace_bytes() is its size.
 struct StrayWs {
   int* count;
+  void* zero;
   int* item;
   int* cell;
   int* rank;
-  int* sorted;
+  void* udata[7];  // listed state in list order: pos[3], vel[3], q
+  int* ucell;
+  void* data[7];   // ... and in cell order
+  int* dcell;
+  int* dsp;
   int* counts;
   int* start;
   int* scan_sums;
 };
 
-StrayWs carve(const Grid& g, int64_t cap, void* ws) {
+StrayWs carve(const Grid& g, int64_t cap, size_t esz, void* ws) {
   char* w = (char*)ws;
   StrayWs s;
   s.count = (int*)w;
+  s.zero = w + 64;
   w += 256;
   s.item = (int*)w;
   w += align256(sizeof(int) * (size_t)cap);
@@ -972,7 +1125,19 @@ StrayWs carve(const Grid& g, int64_t cap, void* ws) {
   w += align256(sizeof(int) * (size_t)cap);
   s.rank = (int*)w;
   w += align256(sizeof(int) * (size_t)cap);
-  s.sorted = (int*)w;
+  for (int k = 0; k < 7; ++k) {
+    s.udata[k] = w;
+    w += align256(esz * (size_t)cap);
+  }
+  s.ucell = (int*)w;
+  w += align256(sizeof(int) * (size_t)cap);
+  for (int k = 0; k < 7; ++k) {
+    s.data[k] = w;
+    w += align256(esz * (size_t)cap);
+  }
+  s.dcell = (int*)w;
+  w += align256(sizeof(int) * (size_t)cap);
+  s.dsp = (int*)w;
   w += align256(sizeof(int) * (size_t)cap);
   s.counts = (int*)w;
   w += align256(sizeof(int) * (size_t)g.nn);
@@ -1014,8 +1179,8 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
   const int ntiles = ntx * nty * ntz;
   int64_t cap = 0;
   for (int s = 0; s < ns; ++s) cap += sp[s].np;
-  StrayWs w = carve(g, cap, ws);
-  hipError_t e = launch_zero(w.count, sizeof(int), st);
+  StrayWs w = carve(g, cap, sizeof(T), ws);
+  hipError_t e = launch_zero(w.count, 256, st);   // the counter and the zero block
   if (e != hipSuccess) return e;
   TArgs<T> a = make_args<T>(g, sp, ns);
   a.Bdep = (const T*)Bdep;
@@ -1025,6 +1190,22 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
   a.stray_item = w.item;
   a.stray_cell = w.cell;
   a.ke = ke;
+  a.zero = w.zero;
+  a.ind_start = w.start;
+  for (int k = 0; k < 3; ++k) {
+    a.sd.pos[k] = (T*)w.data[k];
+    a.sd.vel[k] = (T*)w.data[3 + k];
+  }
+  a.sd.q = (T*)w.data[6];
+  a.sd.cell = w.dcell;
+  a.sd.sp = w.dsp;
+  for (int k = 0; k < 3; ++k) {
+    a.ul.pos[k] = (T*)w.udata[k];
+    a.ul.vel[k] = (T*)w.udata[3 + k];
+  }
+  a.ul.q = (T*)w.udata[6];
+  a.ul.cell = w.ucell;
+  a.ul.sp = nullptr;
   constexpr int kGroupWaves = 4;   // 4-wave workgroups: three fit a CU at the mover's register count
   if (move) {
     hipLaunchKernelGGL((k_group<T, TX, TY, TZ, kGroupWaves, true>), dim3(ntiles), dim3(kGroupWaves * 64), 0, st, g,
@@ -1042,11 +1223,8 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
                      w.rank);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_exclusive_scan(w.counts, g.nn, w.start, w.scan_sums, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_stray_scatter, dim3(1024), dim3(256), 0, st, (const int*)w.count, (const int*)w.cell,
-                     (const int*)w.rank, (const int*)w.start, (const int*)w.item, w.sorted);
+  hipLaunchKernelGGL(k_stray_scatter<T>, dim3(1024), dim3(256), 0, st, a, (const int*)w.rank);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  a.ind_start = w.start;
-  a.ind_item = w.sorted;
   hipLaunchKernelGGL((k_deposit<T, TX, TY, TZ, NW>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty, ntz,
                      (T*)J, (T*)M);
   return hipGetLastError();
@@ -1054,10 +1232,12 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
 
 }  // namespace
 
-size_t tiled_workspace_bytes(const Grid& g, int64_t np_total) {
+size_t tiled_workspace_bytes(const Grid& g, int64_t np_total, bool f32) {
   const int64_t nscan = (g.nn + 1023) / 1024 + 1;
-  return 256 + 4 * align256(sizeof(int) * (size_t)np_total) + align256(sizeof(int) * (size_t)g.nn) +
-         align256(sizeof(int) * (size_t)(g.nn + 1)) + align256(sizeof(int) * (size_t)nscan);
+  const size_t esz = f32 ? 4 : 8;
+  return 256 + 6 * align256(sizeof(int) * (size_t)np_total) + 14 * align256(esz * (size_t)np_total) +
+         align256(sizeof(int) * (size_t)g.nn) + align256(sizeof(int) * (size_t)(g.nn + 1)) +
+         align256(sizeof(int) * (size_t)nscan);
 }
 
 bool tiled_species_ok(const SpeciesArgs* sp, int ns) {

@@ -31,7 +31,7 @@ hipError_t launch_deposit_atomic(const Grid& g, bool f32, const SpeciesArgs* sp,
 
 // Tiled deposit over particles grouped by cell ranges (cell_start); particles
 // outside their range's cell are handled through a stray list in `ws`.
-size_t tiled_workspace_bytes(const Grid& g, int64_t np_total);
+size_t tiled_workspace_bytes(const Grid& g, int64_t np_total, bool f32);
 bool tiled_species_ok(const SpeciesArgs* sp, int ns);
 hipError_t launch_deposit_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* B,
                                 void* J, void* M, void* ws, hipStream_t st);
