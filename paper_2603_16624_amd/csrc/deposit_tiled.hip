@@ -537,11 +537,13 @@ __device__ __forceinline__ void flush_brick(const Grid& g, const T* scell, int x
 
 // Records in LDS are stored transposed, rec[row][slot] with a row stride of
 // 66 slots (64 particles + 2): the MFMA operand reads of 16 lanes with
-// consecutive rows and 2 lane groups then hit 32 different banks. Rows 39-43
+// consecutive rows and 2 lane groups then hit 32 different banks. Rows 39-41
 // are not read as used operands; they stage the cells' corner fields
-// (during phase 1) and the current class sums (during phase 3).
+// (during phase 1) and the current class sums (during phase 3). With 42 rows
+// a 4-wavefront workgroup on a 4x4x2 brick needs 79 KB of LDS (FP32), so two
+// workgroups share a CU.
 constexpr int kSlots = 66;
-constexpr int kRows = 44;
+constexpr int kRows = 42;
 constexpr int kStage = 39 * kSlots;        // [2 cells][24]: deposit B at the corners
 constexpr int kTcur = 39 * kSlots;         // [2 cells][84]: current class sums (phase 3 only)
 
@@ -1249,13 +1251,13 @@ bool tiled_species_ok(const SpeciesArgs* sp, int ns) {
 
 hipError_t launch_deposit_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* B, void* J,
                                 void* M, void* ws, hipStream_t st) {
-  if (f32) return run_T<float, 4, 4, 4, 8>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
+  if (f32) return run_T<float, 4, 4, 2, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
   return run_T<double, 4, 4, 2, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
 }
 
 hipError_t launch_move_deposit(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* E, const void* B,
                                const void* Bnext, void* J, void* M, double* ke, void* ws, hipStream_t st) {
-  if (f32) return run_T<float, 4, 4, 4, 8>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st);
+  if (f32) return run_T<float, 4, 4, 2, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st);
   return run_T<double, 4, 4, 2, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st);
 }
 
