@@ -1051,25 +1051,12 @@ __global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_stray_rank(const int* __restrict__ count, const int* __restrict__ cellv,
                                                     int* __restrict__ counts, int* __restrict__ ranks) {
+  // one returning atomic per stray, all lanes at once: strays of a wavefront
+  // mostly lie in different cells, so a per-key leader loop would serialise
   const int n = *count;
-  const int lane = threadIdx.x & 63;
-  for (int base = blockIdx.x * 256; base < n; base += gridDim.x * 256) {
-    const int i = base + threadIdx.x;
-    const int key = i < n ? cellv[i] : -1;
-    const bool active = key >= 0;   // entries with cell -1 have left the list
-    unsigned long long pending = __ballot(active);
-    int my_rank = 0;
-    while (pending) {
-      const int leader = __ffsll((unsigned long long)pending) - 1;
-      const int lkey = __shfl(key, leader);
-      const unsigned long long grp = __ballot(key == lkey) & pending;
-      int b0 = 0;
-      if (lane == leader) b0 = atomicAdd(&counts[lkey], __popcll(grp));
-      b0 = __shfl(b0, leader);
-      if ((grp >> lane) & 1ull) my_rank = b0 + __popcll(grp & ((1ull << lane) - 1ull));
-      pending &= ~grp;
-    }
-    if (active) ranks[i] = my_rank;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const int c = cellv[i];
+    if (c >= 0) ranks[i] = atomicAdd(&counts[c], 1);   // entries with cell -1 have left the list
   }
 }
 
