@@ -654,11 +654,9 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
     return d;
   };
 
-  int r_cur;
-  PData<T> pd = locate(wave * 64 + lane, r_cur);
-  for (int base = wave * 64; base < total; base += NT) {
-    int r_nxt;
-    const PData<T> pn = locate(base + NT + lane, r_nxt);   // next block, in flight during this one
+  // one particle per lane: move / check it and list it if it strays (reached
+  // by the whole wavefront: the stray slots use ballots)
+  auto process = [&](const PData<T>& pd, int r_cur) {
     bool stray = false;
     int item = 0, lcell = 0;
     // the listed state: the particle as it is now (moved, when moved here)
@@ -734,8 +732,36 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
     }
     if (__ballot(stray && sb.n == 2)) sb.flush(args, lane);   // a lane needs a third slot
     if (stray) sb.push(item, lcell, rec);
-    pd = pn;
-    r_cur = r_nxt;
+  };
+
+  if constexpr (sizeof(T) == 4) {
+    // two blocks of 64 per wavefront and iteration, the next two blocks'
+    // loads in flight while these are processed
+    int ra, rb;
+    PData<T> pa = locate(wave * 128 + lane, ra);
+    PData<T> pb = locate(wave * 128 + 64 + lane, rb);
+    for (int base = wave * 128; base < total; base += 2 * NT) {
+      int rna, rnb;
+      const PData<T> na = locate(base + 2 * NT + lane, rna);
+      const PData<T> nb = locate(base + 2 * NT + 64 + lane, rnb);
+      process(pa, ra);
+      process(pb, rb);
+      pa = na;
+      ra = rna;
+      pb = nb;
+      rb = rnb;
+    }
+  } else {
+    // FP64: one block per iteration (its registers allow no second)
+    int ra;
+    PData<T> pa = locate(wave * 64 + lane, ra);
+    for (int base = wave * 64; base < total; base += NT) {
+      int rna;
+      const PData<T> na = locate(base + NT + lane, rna);
+      process(pa, ra);
+      pa = na;
+      ra = rna;
+    }
   }
   if constexpr (MOVE) {
     if (args.ke) {
