@@ -107,6 +107,7 @@ struct TArgs {
   const int* ind_start;   // the stray list sorted by cell: ranges
   StrayData<T> sd;        // ... and the strays' state in that order
   const void* zero;       // 64 zero bytes: the load target of idle lanes
+  void* sink;             // the store target of idle lanes (never read)
   double* ke;
 };
 
@@ -648,7 +649,9 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
       d.v0 = gld(sp.vel[0] + p);
       d.v1 = gld(sp.vel[1] + p);
       d.v2 = gld(sp.vel[2] + p);
-      d.q = sp.q ? gld(sp.q + p) : sp.q_const;
+      // raw charge (0 for a constant-charge species, whose charge is added at
+      // use): a select into the loaded register would make the compiler wait
+      d.q = gld((sp.q ? sp.q : (const T*)args.zero) + (sp.q ? p : 0));
       if constexpr (sizeof(T) == 4) d.c = gld(sp.cell + p);
     }
     return d;
@@ -657,78 +660,88 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
   // one particle per lane: move / check it and list it if it strays (reached
   // by the whole wavefront: the stray slots use ballots)
   auto process = [&](const PData<T>& pd, int r_cur) {
-    bool stray = false;
-    int item = 0, lcell = 0;
+    // Branch-free: every lane runs the arithmetic and issues the same
+    // stores (a lane without a particle writes into the sink block),
+    // so the loop issues a fixed number of memory operations per iteration
+    // and the next block's loads need not be waited for early.
+    const TSpecies<T>& sp = lsp[pd.s];
+    const T q = pd.q + (sp.q ? T(0) : sp.q_const);
+    const BrickCell gc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, r_cur / kMaxTiledSpecies);
+    Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
+    const int pcell0 = ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]);
+    int item = (pd.s << kItemShift) | pd.p;
     // the listed state: the particle as it is now (moved, when moved here)
-    SRec<T> rec{pd.x0, pd.x1, pd.x2, pd.v0, pd.v1, pd.v2, pd.q, pd.c};
-    if (pd.ok) {
-      const TSpecies<T>& sp = lsp[pd.s];
-      const BrickCell gc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, r_cur / kMaxTiledSpecies);
-      Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
-      const int pcell0 = ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]);
-      item = (pd.s << kItemShift) | pd.p;
-      if constexpr (MOVE) {
-        // local cell in the halo'd box (periodic)
-        const int dx = (ps.i[0] - x0 + 1 + g.nx) % g.nx;
-        const int dy = (ps.i[1] - y0 + 1 + g.ny) % g.ny;
-        const int dz = (ps.i[2] - z0 + 1 + g.nz) % g.nz;
-        if (dx <= TX + 1 && dy <= TY + 1 && dz <= TZ + 1) {
-          Vec3<T> Ep{T(0), T(0), T(0)}, Bp{T(0), T(0), T(0)};
+    SRec<T> rec{pd.x0, pd.x1, pd.x2, pd.v0, pd.v1, pd.v2, q, pd.c};
+    bool stray;
+    int lcell;
+    if constexpr (MOVE) {
+      // local cell in the halo'd box (periodic)
+      const int dx = (ps.i[0] - x0 + 1 + g.nx) % g.nx;
+      const int dy = (ps.i[1] - y0 + 1 + g.ny) % g.ny;
+      const int dz = (ps.i[2] - z0 + 1 + g.nz) % g.nz;
+      const bool inbox = pd.ok && dx <= TX + 1 && dy <= TY + 1 && dz <= TZ + 1;
+      const int lx = inbox ? dx : 0, ly = inbox ? dy : 0, lz = inbox ? dz : 0;
+      Vec3<T> Ep{T(0), T(0), T(0)}, Bp{T(0), T(0), T(0)};
 #pragma unroll
-          for (int a = 0; a < 8; ++a) {
-            const T w = corner_weight(ps, a);
-            const int nl = (dx + (a & 1)) + HX * ((dy + ((a >> 1) & 1)) + HY * (dz + ((a >> 2) & 1)));
-            Ep.x = fma(w, fld[nl], Ep.x);
-            Ep.y = fma(w, fld[HN + nl], Ep.y);
-            Ep.z = fma(w, fld[2 * HN + nl], Ep.z);
-            Bp.x = fma(w, fld[3 * HN + nl], Bp.x);
-            Bp.y = fma(w, fld[4 * HN + nl], Bp.y);
-            Bp.z = fma(w, fld[5 * HN + nl], Bp.z);
-          }
-          T a0[9];
-          rotation(Bp, sp.beta, a0);
-          Vec3<T> u;
-          const Vec3<T> v = velocity_update(a0, Vec3<T>{pd.v0, pd.v1, pd.v2}, Ep, sp.beta, u);
-          int pcell;
-          if constexpr (sizeof(T) == 4) {
-            int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
-            rec.x0 = push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx);
-            rec.x1 = push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny);
-            rec.x2 = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
-            pcell = ix + g.nx * (iy + g.ny * iz);
-            gst(sp.cell + pd.p, pcell);
-          } else {
-            rec.x0 = push_abs(pd.x0, g.dt, v.x, g.nx * g.hx);
-            rec.x1 = push_abs(pd.x1, g.dt, v.y, g.ny * g.hy);
-            rec.x2 = push_abs(pd.x2, g.dt, v.z, g.nz * g.hz);
-            const Stencil<double> nps = stencil_abs(g, rec.x0, rec.x1, rec.x2);
-            pcell = nps.i[0] + g.nx * (nps.i[1] + g.ny * nps.i[2]);
-          }
-          rec.v0 = v.x;
-          rec.v1 = v.y;
-          rec.v2 = v.z;
-          rec.c = pcell;
-          gst(sp.pos[0] + pd.p, rec.x0);
-          gst(sp.pos[1] + pd.p, rec.x1);
-          gst(sp.pos[2] + pd.p, rec.x2);
-          gst(sp.vel[0] + pd.p, v.x);
-          gst(sp.vel[1] + pd.p, v.y);
-          gst(sp.vel[2] + pd.p, v.z);
-          if (args.ke) {
-            const double vx = v.x, vy = v.y, vz = v.z;
-            kel += 0.5 * ((double)pd.q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz);
-          }
-          stray = pcell != gc.cell;   // the deposit takes the others from the range
-          lcell = pcell;
-        } else {
-          stray = true;               // beyond the box: moved by the stray mover
-          item |= kUnmoved;
-          lcell = gc.cell;
-        }
-      } else {
-        stray = pcell0 != gc.cell;
-        lcell = pcell0;
+      for (int a = 0; a < 8; ++a) {
+        const T w = corner_weight(ps, a);
+        const int nl = (lx + (a & 1)) + HX * ((ly + ((a >> 1) & 1)) + HY * (lz + ((a >> 2) & 1)));
+        Ep.x = fma(w, fld[nl], Ep.x);
+        Ep.y = fma(w, fld[HN + nl], Ep.y);
+        Ep.z = fma(w, fld[2 * HN + nl], Ep.z);
+        Bp.x = fma(w, fld[3 * HN + nl], Bp.x);
+        Bp.y = fma(w, fld[4 * HN + nl], Bp.y);
+        Bp.z = fma(w, fld[5 * HN + nl], Bp.z);
       }
+      T a0[9];
+      rotation(Bp, sp.beta, a0);
+      Vec3<T> u;
+      const Vec3<T> v = velocity_update(a0, Vec3<T>{pd.v0, pd.v1, pd.v2}, Ep, sp.beta, u);
+      T n0, n1, n2;
+      int pcell;
+      if constexpr (sizeof(T) == 4) {
+        int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
+        n0 = push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx);
+        n1 = push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny);
+        n2 = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
+        pcell = ix + g.nx * (iy + g.ny * iz);
+      } else {
+        n0 = push_abs(pd.x0, g.dt, v.x, g.nx * g.hx);
+        n1 = push_abs(pd.x1, g.dt, v.y, g.ny * g.hy);
+        n2 = push_abs(pd.x2, g.dt, v.z, g.nz * g.hz);
+        const Stencil<double> nps = stencil_abs(g, n0, n1, n2);
+        pcell = nps.i[0] + g.nx * (nps.i[1] + g.ny * nps.i[2]);
+      }
+      // moved state in the box; unchanged beyond it (the stray mover moves it)
+      if (inbox) {
+        rec.x0 = n0;
+        rec.x1 = n1;
+        rec.x2 = n2;
+        rec.v0 = v.x;
+        rec.v1 = v.y;
+        rec.v2 = v.z;
+        rec.c = pcell;
+      }
+      const int wi = pd.ok ? pd.p : 0;
+      T* const z = (T*)args.sink;
+      gst((pd.ok ? sp.pos[0] : z) + wi, rec.x0);
+      gst((pd.ok ? sp.pos[1] : z) + wi, rec.x1);
+      gst((pd.ok ? sp.pos[2] : z) + wi, rec.x2);
+      gst((pd.ok ? sp.vel[0] : z) + wi, rec.v0);
+      gst((pd.ok ? sp.vel[1] : z) + wi, rec.v1);
+      gst((pd.ok ? sp.vel[2] : z) + wi, rec.v2);
+      if constexpr (sizeof(T) == 4) gst((pd.ok ? sp.cell : (int32_t*)args.sink) + wi, rec.c);
+      if (args.ke) {
+        const double vx = v.x, vy = v.y, vz = v.z;
+        kel += inbox ? 0.5 * ((double)q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz) : 0.0;
+      }
+      // listed: moved out of the range's cell, or beyond the box (unmoved)
+      stray = pd.ok && (inbox ? pcell != gc.cell : true);
+      if (pd.ok && !inbox) item |= kUnmoved;
+      lcell = inbox ? pcell : gc.cell;
+    } else {
+      stray = pd.ok && pcell0 != gc.cell;
+      lcell = pcell0;
     }
     if (__ballot(stray && sb.n == 2)) sb.flush(args, lane);   // a lane needs a third slot
     if (stray) sb.push(item, lcell, rec);
@@ -916,20 +929,23 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
 
       // ---- 2. matrix cores: S[value][class] += sum over 4 particles per step ----
       // records past a cell's count are zero, so all 8 steps of a block run
-      acc_t dA0 = {0, 0, 0, 0}, dA1 = {0, 0, 0, 0}, dB0 = {0, 0, 0, 0}, dB1 = {0, 0, 0, 0};
+      // eight independent accumulator chains of four steps each (even and
+      // odd particle quads), so that the matrix-core latency is not a chain
+      // of eight dependent instructions
+      acc_t eA0 = {0, 0, 0, 0}, eA1 = {0, 0, 0, 0}, eB0 = {0, 0, 0, 0}, eB1 = {0, 0, 0, 0};
+      acc_t oA0 = {0, 0, 0, 0}, oA1 = {0, 0, 0, 0}, oB0 = {0, 0, 0, 0}, oB1 = {0, 0, 0, 0};
 #pragma unroll
-      for (int k4 = 0; k4 < 32; k4 += 4) {
-        const T aA = opnd[k4];
-        const T aB = opnd[32 + k4];
-        const T bA0 = opnd[12 * kSlots + k4];
-        const T bB0 = opnd[12 * kSlots + 32 + k4];
-        const T bA1 = opnd[28 * kSlots + k4];
-        const T bB1 = opnd[28 * kSlots + 32 + k4];
-        dA0 = MF::run(aA, bA0, dA0);
-        dB0 = MF::run(aB, bB0, dB0);
-        dA1 = MF::run(aA, bA1, dA1);
-        dB1 = MF::run(aB, bB1, dB1);
+      for (int k4 = 0; k4 < 32; k4 += 8) {
+        eA0 = MF::run(opnd[k4], opnd[12 * kSlots + k4], eA0);
+        eB0 = MF::run(opnd[32 + k4], opnd[12 * kSlots + 32 + k4], eB0);
+        eA1 = MF::run(opnd[k4], opnd[28 * kSlots + k4], eA1);
+        eB1 = MF::run(opnd[32 + k4], opnd[28 * kSlots + 32 + k4], eB1);
+        oA0 = MF::run(opnd[k4 + 4], opnd[12 * kSlots + k4 + 4], oA0);
+        oB0 = MF::run(opnd[36 + k4], opnd[12 * kSlots + 36 + k4], oB0);
+        oA1 = MF::run(opnd[k4 + 4], opnd[28 * kSlots + k4 + 4], oA1);
+        oB1 = MF::run(opnd[36 + k4], opnd[28 * kSlots + 36 + k4], oB1);
       }
+      const acc_t dA0 = eA0 + oA0, dA1 = eA1 + oA1, dB0 = eB0 + oB0, dB1 = eB1 + oB1;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if constexpr (sizeof(T) == 4) {
@@ -1107,7 +1123,8 @@ __global__ void __launch_bounds__(256) k_stray_scatter(TArgs<T> args, const int*
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Workspace of the tiled path: the stray counter and a 64-byte zero block,
+// Workspace of the tiled path: the stray counter, a zero block and a sink
+// (256 bytes each),
 // the stray list (item, cell, rank), the strays' state in list order (7
 // arrays of esz-byte values and the cell) and in cell order (the same and the
 // species), the per-cell stray counts and their scan. Laid out by carve();
@@ -1115,6 +1132,7 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 struct StrayWs {
   int* count;
   void* zero;
+  void* sink;
   int* item;
   int* cell;
   int* rank;
@@ -1131,9 +1149,13 @@ struct StrayWs {
 StrayWs carve(const Grid& g, int64_t cap, size_t esz, void* ws) {
   char* w = (char*)ws;
   StrayWs s;
+  // the counter (hit by atomics), the zero block (read by every idle or
+  // constant-charge lane) and the sink (written by idle lanes) on cache
+  // lines of their own
   s.count = (int*)w;
-  s.zero = w + 64;
-  w += 256;
+  s.zero = w + 256;
+  s.sink = w + 512;
+  w += 768;
   s.item = (int*)w;
   w += align256(sizeof(int) * (size_t)cap);
   s.cell = (int*)w;
@@ -1195,7 +1217,7 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
   int64_t cap = 0;
   for (int s = 0; s < ns; ++s) cap += sp[s].np;
   StrayWs w = carve(g, cap, sizeof(T), ws);
-  hipError_t e = launch_zero(w.count, 256, st);   // the counter and the zero block
+  hipError_t e = launch_zero(w.count, 512, st);   // the counter and the zero block
   if (e != hipSuccess) return e;
   TArgs<T> a = make_args<T>(g, sp, ns);
   a.Bdep = (const T*)Bdep;
@@ -1206,6 +1228,7 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
   a.stray_cell = w.cell;
   a.ke = ke;
   a.zero = w.zero;
+  a.sink = w.sink;
   a.ind_start = w.start;
   for (int k = 0; k < 3; ++k) {
     a.sd.pos[k] = (T*)w.data[k];
@@ -1250,7 +1273,7 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
 size_t tiled_workspace_bytes(const Grid& g, int64_t np_total, bool f32) {
   const int64_t nscan = (g.nn + 1023) / 1024 + 1;
   const size_t esz = f32 ? 4 : 8;
-  return 256 + 6 * align256(sizeof(int) * (size_t)np_total) + 14 * align256(esz * (size_t)np_total) +
+  return 768 + 6 * align256(sizeof(int) * (size_t)np_total) + 14 * align256(esz * (size_t)np_total) +
          align256(sizeof(int) * (size_t)g.nn) + align256(sizeof(int) * (size_t)(g.nn + 1)) +
          align256(sizeof(int) * (size_t)nscan);
 }
