@@ -334,7 +334,10 @@ __device__ __forceinline__ void fill_tables(const TArgs<T>& args, TSpecies<T>* l
 // Particle ip of a cell whose particles are the ranges cnt/beg of the species
 // slots and then the stray slot, loaded without branches.
 template <typename T>
-__device__ __forceinline__ PData<T> load_dep(const PtrSet<T>* lptr, const int* cnt, const int* beg, int total,
+using LdsPtrSet = const __attribute__((address_space(3))) PtrSet<T>;
+
+template <typename T>
+__device__ __forceinline__ PData<T> load_dep(LdsPtrSet<T>* lptr, const int* cnt, const int* beg, int total,
                                              int ip) {
   PData<T> d;
   d.ok = ip < total;
@@ -348,7 +351,7 @@ __device__ __forceinline__ PData<T> load_dep(const PtrSet<T>* lptr, const int* c
     }
   const int ts = d.ok ? slot : kZeroSlot;
   const int pi = d.ok ? p : 0;
-  const PtrSet<T>& P = lptr[ts];
+  LdsPtrSet<T>& P = lptr[ts];   // LDS reads (a generic pointer would make them flat loads)
   // raw loads only: nothing here may use a loaded value, or the compiler
   // waits for the loads at once (see dep_species, dep_charge)
   d.x0 = gld(P.pos[0] + pi);
@@ -370,7 +373,7 @@ __device__ __forceinline__ int dep_species(const PData<T>& d) {
   return d.p == kStraySlot ? d.s : (d.p < kMaxTiledSpecies ? d.p : 0);
 }
 template <typename T>
-__device__ __forceinline__ T dep_charge(const PData<T>& d, const PtrSet<T>* lptr) {
+__device__ __forceinline__ T dep_charge(const PData<T>& d, LdsPtrSet<T>* lptr) {
   return d.q + lptr[d.p].qconst;
 }
 
@@ -421,12 +424,12 @@ __device__ __forceinline__ RangeLd load_ranges(const TArgs<T>& args, const TSpec
 #pragma unroll
   for (int s = 0; s < kMaxTiledSpecies; ++s) {
     const int32_t* cs = lsp[s].cell_start;   // unused species alias species 0
-    r.lo[s] = cs[cl];
-    r.hi[s] = cs[cl + 1];
+    r.lo[s] = gld(cs + cl);                  // global loads (not flat: those would count as LDS too)
+    r.hi[s] = gld(cs + cl + 1);
   }
   if constexpr (NSLOT > kStraySlot) {
-    r.lo[kStraySlot] = args.ind_start[cl];
-    r.hi[kStraySlot] = args.ind_start[cl + 1];
+    r.lo[kStraySlot] = gld(args.ind_start + cl);
+    r.hi[kStraySlot] = gld(args.ind_start + cl + 1);
   }
   return r;
 }
@@ -563,7 +566,8 @@ constexpr int kTcur = 39 * kSlots;         // [2 cells][84]: current class sums 
 // unmoved (with its range's cell) for the stray mover. Without MOVE a
 // particle outside its range's cell is listed with its cell.
 template <typename T, int TX, int TY, int TZ, int NW, bool MOVE>
-__global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   constexpr int NCELL = TX * TY * TZ;
   constexpr int HX = TX + 3, HY = TY + 3, HZ = TZ + 3, HN = HX * HY * HZ;   // halo'd node box
   constexpr int NR = NCELL * kMaxTiledSpecies;                            // ranges: cell-major
@@ -576,12 +580,14 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
   __shared__ double red[NW];
   __shared__ int wst[NW];
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
+  __shared__ void* lsink;   // in LDS beside the species table: selects between them stay LDS reads
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   int x0, y0, z0;
   brick_origin<TX, TY, TZ>(ntx, nty, ntz, x0, y0, z0);
   fill_tables<T>(args, lsp, nullptr, tid);
+  if (tid == 0) lsink = args.sink;
   // range r = (cell lc = r / 4, species r % 4): start, and the flat offsets
   int n = 0;
   if (tid < NR) {
@@ -723,14 +729,14 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
         rec.c = pcell;
       }
       const int wi = pd.ok ? pd.p : 0;
-      T* const z = (T*)args.sink;
+      T* const z = (T*)lsink;
       gst((pd.ok ? sp.pos[0] : z) + wi, rec.x0);
       gst((pd.ok ? sp.pos[1] : z) + wi, rec.x1);
       gst((pd.ok ? sp.pos[2] : z) + wi, rec.x2);
       gst((pd.ok ? sp.vel[0] : z) + wi, rec.v0);
       gst((pd.ok ? sp.vel[1] : z) + wi, rec.v1);
       gst((pd.ok ? sp.vel[2] : z) + wi, rec.v2);
-      if constexpr (sizeof(T) == 4) gst((pd.ok ? sp.cell : (int32_t*)args.sink) + wi, rec.c);
+      if constexpr (sizeof(T) == 4) gst((pd.ok ? sp.cell : (int32_t*)lsink) + wi, rec.c);
       if (args.ke) {
         const double vx = v.x, vy = v.y, vz = v.z;
         kel += inbox ? 0.5 * ((double)q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz) : 0.0;
@@ -753,6 +759,10 @@ __global__ void __launch_bounds__(NW * 64) k_group(Grid g, TArgs<T> args, int nt
     int ra, rb;
     PData<T> pa = locate(wave * 128 + lane, ra);
     PData<T> pb = locate(wave * 128 + 64 + lane, rb);
+    // the first blocks are waited for here, so that at the loop head no
+    // load from before the loop is pending (else the compiler waits for all
+    // loads, the next blocks' included, at the first use)
+    __builtin_amdgcn_s_waitcnt(0);
     for (int base = wave * 128; base < total; base += 2 * NT) {
       int rna, rnb;
       const PData<T> na = locate(base + 2 * NT + lane, rna);
@@ -823,7 +833,8 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
   // 16-bit immediate of ds_read), then the per-cell sums
   __shared__ __attribute__((aligned(16))) T smem[NW * WREC + NCELL * SCS];
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
-  __shared__ PtrSet<T> lptr[kZeroSlot + 1];
+  __shared__ PtrSet<T> lptr_tab[kZeroSlot + 1];
+  LdsPtrSet<T>* const lptr = (LdsPtrSet<T>*)lptr_tab;
   T* const scell = smem + NW * WREC;
 
   const int tid = threadIdx.x;
@@ -838,7 +849,7 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
 
   for (int i = tid; i < NCELL * SCS; i += NW * 64) scell[i] = T(0);
   for (int i = tid; i < NW * WREC; i += NW * 64) smem[i] = T(0);
-  fill_tables(args, lsp, lptr, tid);
+  fill_tables(args, lsp, lptr_tab, tid);
   __syncthreads();
 
   T* const wrec = smem + wave * WREC;
