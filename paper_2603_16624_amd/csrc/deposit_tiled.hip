@@ -29,7 +29,7 @@
 //   2. the contraction runs on the matrix cores: v_mfma 16x16x4 with rows =
 //      the 12 values (padded to 16), columns = the 27 classes (two tiles of 16)
 //      and K = 4 particles per instruction; FP32 sums are formed in blocks of
-//      32 particles and the blocks combined with Kahan compensation;
+//      64 particles and the blocks combined with Kahan compensation;
 //   3. per-cell sums go to LDS (one writer per entry, no atomics);
 // then, after a workgroup barrier, every (node, entry) of the brick gathers
 // its <= 8 cell contributions and is added to the global J and M once.
@@ -901,8 +901,9 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
     if (hl < 24) stage[hl] = sv;
     wave_sync();
 
-    // running sums of the two cells: [cell][tile][reg]
+    // running sums of the two cells: [cell][tile][reg]; matrix-core block sums
     T S[2][2][4], C[2][2][4];
+    acc_t dA0 = {0, 0, 0, 0}, dA1 = {0, 0, 0, 0}, dB0 = {0, 0, 0, 0}, dB1 = {0, 0, 0, 0};
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -917,7 +918,11 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
       {
         const TSpecies<T>& sp = lsp[dep_species(pd)];
         const Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
-        const bool keep = pd.ok && ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]) == cell;
+        // in the cell: FP32 compares the stored cell index (the weights need
+        // only the offsets), FP64 the cell of the stencil
+        bool keep;
+        if constexpr (sizeof(T) == 4) keep = pd.ok && pd.c == cell;
+        else keep = pd.ok && ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]) == cell;
         T W[8];
 #pragma unroll
         for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
@@ -940,36 +945,37 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
 
       // ---- 2. matrix cores: S[value][class] += sum over 4 particles per step ----
       // records past a cell's count are zero, so all 8 steps of a block run
-      // eight independent accumulator chains of four steps each (even and
-      // odd particle quads), so that the matrix-core latency is not a chain
-      // of eight dependent instructions
-      acc_t eA0 = {0, 0, 0, 0}, eA1 = {0, 0, 0, 0}, eB0 = {0, 0, 0, 0}, eB1 = {0, 0, 0, 0};
-      acc_t oA0 = {0, 0, 0, 0}, oA1 = {0, 0, 0, 0}, oB0 = {0, 0, 0, 0}, oB1 = {0, 0, 0, 0};
+      // the matrix cores accumulate two blocks (64 particles) before the
+      // running sums take them with Kahan compensation
 #pragma unroll
-      for (int k4 = 0; k4 < 32; k4 += 8) {
-        eA0 = MF::run(opnd[k4], opnd[12 * kSlots + k4], eA0);
-        eB0 = MF::run(opnd[32 + k4], opnd[12 * kSlots + 32 + k4], eB0);
-        eA1 = MF::run(opnd[k4], opnd[28 * kSlots + k4], eA1);
-        eB1 = MF::run(opnd[32 + k4], opnd[28 * kSlots + 32 + k4], eB1);
-        oA0 = MF::run(opnd[k4 + 4], opnd[12 * kSlots + k4 + 4], oA0);
-        oB0 = MF::run(opnd[36 + k4], opnd[12 * kSlots + 36 + k4], oB0);
-        oA1 = MF::run(opnd[k4 + 4], opnd[28 * kSlots + k4 + 4], oA1);
-        oB1 = MF::run(opnd[36 + k4], opnd[28 * kSlots + 36 + k4], oB1);
+      for (int k4 = 0; k4 < 32; k4 += 4) {
+        const T aA = opnd[k4];
+        const T aB = opnd[32 + k4];
+        const T bA0 = opnd[12 * kSlots + k4];
+        const T bB0 = opnd[12 * kSlots + 32 + k4];
+        const T bA1 = opnd[28 * kSlots + k4];
+        const T bB1 = opnd[28 * kSlots + 32 + k4];
+        dA0 = MF::run(aA, bA0, dA0);
+        dB0 = MF::run(aB, bB0, dB0);
+        dA1 = MF::run(aA, bA1, dA1);
+        dB1 = MF::run(aB, bB1, dB1);
       }
-      const acc_t dA0 = eA0 + oA0, dA1 = eA1 + oA1, dB0 = eB0 + oB0, dB1 = eB1 + oB1;
+      if (((ch >> 5) & 1) || ch + 32 >= cmax) {   // wave-uniform
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if constexpr (sizeof(T) == 4) {
-          kahan(S[0][0][q], C[0][0][q], dA0[q]);
-          kahan(S[0][1][q], C[0][1][q], dA1[q]);
-          kahan(S[1][0][q], C[1][0][q], dB0[q]);
-          kahan(S[1][1][q], C[1][1][q], dB1[q]);
-        } else {
-          S[0][0][q] += dA0[q];
-          S[0][1][q] += dA1[q];
-          S[1][0][q] += dB0[q];
-          S[1][1][q] += dB1[q];
+        for (int q = 0; q < 4; ++q) {
+          if constexpr (sizeof(T) == 4) {
+            kahan(S[0][0][q], C[0][0][q], dA0[q]);
+            kahan(S[0][1][q], C[0][1][q], dA1[q]);
+            kahan(S[1][0][q], C[1][0][q], dB0[q]);
+            kahan(S[1][1][q], C[1][1][q], dB1[q]);
+          } else {
+            S[0][0][q] += dA0[q];
+            S[0][1][q] += dA1[q];
+            S[1][0][q] += dB0[q];
+            S[1][1][q] += dB1[q];
+          }
         }
+        dA0 = dA1 = dB0 = dB1 = acc_t{0, 0, 0, 0};
       }
       wave_sync();
     }
