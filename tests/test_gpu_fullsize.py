@@ -1,0 +1,144 @@
+"""GPU parity at the benchmark size, on sampled outputs.
+
+Workload: 64^3 periodic cells, 64 particles per cell per species, two
+species (33,554,432 particles), as generated for the benchmark. The fused
+particle pass (ecsim_move_moments, the call the benchmark times) runs twice
+on one cell grouping, the second time with the grouping stale, as between
+re-sorts. The FP64 oracle is too slow for every output at this size, so it
+checks samples:
+
+* the moved state (position, velocity) of sampled particles, each followed
+  through the same two moves from its initial state;
+* J-hat and the 14 stored mass-matrix blocks at sampled nodes: the oracle
+  moves and deposits every particle that ends within one cell of the 8
+  cells around those nodes (a node receives only from those 8 cells).
+
+Tolerances as in the other parity tests (relative max-norm over the sample):
+1e-12 FP64, 1e-5 FP32 (the oracle then runs on the FP32 inputs widened).
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import dev, host, need_gpu, periodic_rel, rel, round32, say, torch
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+NSAMPLE = 4096     # sampled particles per species
+NNODES = 8         # sampled nodes
+
+
+@pytest.fixture(scope="module")
+def E():
+    need_gpu()
+    from paper_2603_16624_amd import ecsim
+    ecsim.lib()
+    return ecsim
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def plasma():
+    from paper_2603_16624_amd import inputs
+    return inputs.config1()
+
+
+def node_fields(p):
+    rng = np.random.default_rng(4242)
+    En = 1e-3 * rng.standard_normal((3, p.nn))
+    BN = np.array([[0.0], [0.0], [0.2]]) + 0.02 * rng.standard_normal((3, p.nn))
+    Bnext = BN + 0.005 * rng.standard_normal((3, p.nn))
+    return En, BN, Bnext
+
+
+def cells_of(x, n, h):
+    """Cell index of absolute positions (3, k)."""
+    ijk = [np.clip(np.floor(x[d] / h[d]).astype(np.int64), 0, n[d] - 1) for d in range(3)]
+    return ijk[0] + n[0] * (ijk[1] + n[1] * ijk[2])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fused_pass_full_size_sampled(E, O, plasma, prec):
+    from paper_2603_16624_amd import inputs as I
+    p = plasma
+    say("full-size fused pass", prec, p.name)
+    En, BN, Bnext = node_fields(p)
+    grid = E.Grid(p.n, p.h, p.dt)
+    if prec == "f64":
+        sp = [E.Species.from_f64(s.qom, s.x, s.v, s.q) for s in p.species]
+        xs, vs, qs = [s.x for s in p.species], [s.v for s in p.species], [s.q for s in p.species]
+        Ec, Bc, Bnc = En, BN, Bnext
+        tdt = torch.float64
+    else:
+        st = I.to_f32_state(p)
+        sp = [E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"]) for s, f in zip(p.species, st)]
+        xs, vs, qs = [f["x64"] for f in st], [f["v64"] for f in st], [f["q64"] for f in st]
+        Ec, Bc, Bnc = round32(En), round32(BN), round32(Bnext)
+        tdt = torch.float32
+        del st
+    tol = TOL[prec]
+    # cell grouping, as the benchmark does before its first pass
+    sorted_sp, perms = [], []
+    for s in sp:
+        d = s.empty_like()
+        cs = torch.empty(grid.nn + 1, dtype=torch.int32, device="cuda")
+        perm = torch.empty(s.np, dtype=torch.int32, device="cuda")
+        E.sort(grid, s, d, cs, perm)
+        perms.append(host(perm).astype(np.int64))
+        sorted_sp.append(d)
+    del sp
+    J = torch.empty((3, p.nn), dtype=tdt, device="cuda")
+    M = torch.empty((14, 9, p.nn), dtype=tdt, device="cuda")
+    Ed, Bd, Bnd = dev(Ec, tdt), dev(Bc, tdt), dev(Bnc, tdt)
+    for _ in range(2):
+        E.move_moments(grid, sorted_sp, Ed, Bd, Bnd, J, M)
+    Jg, Mg = host(J), host(M)
+
+    def oracle_twice(s, x, v):
+        for _ in range(2):
+            x, v = O.move(p.n, p.h, p.dt, x, v, s.qom, Ec, Bc)
+        return x, v
+
+    rng = np.random.default_rng(77 + (prec == "f32"))
+    gpu_cells = []
+    for s, sd, x, v, perm in zip(p.species, sorted_sp, xs, vs, perms):
+        # the GPU's state after the two passes, in sorted order
+        if prec == "f64":
+            xg = host(sd.pos)
+        else:
+            xg = I.decode_f32(host(sd.cell), host(sd.pos), p.n, p.h)
+        vg = host(sd.vel)
+        gpu_cells.append(cells_of(xg, p.n, p.h))
+        # sampled particles against the oracle
+        k = rng.choice(s.np, size=min(NSAMPLE, s.np), replace=False)
+        xo, vo = oracle_twice(s, x[:, perm[k]], v[:, perm[k]])
+        assert periodic_rel(xg[:, k], xo, p.L) < tol
+        assert rel(vg[:, k], vo) < tol
+        del xg, vg
+
+    # sampled nodes: the oracle deposits every particle now within one cell of
+    # the 8 cells around them
+    nodes = rng.choice(p.nn, size=NNODES, replace=False)
+    near = np.zeros(p.nn, dtype=bool)
+    nx, ny, nz = p.n
+    for gnode in nodes:
+        gx, gy, gz = gnode % nx, (gnode // nx) % ny, gnode // (nx * ny)
+        for dz in range(-2, 2):
+            for dy in range(-2, 2):
+                for dx in range(-2, 2):
+                    near[(gx + dx) % nx + nx * (((gy + dy) % ny) + ny * ((gz + dz) % nz))] = True
+    Jo = np.zeros((3, p.nn))
+    M27 = np.zeros((27, 9, p.nn))
+    for s, x, v, q, perm, gc in zip(p.species, xs, vs, qs, perms, gpu_cells):
+        idx = perm[np.nonzero(near[gc])[0]]
+        xo, vo = oracle_twice(s, x[:, idx], v[:, idx])
+        O.moments(p.n, p.h, p.dt, xo, vo, q[idx] if np.ndim(q) else q, s.qom, Bnc, Jo, M27)
+    Mo = O.m14(p.n, M27)
+    assert rel(Jg[:, nodes], Jo[:, nodes]) < tol
+    assert rel(Mg[:, :, nodes], Mo[:, :, nodes]) < tol
