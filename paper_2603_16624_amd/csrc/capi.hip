@@ -52,9 +52,8 @@ ecsim_status make_grid(const ecsim_grid* gr, Grid& g) {
   g.dt = gr->dt;
   g.nn = nn;
   g.V = gr->h[0] * gr->h[1] * gr->h[2];
-  g.div_x = FastDiv{(uint32_t)g.nx, 1.0f / (float)g.nx};
-  g.div_xy = FastDiv{(uint32_t)(g.nx * g.ny), 1.0f / (float)((int64_t)g.nx * g.ny)};
-  g.fastdiv = nn < ((int64_t)1 << 24) ? 1 : 0;
+  g.div_x = make_fastdiv((uint32_t)g.nx);
+  g.div_xy = make_fastdiv((uint32_t)((int64_t)g.nx * g.ny));
   return ECSIM_OK;
 }
 

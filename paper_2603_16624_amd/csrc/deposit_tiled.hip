@@ -259,6 +259,7 @@ __host__ __device__ constexpr int pair_class(int k, int a) {
 // kStraySlot the sorted strays, kZeroSlot a zero block (idle lanes). Every
 // pointer is valid, so the loads need no branch.
 constexpr int kZeroSlot = kStraySlot + 1;
+constexpr int kMapCap = 8192;   // grouped pass: largest brick list with a position -> range map
 template <typename T>
 struct PtrSet {
   const T* pos[3];
@@ -336,21 +337,43 @@ __device__ __forceinline__ void fill_tables(const TArgs<T>& args, TSpecies<T>* l
 template <typename T>
 using LdsPtrSet = const __attribute__((address_space(3))) PtrSet<T>;
 
-template <typename T>
-__device__ __forceinline__ PData<T> load_dep(LdsPtrSet<T>* lptr, const int* cnt, const int* beg, int total,
-                                             int ip) {
-  PData<T> d;
-  d.ok = ip < total;
-  int slot = 0, idx = ip, p = beg[0] + ip;
+// A cell's particle list is its slots' ranges back to back: list position ip
+// lies in slot k when end[k-1] <= ip < end[k], at particle beg[k] + ip - end[k-1].
+// With dlt[k] = beg[k] - end[k-1] stored as d0 = dlt[0] and the steps
+// inc[k] = dlt[k+1] - dlt[k], the index is ip + d0 + the steps of the ends
+// passed: sums of selects, which the compiler cannot turn into an indexed
+// (private memory) table.
+struct Ranges {
+  int end[kSlots5 - 1], inc[kSlots5 - 1], d0, total;
+};
+
+__device__ __forceinline__ Ranges select_ranges(bool a, const Ranges& x, const Ranges& y) {
+  Ranges r;
 #pragma unroll
-  for (int k = 0; k < kSlots5 - 1; ++k)
-    if (slot == k && idx >= cnt[k]) {   // constant indices only: no private memory
-      idx -= cnt[k];
-      slot = k + 1;
-      p = beg[k + 1] + idx;
-    }
+  for (int k = 0; k < kSlots5 - 1; ++k) {
+    r.end[k] = a ? x.end[k] : y.end[k];
+    r.inc[k] = a ? x.inc[k] : y.inc[k];
+  }
+  r.d0 = a ? x.d0 : y.d0;
+  r.total = a ? x.total : y.total;
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ PData<T> load_dep(LdsPtrSet<T>* lptr, const Ranges& r, int ip) {
+  PData<T> d;
+  d.ok = ip < r.total;
+  // slot and particle index by compares against the slot ends (branch-free;
+  // constant indices only, so no private memory)
+  int slot = 0, dl = r.d0;
+#pragma unroll
+  for (int k = 0; k < kSlots5 - 1; ++k) {
+    const bool past = ip >= r.end[k];
+    slot += past ? 1 : 0;
+    dl += past ? r.inc[k] : 0;
+  }
   const int ts = d.ok ? slot : kZeroSlot;
-  const int pi = d.ok ? p : 0;
+  const int pi = d.ok ? ip + dl : 0;
   LdsPtrSet<T>& P = lptr[ts];   // LDS reads (a generic pointer would make them flat loads)
   // raw loads only: nothing here may use a loaded value, or the compiler
   // waits for the loads at once (see dep_species, dep_charge)
@@ -413,10 +436,6 @@ __device__ __forceinline__ void brick_origin(int ntx, int nty, int ntz, int& x0,
 struct RangeLd {
   int lo[kSlots5], hi[kSlots5];
 };
-struct Ranges {
-  int cnt[kSlots5], beg[kSlots5], total;
-};
-
 template <typename T, int NSLOT>
 __device__ __forceinline__ RangeLd load_ranges(const TArgs<T>& args, const TSpecies<T>* lsp, const BrickCell& c) {
   RangeLd r{};
@@ -436,14 +455,20 @@ __device__ __forceinline__ RangeLd load_ranges(const TArgs<T>& args, const TSpec
 
 template <typename T, int NSLOT>
 __device__ __forceinline__ Ranges make_ranges(const TArgs<T>& args, const RangeLd& r, const BrickCell& c) {
-  Ranges q{};
+  static_assert(NSLOT == kSlots5, "ranges cover every slot");
+  Ranges q;
+  int e = 0, prev = 0;
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
     const bool used = s == kStraySlot || s < args.ns;
-    q.beg[s] = r.lo[s];
-    q.cnt[s] = (c.valid && used) ? r.hi[s] - r.lo[s] : 0;
-    q.total += q.cnt[s];
+    const int dlt = r.lo[s] - e;
+    if (s == 0) q.d0 = dlt;
+    else q.inc[s - 1] = dlt - prev;
+    prev = dlt;
+    e += (c.valid && used) ? r.hi[s] - r.lo[s] : 0;
+    if (s < NSLOT - 1) q.end[s] = e;
   }
+  q.total = e;
   return q;
 }
 
@@ -508,7 +533,7 @@ __device__ __forceinline__ void flush_brick(const Grid& g, const T* scell, int x
       if (lcx >= 0 && lcx < TX && lcy >= 0 && lcy < TY && lcz >= 0 && lcz < TZ) vmask |= 1 << a;
     }
     const int cbase = nx_ + TX * (ny_ + TY * nz_);          // cell index of n (may lie outside)
-    const int gx = (x0 + nx_) % g.nx, gy = (y0 + ny_) % g.ny, gz = (z0 + nz_) % g.nz;
+    const int gx = wrap_once(x0 + nx_, g.nx), gy = wrap_once(y0 + ny_, g.ny), gz = wrap_once(z0 + nz_, g.nz);
     const int64_t gn = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
     if (is_m) {
 #pragma unroll
@@ -578,9 +603,12 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   __shared__ int roff[NR + 1];
   __shared__ int wsum[NW];
   __shared__ double red[NW];
-  __shared__ int wst[NW];
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
+  __shared__ int wst[NW];
   __shared__ void* lsink;   // in LDS beside the species table: selects between them stay LDS reads
+  // list position -> range, for bricks of at most kMapCap particles
+  __shared__ uint8_t rmap[kMapCap];
+  static_assert(NR <= 256, "range indices fit a byte");
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -627,39 +655,52 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   }
   __syncthreads();
   const int total = roff[NR];
+  const bool mapped = total <= kMapCap;   // workgroup-uniform
+  if (mapped && tid < NR) {
+    const int a = roff[tid];
+    for (int i = 0; i < n; ++i) rmap[a + i] = (uint8_t)tid;
+  }
+  __syncthreads();
   double kel = 0.0;
   StrayBuf<T> sb;
 
-  // flat index i -> (range, particle); the last range with roff <= i is the
-  // non-empty one holding i
+  // flat index i -> (range, particle): from the map, else the last range with
+  // roff <= i (the non-empty one holding i) by binary search
   auto locate = [&](int i, int& r) -> PData<T> {
-    PData<T> d{};
+    // Branch-free: a position past the list reads the last particle (never
+    // stored back: ok is false), so every lane issues the same loads into
+    // the same registers. Needs total > 0.
+    PData<T> d;
     d.ok = i < total;
-    r = 0;
-    if (d.ok) {
-      int lo = 0, hi = NR - 1;
+    const int ic = d.ok ? i : total - 1;
+    int lo = 0;
+    if (mapped) {   // workgroup-uniform
+      lo = rmap[ic];
+    } else {
+      int hi = NR - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (roff[mid] <= i) lo = mid;
+        if (roff[mid] <= ic) lo = mid;
         else hi = mid - 1;
       }
-      r = lo;
-      const int s = lo % kMaxTiledSpecies;
-      const int p = rbeg[lo] + (i - roff[lo]);
-      const TSpecies<T>& sp = lsp[s];
-      d.s = s;
-      d.p = p;
-      d.x0 = gld(sp.pos[0] + p);
-      d.x1 = gld(sp.pos[1] + p);
-      d.x2 = gld(sp.pos[2] + p);
-      d.v0 = gld(sp.vel[0] + p);
-      d.v1 = gld(sp.vel[1] + p);
-      d.v2 = gld(sp.vel[2] + p);
-      // raw charge (0 for a constant-charge species, whose charge is added at
-      // use): a select into the loaded register would make the compiler wait
-      d.q = gld((sp.q ? sp.q : (const T*)args.zero) + (sp.q ? p : 0));
-      if constexpr (sizeof(T) == 4) d.c = gld(sp.cell + p);
     }
+    r = lo;
+    const int s = lo % kMaxTiledSpecies;
+    const int p = rbeg[lo] + (ic - roff[lo]);
+    const TSpecies<T>& sp = lsp[s];
+    d.s = s;
+    d.p = p;
+    d.x0 = gld(sp.pos[0] + p);
+    d.x1 = gld(sp.pos[1] + p);
+    d.x2 = gld(sp.pos[2] + p);
+    d.v0 = gld(sp.vel[0] + p);
+    d.v1 = gld(sp.vel[1] + p);
+    d.v2 = gld(sp.vel[2] + p);
+    // raw charge (0 for a constant-charge species, whose charge is added at
+    // use): a select into the loaded register would make the compiler wait
+    d.q = gld((sp.q ? sp.q : (const T*)args.zero) + (sp.q ? p : 0));
+    if constexpr (sizeof(T) == 4) d.c = gld(sp.cell + p);
+    else d.c = 0;
     return d;
   };
 
@@ -682,9 +723,9 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
     int lcell;
     if constexpr (MOVE) {
       // local cell in the halo'd box (periodic)
-      const int dx = (ps.i[0] - x0 + 1 + g.nx) % g.nx;
-      const int dy = (ps.i[1] - y0 + 1 + g.ny) % g.ny;
-      const int dz = (ps.i[2] - z0 + 1 + g.nz) % g.nz;
+      const int dx = wrap_once(ps.i[0] - x0 + 1, g.nx);
+      const int dy = wrap_once(ps.i[1] - y0 + 1, g.ny);
+      const int dz = wrap_once(ps.i[2] - z0 + 1, g.nz);
       const bool inbox = pd.ok && dx <= TX + 1 && dy <= TY + 1 && dz <= TZ + 1;
       const int lx = inbox ? dx : 0, ly = inbox ? dy : 0, lz = inbox ? dz : 0;
       Vec3<T> Ep{T(0), T(0), T(0)}, Bp{T(0), T(0), T(0)};
@@ -753,7 +794,9 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
     if (stray) sb.push(item, lcell, rec);
   };
 
-  if constexpr (sizeof(T) == 4) {
+  if (total == 0) {
+    // no particles in the brick: nothing to move or list
+  } else if constexpr (sizeof(T) == 4) {
     // two blocks of 64 per wavefront and iteration, the next two blocks'
     // loads in flight while these are processed
     int ra, rb;
@@ -763,27 +806,35 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
     // load from before the loop is pending (else the compiler waits for all
     // loads, the next blocks' included, at the first use)
     __builtin_amdgcn_s_waitcnt(0);
-    for (int base = wave * 128; base < total; base += 2 * NT) {
-      int rna, rnb;
-      const PData<T> na = locate(base + 2 * NT + lane, rna);
-      const PData<T> nb = locate(base + 2 * NT + 64 + lane, rnb);
+    // unrolled once more, so that the two register sets swap roles instead
+    // of being copied (a copy of a loaded register waits for its load)
+    int rna, rnb;
+    PData<T> na, nb;
+    for (int base = wave * 128; base < total;) {
+      na = locate(base + 2 * NT + lane, rna);
+      nb = locate(base + 2 * NT + 64 + lane, rnb);
       process(pa, ra);
       process(pb, rb);
-      pa = na;
-      ra = rna;
-      pb = nb;
-      rb = rnb;
+      base += 2 * NT;
+      if (base >= total) break;   // workgroup-uniform
+      pa = locate(base + 2 * NT + lane, ra);
+      pb = locate(base + 2 * NT + 64 + lane, rb);
+      process(na, rna);
+      process(nb, rnb);
+      base += 2 * NT;
     }
   } else {
     // FP64: one block per iteration (its registers allow no second)
-    int ra;
-    PData<T> pa = locate(wave * 64 + lane, ra);
-    for (int base = wave * 64; base < total; base += NT) {
-      int rna;
-      const PData<T> na = locate(base + NT + lane, rna);
+    int ra, rna;
+    PData<T> pa = locate(wave * 64 + lane, ra), na;
+    for (int base = wave * 64; base < total;) {
+      na = locate(base + NT + lane, rna);
       process(pa, ra);
-      pa = na;
-      ra = rna;
+      base += NT;
+      if (base >= total) break;
+      pa = locate(base + NT + lane, ra);
+      process(na, rna);
+      base += NT;
     }
   }
   if constexpr (MOVE) {
@@ -817,7 +868,6 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   __syncthreads();
   write_strays(args, lane, wst[wave], k0, sb.item0, sb.cell0, sb.r0, k1, sb.item1, sb.cell1, sb.r1);
 }
-
 // ---------------------------------------------------------------------------
 // tiled deposit
 // ---------------------------------------------------------------------------
@@ -871,7 +921,7 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
   BrickCell pc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, 2 * wave + half);
   T sv = load_stage(pc);
   Ranges rg = make_ranges<T, kSlots5>(args, load_ranges<T, kSlots5>(args, lsp, pc), pc);
-  PData<T> pd = load_dep<T>(lptr, rg.cnt, rg.beg, rg.total, hl);
+  PData<T> pd = load_dep<T>(lptr, rg, hl);
 
   for (int pair = wave; pair < NPAIR; pair += NW) {
     const bool has_next = pair + NW < NPAIR;   // wave-uniform
@@ -891,7 +941,7 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
     if (cmax == 0) {   // wave-uniform: both cells empty
       if (has_next) {
         rg = make_ranges<T, kSlots5>(args, nrl, nc);
-        pd = load_dep<T>(lptr, rg.cnt, rg.beg, rg.total, hl);
+        pd = load_dep<T>(lptr, rg, hl);
       }
       pc = nc;
       sv = nsv;
@@ -901,9 +951,8 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
     if (hl < 24) stage[hl] = sv;
     wave_sync();
 
-    // running sums of the two cells: [cell][tile][reg]; matrix-core block sums
+    // running sums of the two cells: [cell][tile][reg]
     T S[2][2][4], C[2][2][4];
-    acc_t dA0 = {0, 0, 0, 0}, dA1 = {0, 0, 0, 0}, dB0 = {0, 0, 0, 0}, dB1 = {0, 0, 0, 0};
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -911,7 +960,9 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
 #pragma unroll
         for (int r = 0; r < 4; ++r) { S[h][t][r] = T(0); C[h][t][r] = T(0); }
 
-    for (int ch = 0; ch < cmax; ch += 32) {
+    // One block of 32 particles per cell: records to LDS, the next block's
+    // loads issued, then 8 matrix-core steps over the records.
+    auto block = [&](int cb, bool fresh, acc_t& dA0, acc_t& dA1, acc_t& dB0, acc_t& dB1) {
       // ---- 1. particle lanes: one record column per lane ----
       // Every lane runs the same arithmetic; lanes whose particle is not in
       // the cell (or that hold none) carry zero charge, so zero values.
@@ -934,19 +985,13 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
       }
       wave_sync();
       // prefetch the next block (of this pair, else of the next pair) while
-      // this block is reduced: one unconditional load site, so that the
-      // loads stay in flight until the next block uses them
-      const bool same = ch + 32 < cmax;   // wave-uniform
+      // this block is reduced: one load site, so that the loads stay in
+      // flight until the next block uses them
+      const bool same = cb + 32 < cmax;   // wave-uniform
       if (!same && has_next) rg = make_ranges<T, kSlots5>(args, nrl, nc);
-      {
-        const Ranges& nr = same ? cr : rg;
-        pd = load_dep<T>(lptr, nr.cnt, nr.beg, nr.total, same ? ch + 32 + hl : hl);
-      }
-
+      pd = load_dep<T>(lptr, select_ranges(same, cr, rg), same ? cb + 32 + hl : hl);
       // ---- 2. matrix cores: S[value][class] += sum over 4 particles per step ----
       // records past a cell's count are zero, so all 8 steps of a block run
-      // the matrix cores accumulate two blocks (64 particles) before the
-      // running sums take them with Kahan compensation
 #pragma unroll
       for (int k4 = 0; k4 < 32; k4 += 4) {
         const T aA = opnd[k4];
@@ -955,27 +1000,38 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
         const T bB0 = opnd[12 * kSlots + 32 + k4];
         const T bA1 = opnd[28 * kSlots + k4];
         const T bB1 = opnd[28 * kSlots + 32 + k4];
-        dA0 = MF::run(aA, bA0, dA0);
-        dB0 = MF::run(aB, bB0, dB0);
-        dA1 = MF::run(aA, bA1, dA1);
-        dB1 = MF::run(aB, bB1, dB1);
+        const acc_t z = {0, 0, 0, 0};
+        const bool f0 = fresh && k4 == 0;
+        dA0 = MF::run(aA, bA0, f0 ? z : dA0);
+        dB0 = MF::run(aB, bB0, f0 ? z : dB0);
+        dA1 = MF::run(aA, bA1, f0 ? z : dA1);
+        dB1 = MF::run(aB, bB1, f0 ? z : dB1);
       }
-      if (((ch >> 5) & 1) || ch + 32 >= cmax) {   // wave-uniform
+    };
+
+    // Superblocks of 64 particles per cell: the matrix cores start from zero
+    // and take up to two blocks, then the running sums take the superblock
+    // sums (FP32 with Kahan compensation).
+    for (int ch = 0; ch < cmax; ch += 64) {
+      acc_t dA0, dA1, dB0, dB1;
+      block(ch, true, dA0, dA1, dB0, dB1);
+      if (ch + 32 < cmax) {   // wave-uniform
+        wave_sync();
+        block(ch + 32, false, dA0, dA1, dB0, dB1);
+      }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if constexpr (sizeof(T) == 4) {
-            kahan(S[0][0][q], C[0][0][q], dA0[q]);
-            kahan(S[0][1][q], C[0][1][q], dA1[q]);
-            kahan(S[1][0][q], C[1][0][q], dB0[q]);
-            kahan(S[1][1][q], C[1][1][q], dB1[q]);
-          } else {
-            S[0][0][q] += dA0[q];
-            S[0][1][q] += dA1[q];
-            S[1][0][q] += dB0[q];
-            S[1][1][q] += dB1[q];
-          }
+      for (int q = 0; q < 4; ++q) {
+        if constexpr (sizeof(T) == 4) {
+          kahan(S[0][0][q], C[0][0][q], dA0[q]);
+          kahan(S[0][1][q], C[0][1][q], dA1[q]);
+          kahan(S[1][0][q], C[1][0][q], dB0[q]);
+          kahan(S[1][1][q], C[1][1][q], dB1[q]);
+        } else {
+          S[0][0][q] += dA0[q];
+          S[0][1][q] += dA1[q];
+          S[1][0][q] += dB0[q];
+          S[1][1][q] += dB1[q];
         }
-        dA0 = dA1 = dB0 = dB1 = acc_t{0, 0, 0, 0};
       }
       wave_sync();
     }
@@ -1036,62 +1092,72 @@ __global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
   __syncthreads();
   const int n = *args.stray_count;
   double kel = 0.0;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const int item = args.stray_item[i];
-    if (!(item & kUnmoved)) continue;
-    const int s = (item >> kItemShift) & (kMaxTiledSpecies - 1);
-    const int p = item & kIndexMask;
-    const TSpecies<T>& sp = lsp[s];
-    const StrayData<T>& ul = args.ul;   // the listed (current) state
-    const T q = ul.q[i];
-    const T x0 = ul.pos[0][i], x1 = ul.pos[1][i], x2 = ul.pos[2][i];
-    Stencil<T> ps = particle_stencil<T>(g, x0, x1, x2, ul.cell[i]);
-    T W[8];
-    int64_t nd[8];
-    corners(g, ps, W, nd);
-    const Vec3<T> Ep = gather(args.Emove, g.nn, W, nd);
-    const Vec3<T> Bp = gather(args.Bmove, g.nn, W, nd);
-    T a0[9];
-    rotation(Bp, sp.beta, a0);
-    Vec3<T> u;
-    const Vec3<T> v = velocity_update(a0, Vec3<T>{ul.vel[0][i], ul.vel[1][i], ul.vel[2][i]}, Ep, sp.beta, u);
-    T n0, n1, n2;
-    int ncell;
-    if constexpr (sizeof(T) == 4) {
-      int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
-      n0 = push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx);
-      n1 = push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny);
-      n2 = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
-      ncell = ix + g.nx * (iy + g.ny * iz);
-      gst(sp.cell + p, ncell);
-    } else {
-      n0 = push_abs(x0, g.dt, v.x, g.nx * g.hx);
-      n1 = push_abs(x1, g.dt, v.y, g.ny * g.hy);
-      n2 = push_abs(x2, g.dt, v.z, g.nz * g.hz);
-      const Stencil<double> nps = stencil_abs(g, n0, n1, n2);
-      ncell = nps.i[0] + g.nx * (nps.i[1] + g.ny * nps.i[2]);
-    }
-    gst(sp.pos[0] + p, n0);
-    gst(sp.pos[1] + p, n1);
-    gst(sp.pos[2] + p, n2);
-    gst(sp.vel[0] + p, v.x);
-    gst(sp.vel[1] + p, v.y);
-    gst(sp.vel[2] + p, v.z);
-    ul.pos[0][i] = n0;
-    ul.pos[1][i] = n1;
-    ul.pos[2][i] = n2;
-    ul.vel[0][i] = v.x;
-    ul.vel[1][i] = v.y;
-    ul.vel[2][i] = v.z;
-    ul.cell[i] = ncell;
-    // back in its range's cell: the deposit takes it from the range, so it
-    // leaves the list (cell -1)
-    const int range_cell = args.stray_cell[i];
-    args.stray_cell[i] = ncell == range_cell ? -1 : ncell;
-    args.stray_item[i] = item & ~kUnmoved;
-    if (args.ke) {
-      const double vx = v.x, vy = v.y, vz = v.z;
-      kel += 0.5 * ((double)q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz);
+  // four entries per thread and pass: their item loads are in flight together
+  // (most entries need no move, so the loads set the pace)
+  const int stride = gridDim.x * 256;
+  for (int i0 = blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += 4 * stride) {
+    int items[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) items[e] = i0 + e * stride < n ? args.stray_item[i0 + e * stride] : 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = i0 + e * stride;
+      const int item = items[e];
+      if (!(item & kUnmoved)) continue;
+      const int s = (item >> kItemShift) & (kMaxTiledSpecies - 1);
+      const int p = item & kIndexMask;
+      const TSpecies<T>& sp = lsp[s];
+      const StrayData<T>& ul = args.ul;   // the listed (current) state
+      const T q = ul.q[i];
+      const T x0 = ul.pos[0][i], x1 = ul.pos[1][i], x2 = ul.pos[2][i];
+      Stencil<T> ps = particle_stencil<T>(g, x0, x1, x2, ul.cell[i]);
+      T W[8];
+      int64_t nd[8];
+      corners(g, ps, W, nd);
+      const Vec3<T> Ep = gather(args.Emove, g.nn, W, nd);
+      const Vec3<T> Bp = gather(args.Bmove, g.nn, W, nd);
+      T a0[9];
+      rotation(Bp, sp.beta, a0);
+      Vec3<T> u;
+      const Vec3<T> v = velocity_update(a0, Vec3<T>{ul.vel[0][i], ul.vel[1][i], ul.vel[2][i]}, Ep, sp.beta, u);
+      T n0, n1, n2;
+      int ncell;
+      if constexpr (sizeof(T) == 4) {
+        int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
+        n0 = push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx);
+        n1 = push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny);
+        n2 = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
+        ncell = ix + g.nx * (iy + g.ny * iz);
+        gst(sp.cell + p, ncell);
+      } else {
+        n0 = push_abs(x0, g.dt, v.x, g.nx * g.hx);
+        n1 = push_abs(x1, g.dt, v.y, g.ny * g.hy);
+        n2 = push_abs(x2, g.dt, v.z, g.nz * g.hz);
+        const Stencil<double> nps = stencil_abs(g, n0, n1, n2);
+        ncell = nps.i[0] + g.nx * (nps.i[1] + g.ny * nps.i[2]);
+      }
+      gst(sp.pos[0] + p, n0);
+      gst(sp.pos[1] + p, n1);
+      gst(sp.pos[2] + p, n2);
+      gst(sp.vel[0] + p, v.x);
+      gst(sp.vel[1] + p, v.y);
+      gst(sp.vel[2] + p, v.z);
+      ul.pos[0][i] = n0;
+      ul.pos[1][i] = n1;
+      ul.pos[2][i] = n2;
+      ul.vel[0][i] = v.x;
+      ul.vel[1][i] = v.y;
+      ul.vel[2][i] = v.z;
+      ul.cell[i] = ncell;
+      // back in its range's cell: the deposit takes it from the range, so it
+      // leaves the list (cell -1)
+      const int range_cell = args.stray_cell[i];
+      args.stray_cell[i] = ncell == range_cell ? -1 : ncell;
+      args.stray_item[i] = item & ~kUnmoved;
+      if (args.ke) {
+        const double vx = v.x, vy = v.y, vz = v.z;
+        kel += 0.5 * ((double)q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz);
+      }
     }
   }
   if (args.ke) {
@@ -1112,29 +1178,57 @@ __global__ void __launch_bounds__(256) k_stray_rank(const int* __restrict__ coun
                                                     int* __restrict__ counts, int* __restrict__ ranks) {
   // one returning atomic per stray, all lanes at once: strays of a wavefront
   // mostly lie in different cells, so a per-key leader loop would serialise
+  // (four entries per thread and pass, their atomics in flight together)
   const int n = *count;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const int c = cellv[i];
-    if (c >= 0) ranks[i] = atomicAdd(&counts[c], 1);   // entries with cell -1 have left the list
+  const int stride = gridDim.x * 256;
+  for (int i0 = blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += 4 * stride) {
+    int c[4], r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = i0 + u * stride < n ? cellv[i0 + u * stride] : -1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) r[u] = c[u] >= 0 ? atomicAdd(&counts[c[u]], 1) : 0;   // cell -1: not listed
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (c[u] >= 0) ranks[i0 + u * stride] = r[u];
   }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_stray_scatter(TArgs<T> args, const int* __restrict__ ranks) {
+  // two entries per thread and pass, their loads in flight together
   const int n = *args.stray_count;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const int c = args.stray_cell[i];
-    if (c < 0) continue;
-    const int o = args.ind_start[c] + ranks[i];
-    const StrayData<T>& u = args.ul;
-    const StrayData<T>& d = args.sd;
-    for (int k = 0; k < 3; ++k) {
-      d.pos[k][o] = u.pos[k][i];
-      d.vel[k][o] = u.vel[k][i];
+  const int stride = gridDim.x * 256;
+  const StrayData<T>& u = args.ul;
+  const StrayData<T>& d = args.sd;
+  for (int i0 = blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += 2 * stride) {
+    int c[2], o[2], sp[2], cl[2];
+    T v[2][7];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) c[h] = i0 + h * stride < n ? args.stray_cell[i0 + h * stride] : -1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = c[h] >= 0 ? i0 + h * stride : 0;
+      const int cc = c[h] >= 0 ? c[h] : 0;
+      o[h] = args.ind_start[cc] + ranks[i];
+      for (int k = 0; k < 3; ++k) {
+        v[h][k] = u.pos[k][i];
+        v[h][3 + k] = u.vel[k][i];
+      }
+      v[h][6] = u.q[i];
+      cl[h] = u.cell[i];
+      sp[h] = (args.stray_item[i] >> kItemShift) & (kMaxTiledSpecies - 1);
     }
-    d.q[o] = u.q[i];
-    d.cell[o] = u.cell[i];
-    d.sp[o] = (args.stray_item[i] >> kItemShift) & (kMaxTiledSpecies - 1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (c[h] < 0) continue;
+      for (int k = 0; k < 3; ++k) {
+        d.pos[k][o[h]] = v[h][k];
+        d.vel[k][o[h]] = v[h][3 + k];
+      }
+      d.q[o[h]] = v[h][6];
+      d.cell[o[h]] = cl[h];
+      d.sp[o[h]] = sp[h];
+    }
   }
 }
 

@@ -13,19 +13,35 @@
 
 namespace ecsim {
 
-// Division by a runtime constant for numerators below 2^24: a float
-// reciprocal estimate, off by at most one, corrected with one remainder test.
+// Exact division by a runtime constant d >= 1 for numerators below 2^31
+// (every cell index): with L = ceil(log2 d) and m = ceil(2^(31+L) / d), which
+// lies in [2^31, 2^32), n / d is the high word of n m shifted right by L - 1.
+// The rounding error of m adds less than n / 2^(31+L) < 1/d to n / d, too
+// little to cross an integer. d = 1 passes n through. Branch-free: one
+// multiply-high and a shift in place of the division sequence.
 struct FastDiv {
-  uint32_t d;
-  float inv;
+  uint32_t d, m;
+  int s;
 };
 
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f{d, 0u, 0};
+  if (d > 1) {
+    int L = 0;
+    while ((1ull << L) < d) ++L;
+    f.m = (uint32_t)(((1ull << (31 + L)) + d - 1) / d);
+    f.s = L - 1;
+  }
+  return f;
+}
+
+__device__ __forceinline__ uint32_t fast_div(uint32_t n, FastDiv f) {
+  return f.d == 1 ? n : (__umulhi(n, f.m) >> f.s);
+}
+
 __device__ __forceinline__ uint32_t fast_divmod(uint32_t n, FastDiv f, uint32_t& r) {
-  uint32_t q = (uint32_t)((float)n * f.inv);
-  int32_t rr = (int32_t)(n - q * f.d);
-  if (rr < 0) { q -= 1; rr += (int32_t)f.d; }
-  else if (rr >= (int32_t)f.d) { q += 1; rr -= (int32_t)f.d; }
-  r = (uint32_t)rr;
+  const uint32_t q = fast_div(n, f);
+  r = n - q * f.d;
   return q;
 }
 
@@ -36,7 +52,6 @@ struct Grid {
   double V;          // control volume of a node
   FastDiv div_x;     // by nx
   FastDiv div_xy;    // by nx * ny
-  int fastdiv;       // nn < 2^24: cell indices decode with FastDiv
 };
 
 template <typename T> struct Vec3 { T x, y, z; };
@@ -52,6 +67,12 @@ struct Stencil {
 };
 
 __device__ __forceinline__ int wrap_up(int i, int n) { return (i + 1 == n) ? 0 : i + 1; }
+
+// i in [-n, 2n) taken periodically into [0, n)
+__device__ __forceinline__ int wrap_once(int i, int n) {
+  i += i < 0 ? n : 0;
+  return i >= n ? i - n : i;
+}
 
 // FP64 form: absolute position in [0, L).
 __device__ __forceinline__ Stencil<double> stencil_abs(const Grid& g, double x, double y, double z) {
@@ -77,17 +98,10 @@ __device__ __forceinline__ Stencil<double> stencil_abs(const Grid& g, double x, 
 
 // FP32 form: int32 cell index + in-cell offsets in [0, 1).
 __device__ __forceinline__ void decode_cell(const Grid& g, int cell, int& ix, int& iy, int& iz) {
-  if (g.fastdiv) {
-    uint32_t r, r2;
-    iz = (int)fast_divmod((uint32_t)cell, g.div_xy, r);
-    iy = (int)fast_divmod(r, g.div_x, r2);
-    ix = (int)r2;
-  } else {
-    ix = cell % g.nx;
-    int t = cell / g.nx;
-    iy = t % g.ny;
-    iz = t / g.ny;
-  }
+  uint32_t r, r2;
+  iz = (int)fast_divmod((uint32_t)cell, g.div_xy, r);
+  iy = (int)fast_divmod(r, g.div_x, r2);
+  ix = (int)r2;
 }
 
 __device__ __forceinline__ Stencil<float> stencil_cell(const Grid& g, int cell, float ox, float oy, float oz) {
@@ -148,7 +162,11 @@ template <typename T>
 __device__ __forceinline__ void rotation(Vec3<T> B, T beta, T a[9]) {
   T bx = beta * B.x, by = beta * B.y, bz = beta * B.z;
   T den = T(1) + ((bx * bx + by * by) + bz * bz);
-  T inv = T(1) / den;
+  // FP32: the hardware reciprocal (1 ulp) in place of the correctly rounded
+  // division sequence; FP64 divides
+  T inv;
+  if constexpr (sizeof(T) == 4) inv = __builtin_amdgcn_rcpf(den);
+  else inv = T(1) / den;
   a[0] = (T(1) + bx * bx) * inv;
   a[1] = (bx * by + bz) * inv;
   a[2] = (bx * bz - by) * inv;
@@ -197,7 +215,9 @@ __device__ __forceinline__ float push_offset(float o, float v, float dth, int& i
   int shift = (int)fl;
   if (r >= 1.0f) { r = 0.0f; shift += 1; }
   int j = idx + shift;
-  if (j < 0 || j >= n) {
+  j += j < 0 ? n : 0;        // one period either way without a division
+  j -= j >= n ? n : 0;
+  if (j < 0 || j >= n) {     // more than one period in a step
     j %= n;
     if (j < 0) j += n;
   }

@@ -24,9 +24,8 @@ __global__ void __launch_bounds__(kBlock) k_mass_apply(Grid g, const TM* __restr
   const int64_t nn = g.nn;
   const int64_t gid = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (gid >= nn) return;
-  const int ix = (int)(gid % g.nx);
-  const int iy = (int)((gid / g.nx) % g.ny);
-  const int iz = (int)(gid / ((int64_t)g.nx * g.ny));
+  int ix, iy, iz;
+  decode_cell(g, (int)gid, ix, iy, iz);
   double y0 = 0.0, y1 = 0.0, y2 = 0.0;
 #pragma unroll
   for (int k = 0; k < 14; ++k) {
@@ -79,7 +78,8 @@ __global__ void __launch_bounds__(kBlock) k_curl_C(Grid g, const double* __restr
   const int64_t nn = g.nn;
   const int64_t c = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (c >= nn) return;
-  const int cx = (int)(c % g.nx), cy = (int)((c / g.nx) % g.ny), cz = (int)(c / ((int64_t)g.nx * g.ny));
+  int cx, cy, cz;
+  decode_cell(g, (int)c, cx, cy, cz);
   const int xs[2] = {cx, wp(cx, g.nx)}, ys[2] = {cy, wp(cy, g.ny)}, zs[2] = {cz, wp(cz, g.nz)};
   double d[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // d[axis][component]
 #pragma unroll
@@ -108,7 +108,8 @@ __global__ void __launch_bounds__(kBlock) k_curl_C(Grid g, const double* __restr
 
 __device__ __forceinline__ void curl_N_at(const Grid& g, const double* __restrict__ B, int64_t nd, double r[3]) {
   const int64_t nn = g.nn;
-  const int gx = (int)(nd % g.nx), gy = (int)((nd / g.nx) % g.ny), gz = (int)(nd / ((int64_t)g.nx * g.ny));
+  int gx, gy, gz;
+  decode_cell(g, (int)nd, gx, gy, gz);
   // cells around node g: g - 1 + a
   const int xs[2] = {wm(gx, g.nx), gx}, ys[2] = {wm(gy, g.ny), gy}, zs[2] = {wm(gz, g.nz), gz};
   double d[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -175,7 +176,8 @@ __global__ void __launch_bounds__(kBlock) k_centres_to_nodes(Grid g, const doubl
                                                              double* __restrict__ BN, float* __restrict__ BN32) {
   const int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (nd >= g.nn) return;
-  const int gx = (int)(nd % g.nx), gy = (int)((nd / g.nx) % g.ny), gz = (int)(nd / ((int64_t)g.nx * g.ny));
+  int gx, gy, gz;
+  decode_cell(g, (int)nd, gx, gy, gz);
   const int xs[2] = {wm(gx, g.nx), gx}, ys[2] = {wm(gy, g.ny), gy}, zs[2] = {wm(gz, g.nz), gz};
   for (int comp = 0; comp < 3; ++comp) {
     double s = 0.0;
