@@ -126,73 +126,78 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// A stray's state as listed: position (FP32: in-cell offsets), velocity,
-// charge and cell.
+// A particle's state as the mover writes it back: position (FP32: in-cell
+// offsets), velocity, charge and cell.
 template <typename T>
 struct SRec {
   T x0, x1, x2, v0, v1, v2, q;
   int c;
 };
 
-template <typename TA, typename T>
-__device__ __forceinline__ void put_stray(const TA& args, int pos, int item, int cell, const SRec<T>& r) {
-  args.stray_item[pos] = item;
-  args.stray_cell[pos] = cell;
-  const StrayData<T>& u = args.ul;
-  u.pos[0][pos] = r.x0;
-  u.pos[1][pos] = r.x1;
-  u.pos[2][pos] = r.x2;
-  u.vel[0][pos] = r.v0;
-  u.vel[1][pos] = r.v1;
-  u.vel[2][pos] = r.v2;
-  u.q[pos] = r.q;
-  u.cell[pos] = r.c;
-}
+// A wavefront's strays (item, cell and state) collect in LDS and go to the
+// list in list order when the buffer is full (one returning atomic per
+// kWaveList entries) and at the end (one atomic per workgroup).
+constexpr int kWaveList = 128;
 
-// Writes the strays a wavefront keeps (per lane: slot 0 if k0, slot 1 if k1)
-// to the list at base, or, for base < 0, at a place reserved with one atomic.
-// Reached by the whole wavefront.
-template <typename TA, typename T>
-__device__ __forceinline__ void write_strays(const TA& args, int lane, int base, bool k0, int i0, int c0,
-                                             const SRec<T>& r0, bool k1, int i1, int c1, const SRec<T>& r1) {
-  const unsigned long long b0 = __ballot(k0), b1 = __ballot(k1);
-  if (base < 0) {
-    int r = 0;
-    if (lane == 0) r = atomicAdd(args.stray_count, __popcll(b0) + __popcll(b1));
-    base = __shfl(r, 0);
-  }
-  const unsigned long long below = (1ull << lane) - 1ull;
-  int pos = base + __popcll(b0 & below) + __popcll(b1 & below);
-  if (k0) {
-    put_stray(args, pos, i0, c0, r0);
-    ++pos;
-  }
-  if (k1) put_stray(args, pos, i1, c1, r1);
-}
-
-// Per-lane holding slots for strays (item, cell, state). When a lane needs a
-// third slot the whole wavefront empties its slots into the list.
 template <typename T>
-struct StrayBuf {
-  int n = 0;
-  int item0 = 0, cell0 = 0, item1 = 0, cell1 = 0;
-  SRec<T> r0{}, r1{};
-  __device__ __forceinline__ void push(int item, int cell, const SRec<T>& r) {
-    if (n == 0) {
-      item0 = item;
-      cell0 = cell;
-      r0 = r;
-    } else {
-      item1 = item;
-      cell1 = cell;
-      r1 = r;
-    }
-    ++n;
-  }
+struct WaveBuf {
+  int item[kWaveList];
+  int cell[kWaveList];
+  T val[7][kWaveList];   // pos[3], vel[3], q
+  int vcell[kWaveList];
+};
+
+template <typename T>
+struct WaveStrays {
+  int fill = 0;   // wavefront-uniform
+
+  // copies the buffer's first fill entries to the list at base
   template <typename TA>
-  __device__ __forceinline__ void flush(const TA& args, int lane) {
-    write_strays(args, lane, -1, n >= 1, item0, cell0, r0, n >= 2, item1, cell1, r1);
-    n = 0;
+  __device__ __forceinline__ void copy_out(const TA& args, const WaveBuf<T>& b, int lane, int base) const {
+    const StrayData<T>& u = args.ul;
+    for (int i = lane; i < fill; i += 64) {
+      const int o = base + i;
+      args.stray_item[o] = b.item[i];
+      args.stray_cell[o] = b.cell[i];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        u.pos[k][o] = b.val[k][i];
+        u.vel[k][o] = b.val[3 + k][i];
+      }
+      u.q[o] = b.val[6][i];
+      u.cell[o] = b.vcell[i];
+    }
+  }
+
+  // lists the lanes with stray set (reached by the whole wavefront)
+  template <typename TA>
+  __device__ __forceinline__ void put(const TA& args, WaveBuf<T>& b, int lane, bool stray, int item, int cell,
+                                      const SRec<T>& r) {
+    const unsigned long long bal = __ballot(stray);
+    const int nst = __popcll(bal);
+    if (nst == 0) return;
+    if (fill + nst > kWaveList) {   // full: to the list
+      int rv = 0;
+      if (lane == 0) rv = atomicAdd(args.stray_count, fill);
+      wave_sync();
+      copy_out(args, b, lane, __builtin_amdgcn_readfirstlane(rv));
+      wave_sync();
+      fill = 0;
+    }
+    if (stray) {
+      const int i = fill + __popcll(bal & ((1ull << lane) - 1ull));
+      b.item[i] = item;
+      b.cell[i] = cell;
+      b.val[0][i] = r.x0;
+      b.val[1][i] = r.x1;
+      b.val[2][i] = r.x2;
+      b.val[3][i] = r.v0;
+      b.val[4][i] = r.v1;
+      b.val[5][i] = r.v2;
+      b.val[6][i] = r.q;
+      b.vcell[i] = r.c;
+    }
+    fill += nst;
   }
 };
 
@@ -605,6 +610,7 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   __shared__ double red[NW];
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
   __shared__ int wst[NW];
+  __shared__ WaveBuf<T> slist[NW];
   __shared__ void* lsink;   // in LDS beside the species table: selects between them stay LDS reads
   // list position -> range, for bricks of at most kMapCap particles
   __shared__ uint8_t rmap[kMapCap];
@@ -662,7 +668,8 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   }
   __syncthreads();
   double kel = 0.0;
-  StrayBuf<T> sb;
+  WaveStrays<T> ws;
+  WaveBuf<T>& wbuf = slist[wave];
 
   // flat index i -> (range, particle): from the map, else the last range with
   // roff <= i (the non-empty one holding i) by binary search
@@ -790,8 +797,7 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
       stray = pd.ok && pcell0 != gc.cell;
       lcell = pcell0;
     }
-    if (__ballot(stray && sb.n == 2)) sb.flush(args, lane);   // a lane needs a third slot
-    if (stray) sb.push(item, lcell, rec);
+    ws.put(args, wbuf, lane, stray, item, lcell, rec);
   };
 
   if (total == 0) {
@@ -844,9 +850,7 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
     }
   }
   // the strays still held take one reservation of the workgroup in the list
-  const bool k0 = sb.n >= 1, k1 = sb.n >= 2;
-  const int wtot = __popcll(__ballot(k0)) + __popcll(__ballot(k1));
-  if (lane == 0) wst[wave] = wtot;
+  if (lane == 0) wst[wave] = ws.fill;
   __syncthreads();
   if (tid == 0) {
     int tot = 0;
@@ -866,7 +870,7 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
     }
   }
   __syncthreads();
-  write_strays(args, lane, wst[wave], k0, sb.item0, sb.cell0, sb.r0, k1, sb.item1, sb.cell1, sb.r1);
+  ws.copy_out(args, wbuf, lane, wst[wave]);
 }
 // ---------------------------------------------------------------------------
 // tiled deposit
@@ -991,9 +995,12 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
       if (!same && has_next) rg = make_ranges<T, kSlots5>(args, nrl, nc);
       pd = load_dep<T>(lptr, select_ranges(same, cr, rg), same ? cb + 32 + hl : hl);
       // ---- 2. matrix cores: S[value][class] += sum over 4 particles per step ----
-      // records past a cell's count are zero, so all 8 steps of a block run
+      // records past a cell's count are zero; the steps past both cells'
+      // counts are skipped
+      const int nk = cmax - cb;   // wave-uniform, >= 1
 #pragma unroll
       for (int k4 = 0; k4 < 32; k4 += 4) {
+        if (k4 > 0 && k4 >= nk) break;
         const T aA = opnd[k4];
         const T aB = opnd[32 + k4];
         const T bA0 = opnd[12 * kSlots + k4];

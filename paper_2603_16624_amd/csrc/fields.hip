@@ -1,5 +1,6 @@
 // Node-grid kernels: matrix-free mass-matrix apply (Eq. 7), staggered curls,
 // centre-to-node averaging, and the FP64 vector kernels of the GMRES solve.
+#include <algorithm>
 #include "internal.h"
 
 namespace ecsim {
@@ -282,6 +283,12 @@ __global__ void __launch_bounds__(kBlock) k_zero(uint32_t* __restrict__ p, int64
   if (i < n) p[i] = 0u;
 }
 
+// 16-byte stores over a fixed grid, for large 16-byte aligned fills
+__global__ void __launch_bounds__(kBlock) k_zero16(uint4* __restrict__ p, int64_t n16) {
+  const uint4 z = {0u, 0u, 0u, 0u};
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n16; i += (int64_t)gridDim.x * kBlock) p[i] = z;
+}
+
 }  // namespace
 
 hipError_t launch_mass_apply(const Grid& g, bool f32, const void* M, const double* x, double a, double b, double* y,
@@ -339,7 +346,15 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
   // a fill kernel rather than a memset node, so the path is safe to capture
   int64_t n = (int64_t)(bytes / 4);
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, st, (uint32_t*)p, n);
+  if ((reinterpret_cast<uintptr_t>(p) & 15) == 0 && n >= 4 * kBlock) {
+    const int64_t n16 = n / 4;
+    const int64_t blocks = std::min<int64_t>(nblocks(n16, kBlock), 8192);
+    hipLaunchKernelGGL(k_zero16, dim3(blocks), dim3(kBlock), 0, st, (uint4*)p, n16);
+    const int64_t tail = n - 4 * n16;
+    if (tail > 0) hipLaunchKernelGGL(k_zero, dim3(1), dim3(kBlock), 0, st, (uint32_t*)p + 4 * n16, tail);
+  } else {
+    hipLaunchKernelGGL(k_zero, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, st, (uint32_t*)p, n);
+  }
   return hipGetLastError();
 }
 
