@@ -346,7 +346,7 @@ hipError_t launch_sort(const Grid& g, bool f32, const SpeciesArgs& src, const Sp
   w += align256(sizeof(int) * (size_t)nc);
   int* sums = (int*)w;
   const int ntiles = (int)((nc + kScanTile - 1) / kScanTile);
-  hipError_t e = hipMemsetAsync(counts, 0, sizeof(int) * (size_t)nc, st);
+  hipError_t e = launch_zero(counts, sizeof(int) * (size_t)nc, st);   // a fill kernel: safe to capture
   if (e != hipSuccess) return e;
   if (np > 0) {
     if (f32)
