@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE passes summarised in the profile named below
 # (scaled by a 1 GiB device copy). Valid only for the kernel sources whose
 # hash is recorded; any change to them makes the figure stale (reported null).
-TRAFFIC = {"sources_sha256": "a764f78216b4e5fa1c0279d5c924ffa875b9e996563efbf2300d68b87a6e3687",
-           "bytes_per_call": 3900051921,
+TRAFFIC = {"sources_sha256": "d7a567dcaece4814acf0ecab52cd7e13d4bf75468f4f8a9d070f6a14198a80f1",
+           "bytes_per_call": 3870672151,
            "profile": "profiles/move_moments_64cubed_fp32.md"}
 
 
@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--sort-every", type=int, default=4)
     ap.add_argument("--no-error", action="store_true", help="skip the FP32-vs-FP64 error measurement")
     ap.add_argument("--calib-copy", action="store_true", help="end with a 1 GiB device copy (byte-counter reference)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the apply and adjoint timings")
     ap.add_argument("--path", choices=("fused", "split"), default="fused",
                     help="fused: one mover+moments kernel; split: mover, then the tiled deposit")
     return ap.parse_args()
@@ -235,6 +236,83 @@ def cpu_baseline(plasma, sample):
                        f"of the 64^3 workload, single thread, {dt:.1f} s")
 
 
+def _time_events(fn, reps, warmup=2):
+    """Median of per-call durations, HIP events on the current stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return _median(ts)
+
+
+def mass_apply_rate(n):
+    """The 14-block apply inside GMRES, timed alone at n^3 nodes: y = M x with M
+    in FP32 and in FP64 (x, y FP64). Algorithmic bytes per node: M (126 values),
+    x read and y written (3 FP64 each)."""
+    import torch
+    from paper_2603_16624_amd import ecsim as E
+    nn = n ** 3
+    grid = E.Grid((n, n, n), (0.5, 0.5, 0.5), 0.1)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x = torch.randn((3, nn), dtype=torch.float64, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    out = {}
+    for name, dt in (("f32_M", torch.float32), ("f64_M", torch.float64)):
+        M = torch.randn((14, 9, nn), dtype=torch.float64, device="cuda", generator=g).to(dt)
+        ms = _time_events(lambda: E.mass_apply(grid, M, x, y, 1.0, 0.0), 20)
+        nbytes = nn * (126 * M.element_size() + 24 + 24)
+        out[name] = {"us_per_call": ms * 1e3, "algorithmic_bytes": nbytes, "GB_per_s": nbytes / (ms * 1e-3) / 1e9,
+                     "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del M
+    return out
+
+
+def adjoint_time():
+    """Adjoint of mover -> moments (ecsim_moments_backward through the mover) on the
+    32^3 x 27 ppc x 2 species workload (1,769,472 particles), FP64 and FP32: time
+    of one backward over both species."""
+    import numpy as np
+    import torch
+    from paper_2603_16624_amd import ecsim as E
+    from paper_2603_16624_amd import inputs as I
+    p = I.config3()
+    rng = np.random.default_rng(3009)
+    En = 1e-3 * rng.standard_normal((3, p.nn))
+    BN = np.array([[0.0], [0.0], [0.2]]) + 1e-3 * rng.standard_normal((3, p.nn))
+    gJ = rng.standard_normal((3, p.nn))
+    gM = rng.standard_normal((14, 9, p.nn))
+    grid = E.Grid(p.n, p.h, p.dt)
+    out = {}
+    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        if prec == "f64":
+            sp = [E.Species.from_f64(s.qom, s.x, s.v, s.q) for s in p.species]
+        else:
+            sp = [E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"])
+                  for s, f in zip(p.species, I.to_f32_state(p))]
+        dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
+        Ed, Bd, gJd, gMd = dev(En), dev(BN), dev(gJ), dev(gM)
+        gE = torch.zeros((3, p.nn), dtype=dt, device="cuda")
+        gB = torch.zeros((3, p.nn), dtype=dt, device="cuda")
+        gx = [torch.empty_like(s.pos) for s in sp]
+        gv = [torch.empty_like(s.vel) for s in sp]
+
+        def bwd():
+            for s, a, b in zip(sp, gx, gv):
+                E.moments_backward(grid, s, Ed, Bd, gJd, gMd, a, b, gE, gB, through_mover=True)
+        ms = _time_events(bwd, 5)
+        out[prec] = {"ms": ms, "particles_per_s": p.n_particles / (ms * 1e-3)}
+    out["workload"] = f"{p.n[0]}x{p.n[1]}x{p.n[2]} cells x 27 ppc x 2 species ({p.n_particles} particles)"
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -269,6 +347,12 @@ def main():
     if not args.no_error:
         err = fixed_error(plasma)
         print(f"[bench] fixed error: {json.dumps(err)}", file=sys.stderr, flush=True)
+    apply = adjoint = None
+    if not args.no_extras:
+        apply = mass_apply_rate(args.n)
+        print(f"[bench] mass apply: {json.dumps(apply)}", file=sys.stderr, flush=True)
+        adjoint = adjoint_time()
+        print(f"[bench] adjoint: {json.dumps(adjoint)}", file=sys.stderr, flush=True)
     if args.calib_copy:
         calibrate_copy()
         print("[bench] copy calibration done", file=sys.stderr, flush=True)
@@ -315,6 +399,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": nbytes, "launch_ms": kms},
         "cpu_baseline": cpu,
+        "mass_apply": apply,
+        "adjoint_backward": adjoint,
     }
     print(json.dumps(out), flush=True)
 
