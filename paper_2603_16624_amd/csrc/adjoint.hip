@@ -8,7 +8,8 @@
 //   rotation: dL/dB'_p by the vector-Jacobian product of Eq. 2;
 //   weights:  dL/dxi' from dL/dW'_a, dL/dx' = dL/dxi' / h;
 //   mover:    x' = x + dt v', v' = 2 alpha u - v, u = v + beta E_p (Eqs. 4-5, 8).
-// Grid gradients gE, gB are scattered with atomics.
+// Grid gradients gE, gB are scattered with atomics, summed first over the
+// runs of lanes that share a node.
 #include "internal.h"
 
 namespace ecsim {
@@ -16,6 +17,34 @@ namespace ecsim {
 namespace {
 
 constexpr int kBlock = 256;
+
+// Adds v[0..NC) of every lane to dst[c][key] (key < 0: nothing). Lanes with
+// equal keys in a contiguous run of the wavefront (cell-sorted particles
+// share their corner nodes) are summed first, by a scan bounded by the run's
+// first lane, and the run's last lane issues the atomics; a key that comes
+// back in a later run is simply a run of its own. Reached by the whole
+// wavefront.
+template <typename T, int NC>
+__device__ __forceinline__ void wave_run_add(int key, T (&v)[NC], T* const (&dst)[NC], int lane) {
+  const int kprev = __shfl_up(key, 1);
+  const bool head = lane == 0 || kprev != key;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto = heads & ((2ull << lane) - 1ull);   // heads at lanes <= lane
+  const int start = 63 - __clzll(upto);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const T o = __shfl_up(v[c], off);
+      if (lane - off >= start) v[c] += o;
+    }
+  }
+  const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+  if (tail && key >= 0) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) unsafeAtomicAdd(dst[c] + key, v[c]);
+  }
+}
 
 template <typename T, bool CELL, bool THROUGH>
 __global__ void __launch_bounds__(kBlock) k_backward(
@@ -25,8 +54,11 @@ __global__ void __launch_bounds__(kBlock) k_backward(
     const T* __restrict__ B, const T* __restrict__ gJ, const T* __restrict__ gM, T* __restrict__ gx0,
     T* __restrict__ gx1, T* __restrict__ gx2, T* __restrict__ gv0, T* __restrict__ gv1, T* __restrict__ gv2,
     T* __restrict__ gE, T* __restrict__ gB) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
-  if (p >= np) return;
+  // every lane runs (the gradient scatter works across the wavefront); lanes
+  // past the end recompute the last particle and store nothing
+  const int lane = threadIdx.x & 63;
+  const bool valid = blockIdx.x * kBlock + threadIdx.x < np;
+  const int p = valid ? blockIdx.x * kBlock + threadIdx.x : np - 1;
   const int64_t nn = g.nn;
   const T qp = q ? q[p] : q_const;
   const T V = T(g.V);
@@ -122,11 +154,11 @@ __global__ void __launch_bounds__(kBlock) k_backward(
               (a1[2] * gh[0] + a1[5] * gh[1]) + a1[8] * gh[2]};
   // alpha' = R(B'_p), B'_p = sum W'_a B[n'_a]
   Vec3<T> gB1 = rotation_vjp(a1, B1, beta, ga1);
+  T* const dstB[3] = {gB, gB + nn, gB + 2 * nn};
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
-    unsafeAtomicAdd(&gB[nd1[c]], W1[c] * gB1.x);
-    unsafeAtomicAdd(&gB[nn + nd1[c]], W1[c] * gB1.y);
-    unsafeAtomicAdd(&gB[2 * nn + nd1[c]], W1[c] * gB1.z);
+    T v3[3] = {valid ? W1[c] * gB1.x : T(0), valid ? W1[c] * gB1.y : T(0), valid ? W1[c] * gB1.z : T(0)};
+    wave_run_add<T, 3>(valid ? (int)nd1[c] : -1, v3, dstB, lane);
     gW1[c] += (B[nd1[c]] * gB1.x + B[nn + nd1[c]] * gB1.y) + B[2 * nn + nd1[c]] * gB1.z;
   }
   T gxi1[3];
@@ -159,14 +191,13 @@ __global__ void __launch_bounds__(kBlock) k_backward(
     Vec3<T> gEp{beta * gu.x, beta * gu.y, beta * gu.z};
     Vec3<T> gBp = rotation_vjp(a0, Bp, beta, ga0);
     T gW0[8];
+    T* const dstEB[6] = {gE, gE + nn, gE + 2 * nn, gB, gB + nn, gB + 2 * nn};
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      unsafeAtomicAdd(&gE[nd0[c]], W0[c] * gEp.x);
-      unsafeAtomicAdd(&gE[nn + nd0[c]], W0[c] * gEp.y);
-      unsafeAtomicAdd(&gE[2 * nn + nd0[c]], W0[c] * gEp.z);
-      unsafeAtomicAdd(&gB[nd0[c]], W0[c] * gBp.x);
-      unsafeAtomicAdd(&gB[nn + nd0[c]], W0[c] * gBp.y);
-      unsafeAtomicAdd(&gB[2 * nn + nd0[c]], W0[c] * gBp.z);
+      T v6[6] = {W0[c] * gEp.x, W0[c] * gEp.y, W0[c] * gEp.z, W0[c] * gBp.x, W0[c] * gBp.y, W0[c] * gBp.z};
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v6[k] = valid ? v6[k] : T(0);
+      wave_run_add<T, 6>(valid ? (int)nd0[c] : -1, v6, dstEB, lane);
       gW0[c] = ((E[nd0[c]] * gEp.x + E[nn + nd0[c]] * gEp.y) + E[2 * nn + nd0[c]] * gEp.z) +
                ((B[nd0[c]] * gBp.x + B[nn + nd0[c]] * gBp.y) + B[2 * nn + nd0[c]] * gBp.z);
     }
@@ -176,12 +207,14 @@ __global__ void __launch_bounds__(kBlock) k_backward(
     gx.y += gxi0[1] / h[1];
     gx.z += gxi0[2] / h[2];
   }
-  gx0[p] = gx.x;
-  gx1[p] = gx.y;
-  gx2[p] = gx.z;
-  gv0[p] = gv.x;
-  gv1[p] = gv.y;
-  gv2[p] = gv.z;
+  if (valid) {
+    gx0[p] = gx.x;
+    gx1[p] = gx.y;
+    gx2[p] = gx.z;
+    gv0[p] = gv.x;
+    gv1[p] = gv.y;
+    gv2[p] = gv.z;
+  }
 }
 
 template <typename T, bool CELL>

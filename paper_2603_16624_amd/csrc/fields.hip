@@ -18,12 +18,17 @@ __device__ __forceinline__ int shift(int i, int o, int n) { return o > 0 ? wp(i,
 // y = a (M x) + b y with the 14 stored blocks (block k at g couples g and
 // g + o_k; the same block, untransposed, couples g + o_k back to g).
 // One thread per node; the [14][9][Nn] layout makes every M read coalesced.
+// Workgroups go to the 8 XCDs in turn; each XCD is given a contiguous eighth
+// of the nodes, so that the blocks read again at g - o (up to one z-plane
+// back) are still in that XCD's L2.
 // ---------------------------------------------------------------------------
 template <typename TM>
 __global__ void __launch_bounds__(kBlock) k_mass_apply(Grid g, const TM* __restrict__ M, const double* __restrict__ x,
                                                        double a, double b, double* __restrict__ y) {
   const int64_t nn = g.nn;
-  const int64_t gid = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  int blk = blockIdx.x;
+  if ((gridDim.x & 7) == 0) blk = (blk & 7) * (gridDim.x >> 3) + (blk >> 3);
+  const int64_t gid = blk * (int64_t)kBlock + threadIdx.x;
   if (gid >= nn) return;
   int ix, iy, iz;
   decode_cell(g, (int)gid, ix, iy, iz);

@@ -535,6 +535,54 @@ def test_backward_f64_matches_dual_oracle(E, O, I, n, ppc):
     assert rel(host(gB), gBo) < TOL64
 
 
+@pytest.mark.parametrize("order", ["cells", "shuffled", "interleaved"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_backward_particle_order(E, O, I, prec, order):
+    """The grid gradients do not depend on particle order: cell-ordered
+    particles (long runs of lanes on one node), a random order, and two cells'
+    particles alternating (the same node coming back in separate runs)."""
+    say("backward order", prec, order)
+    p, En, BN, gJ, gM = grad_case(I, (6, 5, 4), 9, 21)
+    grid = E.Grid(p.n, p.h, p.dt)
+    tdt, tol = (torch.float64, TOL64) if prec == "f64" else (torch.float32, TOL32)
+    rng = np.random.default_rng(22)
+    gE = torch.zeros((3, p.nn), dtype=tdt, device="cuda")
+    gB = torch.zeros((3, p.nn), dtype=tdt, device="cuda")
+    gEo = np.zeros((3, p.nn))
+    gBo = np.zeros((3, p.nn))
+    Ec, Bc, gJc, gMc = (En, BN, gJ, gM) if prec == "f64" else (round32(En), round32(BN), round32(gJ), round32(gM))
+    states = I.to_f32_state(p) if prec == "f32" else [None] * len(p.species)
+    for s, f in zip(p.species, states):
+        x = s.x if f is None else f["x64"]
+        cells = np.floor(x[0] / p.h[0]).astype(np.int64) + p.n[0] * (np.floor(x[1] / p.h[1]).astype(np.int64)
+                                                                      + p.n[1] * np.floor(x[2] / p.h[2]).astype(np.int64))
+        if order == "cells":
+            perm = np.argsort(cells, kind="stable")
+        elif order == "shuffled":
+            perm = rng.permutation(s.np)
+        else:
+            srt = np.argsort(cells, kind="stable")
+            half = (len(srt) + 1) // 2
+            perm = np.empty_like(srt)
+            perm[0::2] = srt[:half]
+            perm[1::2] = srt[half:]
+        if f is None:
+            sp = E.Species.from_f64(s.qom, s.x[:, perm], s.v[:, perm], s.q[perm])
+            xs, vs, qs = s.x[:, perm], s.v[:, perm], s.q[perm]
+        else:
+            sp = E.Species.from_f32(s.qom, f["cell"][perm], f["off"][:, perm], f["v"][:, perm], f["q"][perm])
+            xs, vs, qs = f["x64"][:, perm], f["v64"][:, perm], f["q64"][perm]
+        gx = torch.empty_like(sp.pos)
+        gv = torch.empty_like(sp.vel)
+        E.moments_backward(grid, sp, dev(Ec, tdt), dev(Bc, tdt), dev(gJc, tdt), dev(gMc, tdt), gx, gv, gE, gB,
+                           through_mover=True)
+        gxo, gvo, _, _ = O.grad(p.n, p.h, p.dt, xs, vs, qs, s.qom, Ec, Bc, gJc, gMc, gEo, gBo)
+        assert rel(host(gx), gxo) < tol
+        assert rel(host(gv), gvo) < tol
+    assert rel(host(gE), gEo) < tol
+    assert rel(host(gB), gBo) < tol
+
+
 def test_backward_f32_matches_dual_oracle(E, O, I):
     say("backward f32")
     p, En, BN, gJ, gM = grad_case(I, (5, 4, 4), 4, 14)
