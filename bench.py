@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE passes summarised in the profile named below
 # (scaled by a 1 GiB device copy). Valid only for the kernel sources whose
 # hash is recorded; any change to them makes the figure stale (reported null).
-TRAFFIC = {"sources_sha256": "d7a567dcaece4814acf0ecab52cd7e13d4bf75468f4f8a9d070f6a14198a80f1",
-           "bytes_per_call": 3870672151,
+TRAFFIC = {"sources_sha256": "c381460922b54bb2c08ef61eb6e660caa737a65b1c9931fd60d664e20c0fa01c",
+           "bytes_per_call": 3870622355,
            "profile": "profiles/move_moments_64cubed_fp32.md"}
 
 
@@ -43,7 +43,10 @@ def kernel_sources_sha256():
     import glob
     import hashlib
     h = hashlib.sha256()
+    # every source the fused pass is built from (the adjoint's is not)
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_2603_16624_amd", "csrc", "*"))):
+        if os.path.basename(f) == "adjoint.hip":
+            continue
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
