@@ -16,7 +16,10 @@
 //   * theta-scheme field equations (Eqs. 6-7), solved for E^{n+theta} with
 //     restarted GMRES, then the field advance to n+1;
 //   * particle mover (Eqs. 4, 5, 8);
-//   * total energy, conserved by the scheme for theta = 1/2.
+//   * total energy, conserved by the scheme for theta = 1/2;
+//   * diagnostic moments of the output routines (Sec. III, diagnostics for
+//     I/O): charge density, charge current without the velocity rotation,
+//     and the charge-weighted second velocity moment (pressure tensor).
 // Units: Gaussian with 4 pi, c = 1, theta = 1/2. Node index
 // ix + nx*(iy + ny*iz); periodic in all directions. Built with
 // -O2 -fno-fast-math -ffp-contract=off.
@@ -417,6 +420,35 @@ void oracle_gather(const int32_t* n, const double* h, int64_t np, const double* 
 }
 
 void oracle_alpha(const double* B, double beta, double* a) { rotation(B, beta, a); }
+
+// Diagnostic moments (Sec. III, diagnostics for I/O), accumulated (+=):
+//   rho [Nn]:   sum_p q_p W_pN / V_N                 (charge density)
+//   Jd  [3][Nn]: sum_p q_p v_p W_pN / V_N            (current, no rotation)
+//   P   [6][Nn]: sum_p q_p v_i v_j W_pN / V_N, components xx, xy, xz, yy,
+//                yz, zz (charge-weighted second velocity moment)
+// at the particles' positions x with velocities v as given.
+void oracle_diagnostics(const int32_t* n, const double* h, int64_t np, const double* x, const double* v,
+                        const double* q, double q_const, double* rho, double* Jd, double* P) {
+  Grid g = make_grid(n, h, 1.0);
+  const int64_t nn = g.nn();
+  const double V = g.V();
+  const int pi[6] = {0, 0, 0, 1, 1, 2}, pj[6] = {0, 1, 2, 1, 2, 2};
+  for (int64_t p = 0; p < np; ++p) {
+    const double qp = q ? q[p] : q_const;
+    double xp[3] = {x[p], x[np + p], x[2 * np + p]};
+    double vp[3] = {v[p], v[np + p], v[2 * np + p]};
+    Stencil<double> s = stencil(g, xp);
+    for (int az = 0; az < 2; ++az)
+      for (int ay = 0; ay < 2; ++ay)
+        for (int ax = 0; ax < 2; ++ax) {
+          const double w = corner_weight(s, ax, ay, az);
+          const int64_t nd = corner_node(g, s, ax, ay, az);
+          rho[nd] += qp * w / V;
+          for (int c = 0; c < 3; ++c) Jd[c * nn + nd] += qp * vp[c] * w / V;
+          for (int c = 0; c < 6; ++c) P[c * nn + nd] += qp * vp[pi[c]] * vp[pj[c]] * w / V;
+        }
+  }
+}
 
 // Moments of Eqs. 1 and 3, accumulated (+=) into J [3][Nn] and M27 [27][9][Nn].
 // q: per-particle charge (or NULL to use q_const). B_node: node magnetic field.

@@ -53,6 +53,7 @@ def _declare(L):
     L.oracle_gather.argtypes = [_p, _p, _i64, _p, _p, _p]
     L.oracle_alpha.argtypes = [_p, _d, _p]
     L.oracle_moments.argtypes = [_p, _p, _d, _i64, _p, _p, _p, _d, _d, _p, _p, _p]
+    L.oracle_diagnostics.argtypes = [_p, _p, _i64, _p, _p, _p, _d, _p, _p, _p]
     L.oracle_m14_from_m27.argtypes = [_p, _p, _p]
     L.oracle_canonical14.argtypes = [_p]
     L.oracle_mass_apply27.argtypes = [_p, _p, _p, _p]
@@ -139,6 +140,23 @@ def moments(n, h, dt, x, v, q, qom, B_node, J=None, M27=None):
     lib().oracle_moments(_ptr(ni), _ptr(hh), float(dt), x.shape[1], _ptr(x), _ptr(v), _ptr(qa), qc,
                          float(qom), _ptr(B_node), _ptr(J), _ptr(M27))
     return J, M27
+
+
+def diagnostics(n, h, x, v, q, rho=None, Jd=None, P=None):
+    """Accumulates the diagnostic moments (Sec. III, diagnostics for I/O): rho (Nn,),
+    the unrotated current Jd (3, Nn) and the charge-weighted second velocity
+    moment P (6, Nn: xx, xy, xz, yy, yz, zz), each divided by the node volume."""
+    ni, hh = _grid(n, h)
+    nn = int(np.prod(n))
+    rho = np.zeros(nn) if rho is None else rho
+    Jd = np.zeros((3, nn)) if Jd is None else Jd
+    P = np.zeros((6, nn)) if P is None else P
+    x = _f64(x)
+    v = _f64(v)
+    qa, qc = _q(q)
+    lib().oracle_diagnostics(_ptr(ni), _ptr(hh), x.shape[1], _ptr(x), _ptr(v), _ptr(qa), qc, _ptr(rho), _ptr(Jd),
+                             _ptr(P))
+    return rho, Jd, P
 
 
 def m14(n, M27):
