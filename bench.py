@@ -278,6 +278,44 @@ def mass_apply_rate(n):
     return out
 
 
+def diagnostics_rate(plasma):
+    """Diagnostic moments (charge density, current, pressure tensor) of the 64^3
+    workload after a sort, FP32 and FP64, tiled path. Algorithmic bytes: the
+    particle state read once (FP32 offsets, cell, velocity: 28 B; FP64: 48 B)
+    and the 10 output values per node written once."""
+    import torch
+    from paper_2603_16624_amd import ecsim as E
+    from paper_2603_16624_amd import inputs as I
+    p = plasma
+    grid = E.Grid(p.n, p.h, p.dt)
+    out = {}
+    for prec in ("f32", "f64"):
+        if prec == "f64":
+            sp = [E.Species.from_f64(s.qom, s.x, s.v, s.q) for s in p.species]
+            tdt, pb = torch.float64, 48
+        else:
+            sp = [E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"])
+                  for s, f in zip(p.species, I.to_f32_state(p))]
+            tdt, pb = torch.float32, 28
+        grp = []
+        for s in sp:
+            d = s.empty_like()
+            E.sort(grid, s, d, torch.empty(grid.nn + 1, dtype=torch.int32, device="cuda"))
+            grp.append(d)
+        del sp
+        rho = torch.empty(p.nn, dtype=tdt, device="cuda")
+        Jd = torch.empty((3, p.nn), dtype=tdt, device="cuda")
+        P = torch.empty((6, p.nn), dtype=tdt, device="cuda")
+        ws = torch.empty(E.diagnostics_workspace_size(grid, grp[0].prec, E.SORTED), dtype=torch.uint8, device="cuda")
+        ms = _time_events(lambda: E.diagnostics(grid, grp, rho, Jd, P, flags=E.SORTED, ws=ws), 5)
+        nbytes = p.n_particles * pb + 10 * p.nn * (8 if prec == "f64" else 4)
+        out[prec] = {"ms": ms, "particles_per_s": p.n_particles / (ms * 1e-3), "GB_per_s": nbytes / (ms * 1e-3) / 1e9,
+                     "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del grp, rho, Jd, P
+        torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_time():
     """Adjoint of mover -> moments (ecsim_moments_backward through the mover) on the
     32^3 x 27 ppc x 2 species workload (1,769,472 particles), FP64 and FP32: time
@@ -350,12 +388,14 @@ def main():
     if not args.no_error:
         err = fixed_error(plasma)
         print(f"[bench] fixed error: {json.dumps(err)}", file=sys.stderr, flush=True)
-    apply = adjoint = None
+    apply = adjoint = diag = None
     if not args.no_extras:
         apply = mass_apply_rate(args.n)
         print(f"[bench] mass apply: {json.dumps(apply)}", file=sys.stderr, flush=True)
         adjoint = adjoint_time()
         print(f"[bench] adjoint: {json.dumps(adjoint)}", file=sys.stderr, flush=True)
+        diag = diagnostics_rate(plasma)
+        print(f"[bench] diagnostics: {json.dumps(diag)}", file=sys.stderr, flush=True)
     if args.calib_copy:
         calibrate_copy()
         print("[bench] copy calibration done", file=sys.stderr, flush=True)
@@ -404,6 +444,7 @@ def main():
         "cpu_baseline": cpu,
         "mass_apply": apply,
         "adjoint_backward": adjoint,
+        "diagnostics": diag,
     }
     print(json.dumps(out), flush=True)
 

@@ -132,6 +132,32 @@ ecsim_status ecsim_moments(const ecsim_grid *grid, const ecsim_particles *specie
                            void *ws, size_t ws_bytes, uint32_t flags, void *stream);
 
 /*
+ * Diagnostic moments of the output routines (paper, Sec. III: the diagnostics
+ * computed for I/O, charge density, charge current and pressure tensor),
+ * summed over `nspecies` species at the particles' stored positions and
+ * velocities, with the interpolation weights W_pg of the moment gather:
+ *   rho[g]  = sum_p q_p W_pg / V                                       [Nn]
+ *   J[c][g] = sum_p q_p v_c W_pg / V  (no velocity rotation)        [3][Nn]
+ *   P[k][g] = sum_p q_p v_i v_j W_pg / V, (i, j) = xx, xy, xz, yy, yz, zz
+ *             for k = 0..5 (charge-weighted second velocity moment)  [6][Nn]
+ * All species share one precision; rho, J and P are in it and are
+ * overwritten unless ECSIM_ACCUMULATE is set. With ECSIM_SORTED every species
+ * carries cell_start and a tiled kernel is used (a particle outside its
+ * range's cell is still counted, through a slower path). Without
+ * ECSIM_SORTED a per-particle atomic kernel takes any order; its FP32 form
+ * accumulates in FP64 in the workspace and rounds once into the outputs.
+ * ws/ws_bytes: device workspace of ecsim_diagnostics_workspace_size() bytes
+ * for the same precision and flags (may be 0 and NULL); contents not kept.
+ * Errors: ECSIM_EINVAL for bad arguments or flags, ECSIM_EWORKSPACE for a
+ * missing or short workspace.
+ */
+ecsim_status ecsim_diagnostics_workspace_size(const ecsim_grid *grid, int32_t prec, uint32_t flags,
+                                              size_t *bytes);
+ecsim_status ecsim_diagnostics(const ecsim_grid *grid, const ecsim_particles *species,
+                               int32_t nspecies, void *rho, void *J, void *P,
+                               void *ws, size_t ws_bytes, uint32_t flags, void *stream);
+
+/*
  * Fused particle pass of one step: every species is moved as by ecsim_move
  * (E_node = E^{n+theta}, B_node = B^n, Eqs. 4, 5, 8), then the moments of
  * Eqs. 1 and 3 at the new positions with B_next = B^{n+1} (the next step's

@@ -173,6 +173,52 @@ ecsim_status ecsim_moments(const ecsim_grid* grid, const ecsim_particles* specie
   return ECSIM_OK;
 }
 
+static size_t diag_ws_bytes(const Grid& g, bool f32, uint32_t flags) {
+  if (flags & ECSIM_SORTED) return 256;            // a zero block
+  return f32 ? sizeof(double) * 10 * (size_t)g.nn : 0;   // FP64 accumulators of the FP32 form
+}
+
+ecsim_status ecsim_diagnostics_workspace_size(const ecsim_grid* grid, int32_t prec, uint32_t flags, size_t* bytes) {
+  Grid g;
+  if (!bytes) return fail(ECSIM_EINVAL, "ecsim_diagnostics_workspace_size: bytes is NULL");
+  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
+  if (check_prec(prec) != ECSIM_OK) return ECSIM_EINVAL;
+  if (flags & ~(uint32_t)(ECSIM_ACCUMULATE | ECSIM_SORTED))
+    return fail(ECSIM_EINVAL, "ecsim_diagnostics_workspace_size: unknown flags 0x%x", flags);
+  *bytes = diag_ws_bytes(g, prec == ECSIM_F32, flags);
+  return ECSIM_OK;
+}
+
+ecsim_status ecsim_diagnostics(const ecsim_grid* grid, const ecsim_particles* species, int32_t nspecies, void* rho,
+                               void* J, void* P, void* ws, size_t ws_bytes, uint32_t flags, void* stream) {
+  Grid g;
+  SpeciesArgs a[kMaxSpecies];
+  if (flags & ~(uint32_t)(ECSIM_ACCUMULATE | ECSIM_SORTED))
+    return fail(ECSIM_EINVAL, "ecsim_diagnostics: unknown flags 0x%x", flags);
+  if (species_list(grid, species, nspecies, g, a, "ecsim_diagnostics", flags, false) != ECSIM_OK) return ECSIM_EINVAL;
+  if (!rho || !J || !P) return fail(ECSIM_EINVAL, "ecsim_diagnostics: rho, J and P are required");
+  const bool f32 = species[0].prec == ECSIM_F32;
+  const size_t esz = f32 ? 4 : 8;
+  const bool tiled = (flags & ECSIM_SORTED) && tiled_species_ok(a, nspecies);
+  const size_t need = diag_ws_bytes(g, f32, tiled ? ECSIM_SORTED : 0);
+  if (need && (!ws || ws_bytes < need))
+    return fail(ECSIM_EWORKSPACE, "ecsim_diagnostics: workspace of %zu bytes needed, %zu given", need,
+                ws ? ws_bytes : 0);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (!(flags & ECSIM_ACCUMULATE)) {
+    if ((e = launch_zero(rho, esz * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_diagnostics zero rho");
+    if ((e = launch_zero(J, esz * 3 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_diagnostics zero J");
+    if ((e = launch_zero(P, esz * 6 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_diagnostics zero P");
+  }
+  if (tiled)
+    e = launch_diagnostics_tiled(g, f32, a, nspecies, rho, J, P, ws, st);
+  else
+    e = launch_diagnostics_atomic(g, f32, a, nspecies, rho, J, P, ws, st);
+  if (e != hipSuccess) return hip_fail(e, "ecsim_diagnostics");
+  return ECSIM_OK;
+}
+
 ecsim_status ecsim_move_moments(const ecsim_grid* grid, const ecsim_particles* species, int32_t nspecies,
                                 const void* E_node, const void* B_node, const void* B_next, void* J, void* M,
                                 double* ke_out, void* ws, size_t ws_bytes, uint32_t flags, void* stream) {

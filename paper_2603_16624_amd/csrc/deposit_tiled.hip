@@ -1087,6 +1087,163 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
 }
 
 // ---------------------------------------------------------------------------
+// diagnostic moments over cell-grouped particles (Sec. III, diagnostics for
+// I/O): per cell, the 10 particle values f = q (1, v, v_i v_j) against the 8
+// corner weights are a (10 x K) by (K x 8) contraction over the cell's K
+// particles, one 16 x 16 matrix-core tile per cell (rows past 10 and columns
+// past 8 are not used); per-cell sums go to LDS and a node gather adds each
+// brick node once to the global arrays. A particle not in its range's cell
+// (stale grouping) is added with global atomics instead.
+// ---------------------------------------------------------------------------
+constexpr int kDVals = 10;                  // q, q v (3), q v_i v_j (xx xy xz yy yz zz)
+constexpr int kDRows = kDVals + 16;         // values, then 8 weights (+8 rows read as unused columns)
+constexpr int kDCell = kDVals * 8;          // per-cell sums: [value][corner]
+
+template <typename T>
+__device__ __forceinline__ void diag_values(T q, T vx, T vy, T vz, T f[kDVals]) {
+  f[0] = q;
+  f[1] = q * vx;
+  f[2] = q * vy;
+  f[3] = q * vz;
+  f[4] = (q * vx) * vx;
+  f[5] = (q * vx) * vy;
+  f[6] = (q * vx) * vz;
+  f[7] = (q * vy) * vy;
+  f[8] = (q * vy) * vz;
+  f[9] = (q * vz) * vz;
+}
+
+template <typename T>
+__device__ __forceinline__ T* diag_target(T* rho, T* Jd, T* P, int64_t nn, int v, int64_t node) {
+  return v == 0 ? rho + node : (v < 4 ? Jd + (v - 1) * nn + node : P + (v - 4) * nn + node);
+}
+
+template <typename T, int TX, int TY, int TZ, int NW>
+__global__ void __launch_bounds__(NW * 64) k_diag_tiled(Grid g, TArgs<T> args, int ntx, int nty, int ntz,
+                                                        T* __restrict__ rho, T* __restrict__ Jd, T* __restrict__ P) {
+  using MF = Mfma<T>;
+  using acc_t = typename MF::acc;
+  constexpr int NCELL = TX * TY * TZ;
+  constexpr int NPAIR = (NCELL + 1) / 2;
+  constexpr int WREC = kDRows * kSlots;
+  __shared__ __attribute__((aligned(16))) T smem[NW * WREC + NCELL * kDCell];
+  __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
+  __shared__ PtrSet<T> lptr_tab[kZeroSlot + 1];
+  LdsPtrSet<T>* const lptr = (LdsPtrSet<T>*)lptr_tab;
+  T* const scell = smem + NW * WREC;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int half = lane >> 5;
+  const int hl = lane & 31;
+  const int col = lane & 15;
+  const int grp = lane >> 4;
+  const int64_t nn = g.nn;
+  const T inv_V = T(1.0 / g.V);
+  int x0, y0, z0;
+  brick_origin<TX, TY, TZ>(ntx, nty, ntz, x0, y0, z0);
+  for (int i = tid; i < NW * WREC + NCELL * kDCell; i += NW * 64) smem[i] = T(0);
+  fill_tables(args, lsp, lptr_tab, tid);
+  __syncthreads();
+  T* const wrec = smem + wave * WREC;
+  const T* const opnd = wrec + col * kSlots + grp;
+
+  for (int pair = wave; pair < NPAIR; pair += NW) {
+    const BrickCell pc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, 2 * pair + half);
+    // the cell's list: its species ranges (the stray slot stays empty; its
+    // range is not loaded, there being no stray list here)
+    const RangeLd rl = load_ranges<T, kMaxTiledSpecies>(args, lsp, pc);
+    Ranges rg;
+    {
+      int e = 0, prev = 0;
+#pragma unroll
+      for (int s = 0; s < kSlots5; ++s) {
+        const bool used = s < args.ns && s != kStraySlot;
+        const int dlt = rl.lo[s] - e;
+        if (s == 0) rg.d0 = dlt;
+        else rg.inc[s - 1] = dlt - prev;
+        prev = dlt;
+        e += (pc.valid && used) ? rl.hi[s] - rl.lo[s] : 0;
+        if (s < kSlots5 - 1) rg.end[s] = e;
+      }
+      rg.total = e;
+    }
+    const int cntA = __builtin_amdgcn_readfirstlane(__shfl(rg.total, 0));
+    const int cntB = __builtin_amdgcn_readfirstlane(__shfl(rg.total, 32));
+    const int cmax = cntA > cntB ? cntA : cntB;
+    if (cmax == 0) continue;   // wave-uniform
+    acc_t dA = {0, 0, 0, 0}, dB = {0, 0, 0, 0};
+    for (int cb = 0; cb < cmax; cb += 32) {
+      const PData<T> pd = load_dep<T>(lptr, rg, cb + hl);
+      {
+        const TSpecies<T>& sp = lsp[dep_species(pd)];
+        (void)sp;
+        const Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
+        const int pcell = ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]);
+        const bool in_cell = pd.ok && pcell == pc.cell;
+        const T q = pd.ok ? dep_charge(pd, lptr) * inv_V : T(0);
+        T f[kDVals];
+        diag_values(in_cell ? q : T(0), pd.v0, pd.v1, pd.v2, f);
+        T W[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
+#pragma unroll
+        for (int i = 0; i < kDVals; ++i) wrec[i * kSlots + lane] = f[i];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) wrec[(kDVals + a) * kSlots + lane] = W[a];
+        if (pd.ok && !in_cell) {   // out of its range's cell: straight to the global arrays
+          T fs[kDVals];
+          diag_values(q, pd.v0, pd.v1, pd.v2, fs);
+#pragma unroll
+          for (int a = 0; a < 8; ++a) {
+            const int64_t node = corner_node(g, ps, a);
+#pragma unroll
+            for (int v = 0; v < kDVals; ++v) unsafeAtomicAdd(diag_target(rho, Jd, P, nn, v, node), fs[v] * W[a]);
+          }
+        }
+      }
+      wave_sync();
+      const int nk = cmax - cb;   // wave-uniform, >= 1
+#pragma unroll
+      for (int k4 = 0; k4 < 32; k4 += 4) {
+        if (k4 > 0 && k4 >= nk) break;
+        dA = MF::run(opnd[k4], opnd[kDVals * kSlots + k4], dA);
+        dB = MF::run(opnd[32 + k4], opnd[kDVals * kSlots + 32 + k4], dB);
+      }
+      wave_sync();
+    }
+    // per-cell sums [value][corner]: rows < 10, columns < 8
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int lch = 2 * pair + h;
+      if (lch >= NCELL || col >= 8) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = MF::row(lane, r);
+        if (row < kDVals) scell[lch * kDCell + row * 8 + col] = h == 0 ? dA[r] : dB[r];
+      }
+    }
+  }
+  __syncthreads();
+  // node gather: every (value, node) of the brick sums its <= 8 cells once
+  constexpr int NX = TX + 1, NY = TY + 1, NZ = TZ + 1, NN = NX * NY * NZ;
+  for (int it = tid; it < kDVals * NN; it += NW * 64) {
+    const int v = it / NN, ln = it % NN;
+    const int nx_ = ln % NX, ny_ = (ln / NX) % NY, nz_ = ln / (NX * NY);
+    T sum = T(0);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int lcx = nx_ - (a & 1), lcy = ny_ - ((a >> 1) & 1), lcz = nz_ - ((a >> 2) & 1);
+      if (lcx >= 0 && lcx < TX && lcy >= 0 && lcy < TY && lcz >= 0 && lcz < TZ)
+        sum += scell[(lcx + TX * (lcy + TY * lcz)) * kDCell + v * 8 + a];
+    }
+    const int gx = wrap_once(x0 + nx_, g.nx), gy = wrap_once(y0 + ny_, g.ny), gz = wrap_once(z0 + nz_, g.nz);
+    const int64_t gn = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
+    if (sum != T(0)) unsafeAtomicAdd(diag_target(rho, Jd, P, nn, v, gn), sum);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // stray mover: particles listed before their move -- found outside their
 // range's cell -- are moved here with fields read from memory, in the same
 // arithmetic as the grouped mover, and their new cell recorded.
@@ -1387,6 +1544,27 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
 }
 
 }  // namespace
+
+namespace {
+template <typename T, int TX, int TY, int TZ, int NW>
+hipError_t run_diag(const Grid& g, const SpeciesArgs* sp, int ns, void* rho, void* Jd, void* P, void* zero,
+                    hipStream_t st) {
+  const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
+  TArgs<T> a = make_args<T>(g, sp, ns);
+  a.zero = zero;
+  hipError_t e = launch_zero(zero, 256, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_diag_tiled<T, TX, TY, TZ, NW>), dim3(ntx * nty * ntz), dim3(NW * 64), 0, st, g, a, ntx, nty,
+                     ntz, (T*)rho, (T*)Jd, (T*)P);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_diagnostics_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, void* rho, void* Jd,
+                                    void* P, void* zero, hipStream_t st) {
+  if (f32) return run_diag<float, 4, 4, 2, 4>(g, sp, ns, rho, Jd, P, zero, st);
+  return run_diag<double, 4, 4, 2, 4>(g, sp, ns, rho, Jd, P, zero, st);
+}
 
 size_t tiled_workspace_bytes(const Grid& g, int64_t np_total, bool f32) {
   const int64_t nscan = (g.nn + 1023) / 1024 + 1;

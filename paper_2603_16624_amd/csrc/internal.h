@@ -26,6 +26,10 @@ constexpr int kMaxSpecies = 8;
 hipError_t launch_move(const Grid& g, bool f32, const SpeciesArgs& sp, const void* E, const void* B,
                        double* ke, hipStream_t st);
 
+hipError_t launch_diagnostics_atomic(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, void* rho, void* Jd,
+                                     void* P, void* acc, hipStream_t st);
+hipError_t launch_diagnostics_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, void* rho, void* Jd,
+                                    void* P, void* zero, hipStream_t st);
 hipError_t launch_deposit_atomic(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* B,
                                  void* J, void* M, hipStream_t st);
 

@@ -1,5 +1,6 @@
 // Particle kernels: mover (Eqs. 4, 5, 8), per-particle atomic moment deposit
 // (Eqs. 1, 3) for particles in any order, and the per-species counting sort.
+#include <algorithm>
 #include "internal.h"
 
 namespace ecsim {
@@ -136,6 +137,47 @@ __global__ void __launch_bounds__(kBlock) k_deposit_atomic(Grid g, int np, const
       for (int ij = 0; ij < 9; ++ij) unsafeAtomicAdd(&Mk[ij * nn], w * a[ij]);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// diagnostic moments, any particle order (Sec. III, diagnostics for I/O):
+// rho += q W / V, Jd += q v W / V, P_ij += q v_i v_j W / V (xx xy xz yy yz zz)
+// ---------------------------------------------------------------------------
+// (TA: the accumulator type; the FP32 form accumulates in FP64, since a node
+// takes thousands of mixed-sign terms in no particular order)
+template <typename T, bool CELL, typename TA>
+__global__ void __launch_bounds__(kBlock) k_diag_atomic(Grid g, int np, const T* __restrict__ p0,
+                                                        const T* __restrict__ p1, const T* __restrict__ p2,
+                                                        const int32_t* __restrict__ cell, const T* __restrict__ v0,
+                                                        const T* __restrict__ v1, const T* __restrict__ v2,
+                                                        const T* __restrict__ q, T q_const, TA* __restrict__ rho,
+                                                        TA* __restrict__ Jd, TA* __restrict__ P) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= np) return;
+  Stencil<T> s = PState<T, CELL>::stencil(g, p0, p1, p2, cell, p);
+  T W[8];
+  int64_t nd[8];
+  corners(g, s, W, nd);
+  const T c = (q ? q[p] : q_const) / T(g.V);
+  const T vx = v0[p], vy = v1[p], vz = v2[p];
+  const T f[10] = {c, c * vx, c * vy, c * vz, (c * vx) * vx, (c * vx) * vy, (c * vx) * vz,
+                   (c * vy) * vy, (c * vy) * vz, (c * vz) * vz};
+  const int64_t nn = g.nn;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    unsafeAtomicAdd(&rho[nd[a]], (TA)(f[0] * W[a]));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&Jd[k * nn + nd[a]], (TA)(f[1 + k] * W[a]));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) unsafeAtomicAdd(&P[k * nn + nd[a]], (TA)(f[4 + k] * W[a]));
+  }
+}
+
+// out += (float)acc over n entries
+__global__ void __launch_bounds__(kBlock) k_add_rounded(int64_t n, const double* __restrict__ acc,
+                                                        float* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    out[i] += (float)acc[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -289,6 +331,38 @@ hipError_t launch_move(const Grid& g, bool f32, const SpeciesArgs& sp, const voi
                        (const double*)B, beta, 0.0, 0.0, 0.0, (const double*)sp.q, sp.q_const, inv_qom, ke);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_diagnostics_atomic(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, void* rho, void* Jd,
+                                     void* P, void* acc, hipStream_t st) {
+  const int64_t nn = g.nn;
+  hipError_t e;
+  double* const a = (double*)acc;   // FP32 form: [10][Nn] FP64 accumulators
+  if (f32 && (e = launch_zero(a, sizeof(double) * 10 * (size_t)nn, st)) != hipSuccess) return e;
+  for (int s = 0; s < ns; ++s) {
+    if (sp[s].np == 0) continue;
+    if (f32)
+      hipLaunchKernelGGL((k_diag_atomic<float, true, double>), dim3(nblocks(sp[s].np, kBlock)), dim3(kBlock), 0, st,
+                         g, (int)sp[s].np, (const float*)sp[s].pos[0], (const float*)sp[s].pos[1],
+                         (const float*)sp[s].pos[2], sp[s].cell, (const float*)sp[s].vel[0],
+                         (const float*)sp[s].vel[1], (const float*)sp[s].vel[2], (const float*)sp[s].q,
+                         (float)sp[s].q_const, a, a + nn, a + 4 * nn);
+    else
+      hipLaunchKernelGGL((k_diag_atomic<double, false, double>), dim3(nblocks(sp[s].np, kBlock)), dim3(kBlock), 0,
+                         st, g, (int)sp[s].np, (const double*)sp[s].pos[0], (const double*)sp[s].pos[1],
+                         (const double*)sp[s].pos[2], (const int32_t*)nullptr, (const double*)sp[s].vel[0],
+                         (const double*)sp[s].vel[1], (const double*)sp[s].vel[2], (const double*)sp[s].q,
+                         sp[s].q_const, (double*)rho, (double*)Jd, (double*)P);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (f32) {
+    const unsigned blocks = (unsigned)std::min<int64_t>(nblocks(nn, kBlock), 4096);
+    hipLaunchKernelGGL(k_add_rounded, dim3(blocks), dim3(kBlock), 0, st, nn, a, (float*)rho);
+    hipLaunchKernelGGL(k_add_rounded, dim3(blocks), dim3(kBlock), 0, st, 3 * nn, a + nn, (float*)Jd);
+    hipLaunchKernelGGL(k_add_rounded, dim3(blocks), dim3(kBlock), 0, st, 6 * nn, a + 4 * nn, (float*)P);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_deposit_atomic(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* B, void* J,

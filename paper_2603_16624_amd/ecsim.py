@@ -61,6 +61,8 @@ def lib():
             "ecsim_moments": [P, P, ctypes.c_int32, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32, P],
             "ecsim_move_moments": [P, P, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32,
                                    P],
+            "ecsim_diagnostics": [P, P, ctypes.c_int32, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32, P],
+            "ecsim_diagnostics_workspace_size": [P, ctypes.c_int32, ctypes.c_uint32, P],
             "ecsim_mass_apply": [P, ctypes.c_int32, P, P, ctypes.c_double, ctypes.c_double, P, P],
             "ecsim_moments_backward": [P, P, P, P, P, P, P, P, P, P, ctypes.c_uint32, P],
             "ecsim_sort": [P, P, P, P, P, P, ctypes.c_size_t, P],
@@ -80,7 +82,7 @@ def lib():
 
 
 EXPORTED = ["ecsim_last_error", "ecsim_version", "ecsim_workspace_size", "ecsim_move", "ecsim_moments",
-            "ecsim_move_moments",
+            "ecsim_move_moments", "ecsim_diagnostics", "ecsim_diagnostics_workspace_size",
             "ecsim_mass_apply", "ecsim_moments_backward", "ecsim_sort", "ecsim_centres_to_nodes", "ecsim_to_f32",
             "ecsim_solve_workspace_size", "ecsim_field_solve", "ecsim_field_energy"]
 
@@ -234,6 +236,25 @@ def moments(grid: Grid, species: Sequence[Species], B: torch.Tensor, J: torch.Te
     nbytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(lib().ecsim_moments(ctypes.byref(grid.c()), arr, len(species), _ptr(B), _ptr(J), _ptr(M), _ptr(ws),
                                nbytes, int(flags), _stream(stream)))
+
+
+def diagnostics_workspace_size(grid: Grid, prec: int, flags: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().ecsim_diagnostics_workspace_size(ctypes.byref(grid.c()), int(prec), int(flags), ctypes.byref(out)))
+    return int(out.value)
+
+
+def diagnostics(grid: Grid, species: Sequence[Species], rho: torch.Tensor, J: torch.Tensor, P: torch.Tensor,
+                flags: int = 0, ws: Optional[torch.Tensor] = None, stream=None):
+    """Diagnostic moments summed over species: rho (Nn,), the current without
+    rotation J (3, Nn) and the charge-weighted second velocity moment P (6, Nn)."""
+    arr = (_Particles * len(species))(*[s.c() for s in species])
+    if ws is None:
+        need = diagnostics_workspace_size(grid, species[0].prec if species else F64, flags)
+        ws = torch.empty(need, dtype=torch.uint8, device=rho.device) if need else None
+    nbytes = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(lib().ecsim_diagnostics(ctypes.byref(grid.c()), arr, len(species), _ptr(rho), _ptr(J), _ptr(P), _ptr(ws),
+                                   nbytes, int(flags), _stream(stream)))
 
 
 def move_moments(grid: Grid, species: Sequence[Species], E: torch.Tensor, B: torch.Tensor, B_next: torch.Tensor,

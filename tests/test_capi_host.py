@@ -164,3 +164,40 @@ def test_sort_and_backward_validation(E):
     st = L.ecsim_moments_backward(ctypes.byref(g), ctypes.byref(p), fake, fake, fake, fake, gp, gp, fake, fake,
                                   0x40, None)
     assert st == E.EINVAL
+
+
+def test_diagnostics_argument_validation(E):
+    """ecsim_diagnostics validates before launching anything (no GPU needed)."""
+    L = E.lib()
+    g = _grid(E)
+    fake = ctypes.c_void_p(0x1000)
+    arr = (E._Particles * 2)(_particles(E), _particles(E, prec=E.F32, cell=True))
+    # mixed precisions
+    assert L.ecsim_diagnostics(ctypes.byref(g), arr, 2, fake, fake, fake, None, 0, 0, None) == E.EINVAL
+    arr = (E._Particles * 1)(_particles(E))
+    # no species, unknown flags, sorted without cell_start, NULL outputs
+    assert L.ecsim_diagnostics(ctypes.byref(g), arr, 0, fake, fake, fake, None, 0, 0, None) == E.EINVAL
+    assert L.ecsim_diagnostics(ctypes.byref(g), arr, 1, fake, fake, fake, None, 0, 0x80, None) == E.EINVAL
+    assert L.ecsim_diagnostics(ctypes.byref(g), arr, 1, fake, fake, fake, None, 0, E.SORTED, None) == E.EINVAL
+    for outs in ((None, fake, fake), (fake, None, fake), (fake, fake, None)):
+        assert L.ecsim_diagnostics(ctypes.byref(g), arr, 1, *outs, None, 0, 0, None) == E.EINVAL
+    assert b"ecsim_diagnostics" in L.ecsim_last_error()
+
+
+def test_diagnostics_workspace_size(E):
+    L = E.lib()
+    g = _grid(E)   # 4^3 nodes
+    out = ctypes.c_size_t(0)
+    assert L.ecsim_diagnostics_workspace_size(ctypes.byref(g), E.F32, 0, ctypes.byref(out)) == E.OK
+    assert out.value == 8 * 10 * 64
+    assert L.ecsim_diagnostics_workspace_size(ctypes.byref(g), E.F64, 0, ctypes.byref(out)) == E.OK
+    assert out.value == 0
+    assert L.ecsim_diagnostics_workspace_size(ctypes.byref(g), E.F32, E.SORTED, ctypes.byref(out)) == E.OK
+    assert out.value == 256
+    assert L.ecsim_diagnostics_workspace_size(ctypes.byref(g), 9, 0, ctypes.byref(out)) == E.EINVAL
+    assert L.ecsim_diagnostics_workspace_size(ctypes.byref(g), E.F32, 0x40, ctypes.byref(out)) == E.EINVAL
+    assert L.ecsim_diagnostics_workspace_size(ctypes.byref(g), E.F32, 0, None) == E.EINVAL
+    # FP32 without SORTED needs the workspace
+    fake = ctypes.c_void_p(0x1000)
+    arr = (E._Particles * 1)(_particles(E, prec=E.F32, cell=True))
+    assert L.ecsim_diagnostics(ctypes.byref(g), arr, 1, fake, fake, fake, None, 0, 0, None) == E.EWORKSPACE
