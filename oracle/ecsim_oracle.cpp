@@ -190,7 +190,10 @@ T wrap_position(T x, double L) {
 
 // Mover of Eqs. 4, 5 and 8 for one particle: gathers E^{n+theta} and B^n at
 // x^{n-1/2}, vbar = alpha (v + beta E_p), v^{n+1} = 2 vbar - v^n,
-// x^{n+1/2} = x^{n-1/2} + dt v^{n+1}.
+// x^{n+1/2} = x^{n-1/2} + dt v^{n+1}. In a reduced (1D or 2D) run the
+// positions along the dimensions of a single cell stay where they are: the
+// mover's fixPosition step (Sec. III) keeps particles on their line or plane;
+// the velocity keeps all three components.
 template <class T>
 void move_one(const Grid& g, double beta, T x[3], T v[3], const T Ep[3], const T Bp[3]) {
   T a[9];
@@ -199,7 +202,8 @@ void move_one(const Grid& g, double beta, T x[3], T v[3], const T Ep[3], const T
   for (int c = 0; c < 3; ++c) u[c] = v[c] + beta * Ep[c];
   matvec(a, u, vb);
   for (int c = 0; c < 3; ++c) v[c] = 2.0 * vb[c] - v[c];
-  for (int c = 0; c < 3; ++c) x[c] = wrap_position(x[c] + g.dt * v[c], g.L(c));
+  for (int c = 0; c < 3; ++c)
+    if (g.n[c] > 1) x[c] = wrap_position(x[c] + g.dt * v[c], g.L(c));
 }
 
 // Neumaier-compensated sum.
