@@ -316,6 +316,26 @@ def diagnostics_rate(plasma):
     return out
 
 
+def two_d_rate(args):
+    """The paper's 2D shape (Sec. IV, GPU generations: 128 x 128 cells, 6400
+    particles per cell) as a reduced run: 128 x 128 x 1 cells, 3200 particles
+    per cell per species, 2 species (104,857,600 particles), FP32 form, fused
+    pass, same protocol as the headline line."""
+    from paper_2603_16624_amd import inputs as I
+    import torch
+    t0 = time.perf_counter()
+    p = I.uniform_plasma(2000, (128, 128, 1), 3200)
+    p.name = "128x128x1 cells x 3200 ppc x 2 species (2D)"
+    r = run_form("f32", args, p)
+    keys = ("pass_ms", "kernel_ms", "sort_ms", "solve_ms", "particles_per_s", "particles_per_s_with_sort_every_step",
+            "hbm_frac_pass", "kernel_gbs")
+    out = {k: r[k] for k in keys}
+    out.update(workload=p.name, particles=p.n_particles, wall_s=time.perf_counter() - t0)
+    del p
+    torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_time():
     """Adjoint of mover -> moments (ecsim_moments_backward through the mover) on the
     32^3 x 27 ppc x 2 species workload (1,769,472 particles), FP64 and FP32: time
@@ -388,7 +408,7 @@ def main():
     if not args.no_error:
         err = fixed_error(plasma)
         print(f"[bench] fixed error: {json.dumps(err)}", file=sys.stderr, flush=True)
-    apply = adjoint = diag = None
+    apply = adjoint = diag = two_d = None
     if not args.no_extras:
         apply = mass_apply_rate(args.n)
         print(f"[bench] mass apply: {json.dumps(apply)}", file=sys.stderr, flush=True)
@@ -396,6 +416,8 @@ def main():
         print(f"[bench] adjoint: {json.dumps(adjoint)}", file=sys.stderr, flush=True)
         diag = diagnostics_rate(plasma)
         print(f"[bench] diagnostics: {json.dumps(diag)}", file=sys.stderr, flush=True)
+        two_d = two_d_rate(args)
+        print(f"[bench] 2d: {json.dumps(two_d)}", file=sys.stderr, flush=True)
     if args.calib_copy:
         calibrate_copy()
         print("[bench] copy calibration done", file=sys.stderr, flush=True)
@@ -445,6 +467,7 @@ def main():
         "mass_apply": apply,
         "adjoint_backward": adjoint,
         "diagnostics": diag,
+        "reduced_2d": two_d,
     }
     print(json.dumps(out), flush=True)
 

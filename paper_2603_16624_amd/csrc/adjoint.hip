@@ -92,8 +92,8 @@ __global__ void __launch_bounds__(kBlock) k_backward(
       float oz = push_offset(s0.w1[2], vn.z, dth2, iz, g.nz);
       s1 = stencil_cell(g, ix + g.nx * (iy + g.ny * iz), ox, oy, oz);
     } else {
-      s1 = stencil_abs(g, push_abs(p0[p], g.dt, vn.x, g.nx * g.hx), push_abs(p1[p], g.dt, vn.y, g.ny * g.hy),
-                       push_abs(p2[p], g.dt, vn.z, g.nz * g.hz));
+      s1 = stencil_abs(g, push_abs(p0[p], g.pdt[0], vn.x, g.nx * g.hx), push_abs(p1[p], g.pdt[1], vn.y, g.ny * g.hy),
+                       push_abs(p2[p], g.pdt[2], vn.z, g.nz * g.hz));
     }
   }
   T W1[8];
@@ -167,11 +167,11 @@ __global__ void __launch_bounds__(kBlock) k_backward(
   Vec3<T> gv = gvn;
 
   if constexpr (THROUGH) {
-    // x' = x + dt v' (wrap is a constant shift)
-    const T dt = T(g.dt);
-    gvn.x += dt * gx.x;
-    gvn.y += dt * gx.y;
-    gvn.z += dt * gx.z;
+    // x' = x + dt v' (wrap is a constant shift; no push along a dimension of
+    // one cell)
+    gvn.x += T(g.pdt[0]) * gx.x;
+    gvn.y += T(g.pdt[1]) * gx.y;
+    gvn.z += T(g.pdt[2]) * gx.z;
     // v' = 2 vbar - v, vbar = alpha u
     Vec3<T> gvb{T(2) * gvn.x, T(2) * gvn.y, T(2) * gvn.z};
     gv = Vec3<T>{-gvn.x, -gvn.y, -gvn.z};
@@ -226,8 +226,8 @@ hipError_t launch_T(const Grid& g, const SpeciesArgs& sp, const void* E, const v
   auto args = [&](auto kern) {
     hipLaunchKernelGGL(kern, grid, block, 0, st, g, sp.np, (const T*)sp.pos[0], (const T*)sp.pos[1],
                        (const T*)sp.pos[2], (const int32_t*)sp.cell, (const T*)sp.vel[0], (const T*)sp.vel[1],
-                       (const T*)sp.vel[2], (const T*)sp.q, (T)sp.q_const, (T)beta, (T)(g.dt / g.hx),
-                       (T)(g.dt / g.hy), (T)(g.dt / g.hz), (const T*)E, (const T*)B, (const T*)gJ, (const T*)gM,
+                       (const T*)sp.vel[2], (const T*)sp.q, (T)sp.q_const, (T)beta, (T)(g.pdt[0] / g.hx),
+                       (T)(g.pdt[1] / g.hy), (T)(g.pdt[2] / g.hz), (const T*)E, (const T*)B, (const T*)gJ, (const T*)gM,
                        (T*)gpos[0], (T*)gpos[1], (T*)gpos[2], (T*)gvel[0], (T*)gvel[1], (T*)gvel[2], (T*)gE,
                        (T*)gB);
   };

@@ -52,6 +52,9 @@ ecsim_status make_grid(const ecsim_grid* gr, Grid& g) {
   g.dt = gr->dt;
   g.nn = nn;
   g.V = gr->h[0] * gr->h[1] * gr->h[2];
+  // the mover's fixPosition step for reduced (1D/2D) runs: no push along a
+  // dimension of a single cell
+  for (int d = 0; d < 3; ++d) g.pdt[d] = gr->n[d] > 1 ? gr->dt : 0.0;
   g.div_x = make_fastdiv((uint32_t)g.nx);
   g.div_xy = make_fastdiv((uint32_t)((int64_t)g.nx * g.ny));
   return ECSIM_OK;

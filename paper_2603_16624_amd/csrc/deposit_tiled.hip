@@ -760,9 +760,9 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
         n2 = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
         pcell = ix + g.nx * (iy + g.ny * iz);
       } else {
-        n0 = push_abs(pd.x0, g.dt, v.x, g.nx * g.hx);
-        n1 = push_abs(pd.x1, g.dt, v.y, g.ny * g.hy);
-        n2 = push_abs(pd.x2, g.dt, v.z, g.nz * g.hz);
+        n0 = push_abs(pd.x0, g.pdt[0], v.x, g.nx * g.hx);
+        n1 = push_abs(pd.x1, g.pdt[1], v.y, g.ny * g.hy);
+        n2 = push_abs(pd.x2, g.pdt[2], v.z, g.nz * g.hz);
         const Stencil<double> nps = stencil_abs(g, n0, n1, n2);
         pcell = nps.i[0] + g.nx * (nps.i[1] + g.ny * nps.i[2]);
       }
@@ -1294,9 +1294,9 @@ __global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
         ncell = ix + g.nx * (iy + g.ny * iz);
         gst(sp.cell + p, ncell);
       } else {
-        n0 = push_abs(x0, g.dt, v.x, g.nx * g.hx);
-        n1 = push_abs(x1, g.dt, v.y, g.ny * g.hy);
-        n2 = push_abs(x2, g.dt, v.z, g.nz * g.hz);
+        n0 = push_abs(x0, g.pdt[0], v.x, g.nx * g.hx);
+        n1 = push_abs(x1, g.pdt[1], v.y, g.ny * g.hy);
+        n2 = push_abs(x2, g.pdt[2], v.z, g.nz * g.hz);
         const Stencil<double> nps = stencil_abs(g, n0, n1, n2);
         ncell = nps.i[0] + g.nx * (nps.i[1] + g.ny * nps.i[2]);
       }
@@ -1477,9 +1477,9 @@ TArgs<T> make_args(const Grid& g, const SpeciesArgs* sp, int ns) {
     a.s[s].inv_qom = 1.0 / sp[s].qom;
     a.s[s].cell_start = sp[s].cell_start;
   }
-  a.dth[0] = (T)(g.dt / g.hx);
-  a.dth[1] = (T)(g.dt / g.hy);
-  a.dth[2] = (T)(g.dt / g.hz);
+  a.dth[0] = (T)(g.pdt[0] / g.hx);
+  a.dth[1] = (T)(g.pdt[1] / g.hy);
+  a.dth[2] = (T)(g.pdt[2] / g.hz);
   return a;
 }
 
@@ -1562,6 +1562,10 @@ hipError_t run_diag(const Grid& g, const SpeciesArgs* sp, int ns, void* rho, voi
 
 hipError_t launch_diagnostics_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, void* rho, void* Jd,
                                     void* P, void* zero, hipStream_t st) {
+  if (g.nz == 1) {
+    if (f32) return run_diag<float, 8, 4, 1, 4>(g, sp, ns, rho, Jd, P, zero, st);
+    return run_diag<double, 8, 4, 1, 4>(g, sp, ns, rho, Jd, P, zero, st);
+  }
   if (f32) return run_diag<float, 4, 4, 2, 4>(g, sp, ns, rho, Jd, P, zero, st);
   return run_diag<double, 4, 4, 2, 4>(g, sp, ns, rho, Jd, P, zero, st);
 }
@@ -1583,12 +1587,21 @@ bool tiled_species_ok(const SpeciesArgs* sp, int ns) {
 
 hipError_t launch_deposit_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* B, void* J,
                                 void* M, void* ws, hipStream_t st) {
+  // single-layer (2D) grids take 8x4x1 bricks, so that no brick cell is empty
+  if (g.nz == 1) {
+    if (f32) return run_T<float, 8, 4, 1, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
+    return run_T<double, 8, 4, 1, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
+  }
   if (f32) return run_T<float, 4, 4, 2, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
   return run_T<double, 4, 4, 2, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
 }
 
 hipError_t launch_move_deposit(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* E, const void* B,
                                const void* Bnext, void* J, void* M, double* ke, void* ws, hipStream_t st) {
+  if (g.nz == 1) {
+    if (f32) return run_T<float, 8, 4, 1, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st);
+    return run_T<double, 8, 4, 1, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st);
+  }
   if (f32) return run_T<float, 4, 4, 2, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st);
   return run_T<double, 4, 4, 2, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st);
 }

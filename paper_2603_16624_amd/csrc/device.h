@@ -52,6 +52,8 @@ struct Grid {
   double V;          // control volume of a node
   FastDiv div_x;     // by nx
   FastDiv div_xy;    // by nx * ny
+  double pdt[3];     // position push time step per dimension: dt, or 0 along a
+                     // dimension of one cell (reduced runs keep positions there)
 };
 
 template <typename T> struct Vec3 { T x, y, z; };

@@ -77,9 +77,9 @@ __global__ void __launch_bounds__(kBlock) k_move(Grid g, int np, T* __restrict__
       p2[p] = oz;
       cell[p] = ix + g.nx * (iy + g.ny * iz);
     } else {
-      p0[p] = push_abs(p0[p], g.dt, vn.x, g.nx * g.hx);
-      p1[p] = push_abs(p1[p], g.dt, vn.y, g.ny * g.hy);
-      p2[p] = push_abs(p2[p], g.dt, vn.z, g.nz * g.hz);
+      p0[p] = push_abs(p0[p], g.pdt[0], vn.x, g.nx * g.hx);
+      p1[p] = push_abs(p1[p], g.pdt[1], vn.y, g.ny * g.hy);
+      p2[p] = push_abs(p2[p], g.pdt[2], vn.z, g.nz * g.hz);
     }
     if (ke) {
       double qp = q ? (double)q[p] : q_const;
@@ -322,7 +322,7 @@ hipError_t launch_move(const Grid& g, bool f32, const SpeciesArgs& sp, const voi
     hipLaunchKernelGGL((k_move<float, true>), dim3(nblocks_capped(sp.np, kBlock)), dim3(kBlock), 0, st, g, sp.np,
                        (float*)sp.pos[0], (float*)sp.pos[1], (float*)sp.pos[2], sp.cell, (float*)sp.vel[0],
                        (float*)sp.vel[1], (float*)sp.vel[2], (const float*)E, (const float*)B, (float)beta,
-                       (float)(g.dt / g.hx), (float)(g.dt / g.hy), (float)(g.dt / g.hz), (const float*)sp.q,
+                       (float)(g.pdt[0] / g.hx), (float)(g.pdt[1] / g.hy), (float)(g.pdt[2] / g.hz), (const float*)sp.q,
                        sp.q_const, inv_qom, ke);
   } else {
     hipLaunchKernelGGL((k_move<double, false>), dim3(nblocks_capped(sp.np, kBlock)), dim3(kBlock), 0, st, g, sp.np,

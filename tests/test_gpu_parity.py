@@ -204,7 +204,7 @@ def test_moments_sorted_tiled(E, O, I, n, ppc, prec):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("n,ppc,vscale", [((8, 8, 8), 27, 1.0), ((6, 5, 4), 9, 40.0), ((2, 3, 2), 7, 20.0),
-                                           ((13, 7, 5), 3, 5.0)])
+                                           ((13, 7, 5), 3, 5.0), ((8, 6, 1), 12, 10.0), ((16, 1, 1), 20, 10.0)])
 def test_move_moments_fused(E, O, I, prec, n, ppc, vscale):
     """Fused mover + deposit (two passes on one stale grouping) against the oracle's move then moments.
 
@@ -450,6 +450,41 @@ def test_centres_to_nodes_and_energy(E, O, I):
     out = torch.zeros(1, dtype=torch.float64, device="cuda")
     E.field_energy(grid, dev(BC), out)
     assert abs(host(out)[0] - O.field_energy(n, (0.5,) * 3, BC)) < 1e-13 * O.field_energy(n, (0.5,) * 3, BC)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_two_dimensional_run(E, O, I, prec):
+    """A reduced run, 8 x 8 x 1 cells x 27 ppc x 2 species, fused path, 8 steps:
+    positions along z stay put (fixPosition), energy is conserved (FP64) and
+    the state matches the oracle's run."""
+    say("2D run", prec)
+    p = I.uniform_plasma(95, (8, 8, 1), 27)
+    P = E.F64 if prec == "f64" else E.F32
+    sim = E.Simulation(p, prec=P, tol=1e-10, fused=True, sort_every=3)
+    if prec == "f32":
+        for s, f in zip(p.species, I.to_f32_state(p)):
+            s.x, s.v, s.q = f["x64"], f["v64"], f["q64"]
+    z0 = [s.x[2].copy() for s in p.species]
+    K0 = sum(O.kinetic(s.v, s.q, s.qom) for s in p.species)
+    WE0, WB0 = sim.energy()
+    e0 = K0 + WE0 + WB0
+    drift = 0.0
+    for step in range(8):
+        sim.step()
+        WE, WB = sim.energy()
+        drift = max(drift, abs(host(sim.scal)[0] + WE + WB - e0) / e0)
+    if prec == "f64":
+        assert drift <= 1e-10
+        ref, _ = O.run_steps(p, 8, tol=1e-13)
+        assert rel(host(sim.E), ref["E"]) < 1e-9
+    else:
+        assert drift <= 1e-5
+    for s, z in zip(sim.species, z0):
+        if prec == "f64":
+            zs = host(s.pos)[2]
+        else:
+            zs = I.decode_f32(host(s.cell), host(s.pos), p.n, p.h)[2]
+        assert np.array_equal(np.sort(zs), np.sort(z))
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
