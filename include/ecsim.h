@@ -104,6 +104,10 @@ ecsim_status ecsim_workspace_size(const ecsim_grid *grid, int64_t np, int32_t pr
  *              (q/m) dt / 2;
  *   v^{n+1}  = 2 vbar - v^n;  x^{n+1/2} = x^{n-1/2} + dt v^{n+1}, wrapped into
  *              the periodic box (F32: offset and cell updated).
+ * Along a dimension of a single cell (a reduced 1D or 2D run) positions are
+ * not pushed: the mover's fixPosition step (Sec. III) keeps particles on
+ * their line or plane; velocities keep all three components. The same holds
+ * in ecsim_move_moments and in the adjoint through the mover.
  * Updates pos/cell/vel of `sp` in place, preserving particle order.
  * E_node, B_node: [3][Nn] in the particles' precision.
  * ke_out: optional device double; receives (+=) sum_p 1/2 m_p |v^{n+1}|^2 with
