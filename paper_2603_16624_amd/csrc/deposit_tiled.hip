@@ -747,10 +747,7 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
         Bp.y = fma(w, fld[4 * HN + nl], Bp.y);
         Bp.z = fma(w, fld[5 * HN + nl], Bp.z);
       }
-      T a0[9];
-      rotation(Bp, sp.beta, a0);
-      Vec3<T> u;
-      const Vec3<T> v = velocity_update(a0, Vec3<T>{pd.v0, pd.v1, pd.v2}, Ep, sp.beta, u);
+      const Vec3<T> v = advance_velocity(Bp, sp.beta, Vec3<T>{pd.v0, pd.v1, pd.v2}, Ep);
       T n0, n1, n2;
       int pcell;
       if constexpr (sizeof(T) == 4) {
@@ -1280,10 +1277,7 @@ __global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
       corners(g, ps, W, nd);
       const Vec3<T> Ep = gather(args.Emove, g.nn, W, nd);
       const Vec3<T> Bp = gather(args.Bmove, g.nn, W, nd);
-      T a0[9];
-      rotation(Bp, sp.beta, a0);
-      Vec3<T> u;
-      const Vec3<T> v = velocity_update(a0, Vec3<T>{ul.vel[0][i], ul.vel[1][i], ul.vel[2][i]}, Ep, sp.beta, u);
+      const Vec3<T> v = advance_velocity(Bp, sp.beta, Vec3<T>{ul.vel[0][i], ul.vel[1][i], ul.vel[2][i]}, Ep);
       T n0, n1, n2;
       int ncell;
       if constexpr (sizeof(T) == 4) {

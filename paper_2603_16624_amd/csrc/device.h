@@ -196,6 +196,29 @@ __device__ __forceinline__ Vec3<T> velocity_update(const T a[9], Vec3<T> v, Vec3
   return Vec3<T>{T(2) * vb.x - v.x, T(2) * vb.y - v.y, T(2) * vb.z - v.z};
 }
 
+// The mover's step of Eqs. 3-5 from the gathered fields. In the FP32 form
+// alpha and the update are evaluated in FP64 and v^{n+1} is rounded once: the
+// map v -> (2 alpha - I) v is a rotation, but with alpha rounded to FP32 it
+// scales |v| by 1 + O(1e-7), and where B is nearly uniform all particles share
+// that rounding, so the kinetic energy would drift one way every step. A single
+// rounding of the result is unbiased and averages out over the particles.
+template <typename T>
+__device__ __forceinline__ Vec3<T> advance_velocity(Vec3<T> Bp, T beta, Vec3<T> v, Vec3<T> Ep) {
+  if constexpr (sizeof(T) == 4) {
+    double a[9];
+    rotation(Vec3<double>{Bp.x, Bp.y, Bp.z}, (double)beta, a);
+    Vec3<double> u;
+    const Vec3<double> r =
+        velocity_update(a, Vec3<double>{v.x, v.y, v.z}, Vec3<double>{Ep.x, Ep.y, Ep.z}, (double)beta, u);
+    return Vec3<T>{(T)r.x, (T)r.y, (T)r.z};
+  } else {
+    T a[9];
+    rotation(Bp, beta, a);
+    Vec3<T> u;
+    return velocity_update(a, v, Ep, beta, u);
+  }
+}
+
 // Position push of Eq. 8, FP64 form: x + dt v wrapped into [0, L); a result
 // that rounds to L is stored as 0.
 __device__ __forceinline__ double push_abs(double x, double dt, double v, double L) {

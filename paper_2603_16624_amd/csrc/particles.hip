@@ -59,11 +59,7 @@ __global__ void __launch_bounds__(kBlock) k_move(Grid g, int np, T* __restrict__
     corners(g, s, W, nd);
     Vec3<T> Ep = gather(E, g.nn, W, nd);
     Vec3<T> Bp = gather(B, g.nn, W, nd);
-    T a[9];
-    rotation(Bp, beta, a);
-    Vec3<T> v{v0[p], v1[p], v2[p]};
-    Vec3<T> u;
-    Vec3<T> vn = velocity_update(a, v, Ep, beta, u);
+    Vec3<T> vn = advance_velocity(Bp, beta, Vec3<T>{v0[p], v1[p], v2[p]}, Ep);
     v0[p] = vn.x;
     v1[p] = vn.y;
     v2[p] = vn.z;

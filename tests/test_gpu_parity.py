@@ -478,7 +478,8 @@ def test_two_dimensional_run(E, O, I, prec):
         ref, _ = O.run_steps(p, 8, tol=1e-13)
         assert rel(host(sim.E), ref["E"]) < 1e-9
     else:
-        assert drift <= 1e-5
+        # 3,456 particles: the once-per-step rounding of v averages less
+        assert drift <= 1e-8
     for s, z in zip(sim.species, z0):
         if prec == "f64":
             zs = host(s.pos)[2]
@@ -531,8 +532,10 @@ def test_small_workload_ten_steps(E, O, I, prec, sort):
                 assert rel(host(s.vel)[:, ka], v[:, kb]) < 1e-9
                 assert periodic_rel(host(s.pos)[:, ka], x[:, kb], p.L) < 1e-9
     else:
-        # FP32 particle arithmetic: energy error from FP32 rounding of v, J and M
-        assert drift <= 1e-6
+        # FP32 particle state: each stored velocity is rounded once per step (the
+        # update itself is formed in FP64), an unbiased error that averages over
+        # the 27,648 particles to a few 1e-10 over ten steps
+        assert drift <= 3e-9
 
 
 # ---------------------------------------------------------------------------
