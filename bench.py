@@ -72,15 +72,17 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(prec, nparticles, nn):
+def algorithmic_bytes(prec, nparticles, nn, q_read=0):
     """Bytes the fused mover + moments pass must move per step.
 
     Per particle: the state (positions + velocities [+ cell]) read once and
-    written once; per node: E^{n+theta}, B^n and B^{n+1} read, J-hat and the
-    14 x 9 mass-matrix entries written once.
+    written once, and a per-particle charge read (``q_read`` particles, none
+    when every particle of a species has the same charge); per node:
+    E^{n+theta}, B^n and B^{n+1} read, J-hat and the 14 x 9 mass-matrix
+    entries written once.
     """
     part, fld = (28, 4) if prec == "f32" else (48, 8)
-    return 2 * part * nparticles + fld * (9 + 3 + 126) * nn
+    return 2 * part * nparticles + fld * q_read + fld * (9 + 3 + 126) * nn
 
 
 def _median(a):
@@ -161,7 +163,8 @@ def run_form(prec, args, plasma):
     full_ms = _median(el(0, 7))
     pass_ms = fields_ms + kernel_ms + moments_ms + sort_ms / args.sort_every
     npart = plasma.n_particles
-    nbytes = algorithmic_bytes(prec, npart, plasma.nn)
+    q_read = sum(sp.np for sp in plasma.species if sp.q_uniform is None)
+    nbytes = algorithmic_bytes(prec, npart, plasma.nn, q_read)
     out = dict(prec=prec, path=args.path, particles=npart, pass_ms=pass_ms, fields_ms=fields_ms, kernel_ms=kernel_ms,
                moments_ms=moments_ms, sort_ms=sort_ms, sort_every=args.sort_every, solve_ms=solve_ms,
                full_step_ms=full_ms, wall_s=wall, gmres_iters=sim.last_iters, gmres_resid=sim.last_resid,
@@ -336,6 +339,24 @@ def two_d_rate(args):
     return out
 
 
+def harris_rate(args):
+    """The double Harris current sheet, 256 x 128 x 8 cells x 128 ppc x 2 species
+    (67,108,864 particles, each with its own charge), FP32 form, fused pass,
+    same protocol as the headline line."""
+    from paper_2603_16624_amd import inputs as I
+    import torch
+    t0 = time.perf_counter()
+    p = I.harris()
+    r = run_form("f32", args, p)
+    keys = ("pass_ms", "kernel_ms", "sort_ms", "solve_ms", "gmres_iters", "particles_per_s",
+            "particles_per_s_with_sort_every_step", "bytes_per_step", "hbm_frac_pass", "kernel_gbs")
+    out = {k: r[k] for k in keys}
+    out.update(workload=p.name, particles=p.n_particles, wall_s=time.perf_counter() - t0)
+    del p
+    torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_time():
     """Adjoint of mover -> moments (ecsim_moments_backward through the mover) on the
     32^3 x 27 ppc x 2 species workload (1,769,472 particles), FP64 and FP32: time
@@ -408,7 +429,7 @@ def main():
     if not args.no_error:
         err = fixed_error(plasma)
         print(f"[bench] fixed error: {json.dumps(err)}", file=sys.stderr, flush=True)
-    apply = adjoint = diag = two_d = None
+    apply = adjoint = diag = two_d = harris = None
     if not args.no_extras:
         apply = mass_apply_rate(args.n)
         print(f"[bench] mass apply: {json.dumps(apply)}", file=sys.stderr, flush=True)
@@ -418,6 +439,8 @@ def main():
         print(f"[bench] diagnostics: {json.dumps(diag)}", file=sys.stderr, flush=True)
         two_d = two_d_rate(args)
         print(f"[bench] 2d: {json.dumps(two_d)}", file=sys.stderr, flush=True)
+        harris = harris_rate(args)
+        print(f"[bench] harris: {json.dumps(harris)}", file=sys.stderr, flush=True)
     if args.calib_copy:
         calibrate_copy()
         print("[bench] copy calibration done", file=sys.stderr, flush=True)
@@ -468,6 +491,7 @@ def main():
         "adjoint_backward": adjoint,
         "diagnostics": diag,
         "reduced_2d": two_d,
+        "double_harris": harris,
     }
     print(json.dumps(out), flush=True)
 

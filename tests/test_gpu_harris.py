@@ -1,0 +1,140 @@
+"""The double Harris current sheet at full size in the FP32 form: 256 x 128 x 8
+periodic cells, 128 particles per cell per species (67,108,864 particles),
+each particle carrying the charge of the local sheet-plus-background density.
+Twenty steps of the scheme (moments -> GMRES -> mover, Sec. II), with the
+adjoint of mover -> moments evaluated on the last step's state.
+
+Checked against the FP64 oracle fed the FP32 values widened exactly
+(relative max-norm over each sample, 1e-5):
+
+* the total energy over the twenty steps, against the GMRES tolerance;
+* the adjoint on the last step: position and velocity gradients of sampled
+  particles, and the E and B gradients at sampled nodes (the oracle
+  differentiates every particle that starts within reach of them);
+* J-hat and the 14 stored blocks after the last pass at sampled nodes, from
+  the GPU's own final particle state.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import dev, host, need_gpu, rel, say, torch
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+STEPS = 20
+NSAMPLE = 4096     # sampled particles per species
+NNODES = 4         # sampled nodes
+
+
+@pytest.fixture(scope="module")
+def E():
+    need_gpu()
+    from paper_2603_16624_amd import ecsim
+    ecsim.lib()
+    return ecsim
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def near_mask(n, nodes):
+    """Cells from which a particle can reach the sampled nodes within one move
+    (its stencil before or after the move): the 4^3 cells around each node."""
+    nx, ny, nz = n
+    near = np.zeros(nx * ny * nz, dtype=bool)
+    for g in nodes:
+        gx, gy, gz = g % nx, (g // nx) % ny, g // (nx * ny)
+        for dz in range(-2, 2):
+            for dy in range(-2, 2):
+                for dx in range(-2, 2):
+                    near[(gx + dx) % nx + nx * (((gy + dy) % ny) + ny * ((gz + dz) % nz))] = True
+    return near
+
+
+def state64(I, p, s, idx):
+    """Widened FP32 state (position, velocity, charge) of the particles idx."""
+    cell = host(s.cell)[idx]
+    off = host(s.pos)[:, idx]
+    x = I.decode_f32(cell, off, p.n, p.h)
+    return x, host(s.vel)[:, idx].astype(np.float64), host(s.q)[idx].astype(np.float64)
+
+
+@pytest.mark.timeout(600)
+def test_harris_twenty_steps_with_adjoint(E, O):
+    from paper_2603_16624_amd import inputs as I
+    p = I.harris()
+    say("double Harris", p.name, p.n_particles)
+    sim = E.Simulation(p, prec=E.F32, tol=1e-10, fused=True, sort_every=4)
+    assert all(s.q is not None for s in sim.species)
+    K0 = 0.0
+    for ps, s in zip(p.species, sim.species):
+        K0 += O.kinetic(host(s.vel).astype(np.float64), host(s.q).astype(np.float64), ps.qom)
+    WE0, WB0 = sim.energy()
+    e0 = K0 + WE0 + WB0
+    drift = 0.0
+
+    def note_energy():
+        WE, WB = sim.energy()
+        return max(drift, abs(host(sim.scal)[0] + WE + WB - e0) / e0)
+
+    for _ in range(STEPS - 1):
+        sim.step()
+        assert sim.last_resid <= 1e-10
+        drift = note_energy()
+    say("drift after", STEPS - 1, "steps", drift)
+
+    # the last step by hand, with the adjoint on its pre-move state
+    sim.solve()
+    assert sim.last_resid <= 1e-10
+    sim.fused_fields()
+    rng = np.random.default_rng(4007)
+    gJ = rng.standard_normal((3, p.nn)).astype(np.float32)
+    gM = rng.standard_normal((14, 9, p.nn)).astype(np.float32)
+    gJd, gMd = dev(gJ, torch.float32), dev(gM, torch.float32)
+    gE = torch.zeros((3, p.nn), dtype=torch.float32, device="cuda")
+    gB = torch.zeros((3, p.nn), dtype=torch.float32, device="cuda")
+    Et64, Bn64 = host(sim.Et_p).astype(np.float64), host(sim.BN_p).astype(np.float64)
+    gJ64, gM64 = gJ.astype(np.float64), gM.astype(np.float64)
+    nodes = rng.choice(p.nn, size=NNODES, replace=False)
+    near = near_mask(p.n, nodes)
+    gEo, gBo = np.zeros((3, p.nn)), np.zeros((3, p.nn))
+    for ps, s in zip(p.species, sim.species):
+        gx, gv = torch.empty_like(s.pos), torch.empty_like(s.vel)
+        E.moments_backward(sim.grid, s, sim.Et_p, sim.BN_p, gJd, gMd, gx, gv, gE, gB, through_mover=True)
+        k = rng.choice(s.np, size=NSAMPLE, replace=False)
+        x, v, q = state64(I, p, s, k)
+        gxo, gvo, _, _ = O.grad(p.n, p.h, p.dt, x, v, q, ps.qom, Et64, Bn64, gJ64, gM64)
+        assert rel(host(gx)[:, k], gxo) < TOL
+        assert rel(host(gv)[:, k], gvo) < TOL
+        del gx, gv
+        idx = np.nonzero(near[host(s.cell)])[0]
+        x, v, q = state64(I, p, s, idx)
+        O.grad(p.n, p.h, p.dt, x, v, q, ps.qom, Et64, Bn64, gJ64, gM64, gEo, gBo)
+    assert rel(host(gE)[:, nodes], gEo[:, nodes]) < TOL
+    assert rel(host(gB)[:, nodes], gBo[:, nodes]) < TOL
+    say("adjoint checked on", NSAMPLE, "particles per species and", NNODES, "nodes")
+    del gE, gB, gJd, gMd
+
+    sim.scal[0] = 0.0
+    sim.fused_particles(sim.scal[0:1])
+    sim.advance_fused()
+    drift = note_energy()
+    say("drift after", STEPS, "steps", drift)
+    assert drift <= 1e-10
+
+    # the moments of the last pass: the GPU's final state, with B^{n+1}
+    Bnext64 = host(sim.BN_p).astype(np.float64)
+    Jo = np.zeros((3, p.nn))
+    M27 = np.zeros((27, 9, p.nn))
+    for ps, s in zip(p.species, sim.species):
+        idx = np.nonzero(near[host(s.cell)])[0]
+        x, v, q = state64(I, p, s, idx)
+        O.moments(p.n, p.h, p.dt, x, v, q, ps.qom, Bnext64, Jo, M27)
+    Mo = O.m14(p.n, M27)
+    assert rel(host(sim.J)[:, nodes], Jo[:, nodes]) < TOL
+    assert rel(host(sim.M)[:, :, nodes], Mo[:, :, nodes]) < TOL
