@@ -530,16 +530,21 @@ __device__ __forceinline__ void flush_brick(const Grid& g, const T* scell, int x
     const int ln = is_m ? it % NN : (it - 9 * NN) % NN;
     const int sub = is_m ? it / NN : (it - 9 * NN) / NN;   // ij, or the current component
     const int nx_ = ln % NX, ny_ = (ln / NX) % NY, nz_ = ln / (NX * NY);
-    // cells n - a that exist in this brick
-    int vmask = 0;
+    // the cells n - a of this brick, as offsets into the per-cell sums; a
+    // cell beyond the brick reads cell 0 and is masked to zero (adding +0
+    // leaves every sum as it would be without the term), so the gather runs
+    // without divergent branches
+    int coff[8];
+    bool cin[8];
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       const int lcx = nx_ - (a & 1), lcy = ny_ - ((a >> 1) & 1), lcz = nz_ - ((a >> 2) & 1);
-      if (lcx >= 0 && lcx < TX && lcy >= 0 && lcy < TY && lcz >= 0 && lcz < TZ) vmask |= 1 << a;
+      cin[a] = lcx >= 0 && lcx < TX && lcy >= 0 && lcy < TY && lcz >= 0 && lcz < TZ;
+      coff[a] = cin[a] ? (lcx + TX * (lcy + TY * lcz)) * SCS : 0;
     }
-    const int cbase = nx_ + TX * (ny_ + TY * nz_);          // cell index of n (may lie outside)
     const int gx = wrap_once(x0 + nx_, g.nx), gy = wrap_once(y0 + ny_, g.ny), gz = wrap_once(z0 + nz_, g.nz);
     const int64_t gn = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
+    const T* const sb = scell + sub;
     if (is_m) {
 #pragma unroll
       for (int k = 0; k < 14; ++k) {
@@ -548,10 +553,8 @@ __device__ __forceinline__ void flush_brick(const Grid& g, const T* scell, int x
         for (int a = 0; a < 8; ++a) {
           const int cls = pair_class(k, a);
           if (cls < 0) continue;
-          if (vmask & (1 << a)) {
-            const int cidx = cbase - ((a & 1) + TX * (((a >> 1) & 1) + TY * ((a >> 2) & 1)));
-            v += scell[cidx * SCS + cls * 9 + sub];
-          }
+          const T x = sb[coff[a] + cls * 9];
+          v += cin[a] ? x : T(0);
         }
         if (v != T(0)) unsafeAtomicAdd(M + (int64_t)(k * 9 + sub) * g.nn + gn, v);
       }
@@ -559,10 +562,8 @@ __device__ __forceinline__ void flush_brick(const Grid& g, const T* scell, int x
       T v = T(0);
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
-        if (vmask & (1 << a)) {
-          const int cidx = cbase - ((a & 1) + TX * (((a >> 1) & 1) + TY * ((a >> 2) & 1)));
-          v += scell[cidx * SCS + 243 + 3 * a + sub];
-        }
+        const T x = sb[coff[a] + 243 + 3 * a];
+        v += cin[a] ? x : T(0);
       }
       if (v != T(0)) unsafeAtomicAdd(J + (int64_t)sub * g.nn + gn, v);
     }

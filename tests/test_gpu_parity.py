@@ -325,6 +325,50 @@ def test_moments_accumulate_flag(E, O, I):
     assert rel(host(J), Jo) < TOL64 and rel(host(M), Mo) < TOL64
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [(5, 6, 3), (9, 5, 1)])
+def test_clear_and_accumulate_grouped(E, O, I, prec, n):
+    """The grouped calls clear J and M over the whole grid (bricks that the grid
+    cuts short included) unless ECSIM_ACCUMULATE is set, when they add to them:
+    outputs prefilled with 7 are overwritten, and an accumulating second call
+    doubles the first. Moments-only and fused calls."""
+    say("clear / accumulate", prec, n)
+    p, En, BN = make_case(I, n, 6, 41)
+    grid = E.Grid(p.n, p.h, p.dt)
+    if prec == "f64":
+        mk = lambda: [E.Species.from_f64(s.qom, s.x, s.v, s.q) for s in p.species]
+        xs, vs, qs = [s.x for s in p.species], [s.v for s in p.species], [s.q for s in p.species]
+        Bc, Ec, tdt, tol = BN, En, torch.float64, TOL64
+    else:
+        st = I.to_f32_state(p)
+        mk = lambda: [E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"]) for s, f in zip(p.species, st)]
+        xs, vs, qs = [f["x64"] for f in st], [f["v64"] for f in st], [f["q64"] for f in st]
+        Bc, Ec, tdt, tol = round32(BN), round32(En), torch.float32, TOL32
+    Bd, Ed = dev(Bc, tdt), dev(Ec, tdt)
+    full = lambda shape: torch.full(shape, 7.0, dtype=tdt, device="cuda")
+    # moments only
+    sp = sorted_species(E, grid, mk())
+    J, M = full((3, p.nn)), full((14, 9, p.nn))
+    E.moments(grid, sp, Bd, J, M, flags=E.SORTED)
+    Jo, Mo = oracle_moments(O, p, xs, vs, qs, Bc)
+    assert rel(host(J), Jo) < tol and rel(host(M), Mo) < tol
+    E.moments(grid, sp, Bd, J, M, flags=E.SORTED | E.ACCUMULATE)
+    assert rel(host(J), 2 * Jo) < tol and rel(host(M), 2 * Mo) < tol
+    # fused: two copies of the same state
+    J1, M1 = full((3, p.nn)), full((14, 9, p.nn))
+    E.move_moments(grid, sorted_species(E, grid, mk()), Ed, Bd, Bd, J1, M1)
+    xo, vo = [], []
+    for s, x, v in zip(p.species, xs, vs):
+        a, b = O.move(p.n, p.h, p.dt, x, v, s.qom, Ec, Bc)
+        xo.append(a)
+        vo.append(b)
+    Jo, Mo = oracle_moments(O, p, xo, vo, qs, Bc)
+    assert rel(host(J1), Jo) < tol and rel(host(M1), Mo) < tol
+    J2, M2 = J1.clone(), M1.clone()
+    E.move_moments(grid, sorted_species(E, grid, mk()), Ed, Bd, Bd, J2, M2, flags=E.ACCUMULATE)
+    assert rel(host(J2), 2 * host(J1)) < tol and rel(host(M2), 2 * host(M1)) < tol
+
+
 # ---------------------------------------------------------------------------
 # sort
 # ---------------------------------------------------------------------------
