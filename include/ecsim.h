@@ -179,6 +179,33 @@ ecsim_status ecsim_move_moments(const ecsim_grid *grid, const ecsim_particles *s
                                 void *ws, size_t ws_bytes, uint32_t flags, void *stream);
 
 /*
+ * The fused particle pass of ecsim_move_moments (same moves, same J and M),
+ * which also regroups the particles by cell for the next pass: the deposit
+ * takes every particle cell by cell (a cell's own range particles still in
+ * it, then the particles that arrived), and writes each species' particles in
+ * that order to dst[s], whose cell_start receives the new ranges. The paper
+ * does not sort its particles (Sec. III); here the grouping that the tiled
+ * deposit relies on is kept exact every step at the cost of one more write of
+ * the particle state, in place of a separate sort.
+ *   species: as for ecsim_move_moments (grouped, cell_start required); their
+ *            arrays are moved in place and are no longer grouped afterwards.
+ *   dst:     nspecies targets (device arrays) of the same precision and sizes,
+ *            with a per-particle charge array exactly where the source has
+ *            one, a cell array in the FP32 form and a cell_start of
+ *            cells + 1 int32 (device out); none may alias a source array.
+ *            After the call dst[s] holds species s's moved particles in cell
+ *            order (positions, velocities, charges, cells) and is what the
+ *            next pass takes as `species`.
+ * Needs nspecies * cells <= 2^20. Workspace, flags, ke_out and errors as for
+ * ecsim_move_moments (ECSIM_EINVAL also for a mismatched or aliasing target).
+ */
+ecsim_status ecsim_move_moments_regroup(const ecsim_grid *grid, const ecsim_particles *species,
+                                        const ecsim_particles *dst, int32_t nspecies,
+                                        const void *E_node, const void *B_node, const void *B_next,
+                                        void *J, void *M, double *ke_out, void *ws, size_t ws_bytes,
+                                        uint32_t flags, void *stream);
+
+/*
  * Matrix-free mass-matrix apply inside the field solve (Eq. 7):
  *   y = a * (M x) + b * y,   (M x)_g = sum over the 27 neighbours g' of
  *   M_{g g'} x_{g'}, using the 14 stored blocks and M_{g,g-o} = M_{g-o,g}

@@ -252,6 +252,60 @@ ecsim_status ecsim_move_moments(const ecsim_grid* grid, const ecsim_particles* s
   return ECSIM_OK;
 }
 
+ecsim_status ecsim_move_moments_regroup(const ecsim_grid* grid, const ecsim_particles* species,
+                                        const ecsim_particles* dst, int32_t nspecies, const void* E_node,
+                                        const void* B_node, const void* B_next, void* J, void* M, double* ke_out,
+                                        void* ws, size_t ws_bytes, uint32_t flags, void* stream) {
+  const char* who = "ecsim_move_moments_regroup";
+  Grid g;
+  SpeciesArgs a[kMaxSpecies], d[kMaxSpecies];
+  if (flags & ~(uint32_t)(ECSIM_ACCUMULATE | ECSIM_SORTED)) return fail(ECSIM_EINVAL, "%s: unknown flags 0x%x", who, flags);
+  if (species_list(grid, species, nspecies, g, a, who, flags, true) != ECSIM_OK) return ECSIM_EINVAL;
+  if (!dst) return fail(ECSIM_EINVAL, "%s: dst is NULL", who);
+  if (!E_node || !B_node || !B_next || !J || !M)
+    return fail(ECSIM_EINVAL, "%s: E_node, B_node, B_next, J and M are required", who);
+  if (!tiled_species_ok(a, nspecies))
+    return fail(ECSIM_EINVAL, "%s: at most 4 species of fewer than 2^28 particles each", who);
+  if ((int64_t)nspecies * g.nn > regroup_max_entries())
+    return fail(ECSIM_EINVAL, "%s: species x cells = %lld exceeds %lld", who, (long long)nspecies * g.nn,
+                (long long)regroup_max_entries());
+  for (int s = 0; s < nspecies; ++s) {
+    if (make_species(&dst[s], d[s], who) != ECSIM_OK) return ECSIM_EINVAL;
+    if (dst[s].prec != species[s].prec || dst[s].np != species[s].np)
+      return fail(ECSIM_EINVAL, "%s: dst[%d] differs from species[%d] in precision or size", who, s, s);
+    if ((dst[s].q == nullptr) != (species[s].q == nullptr))
+      return fail(ECSIM_EINVAL, "%s: dst[%d] and species[%d] differ in per-particle charge", who, s, s);
+    if (!dst[s].cell_start) return fail(ECSIM_EINVAL, "%s: dst[%d].cell_start is required", who, s);
+    // no target may alias a source array of any species
+    const void* tg[9] = {dst[s].pos[0], dst[s].pos[1], dst[s].pos[2], dst[s].vel[0], dst[s].vel[1],
+                         dst[s].vel[2], dst[s].q, dst[s].cell, dst[s].cell_start};
+    for (int r = 0; r < nspecies; ++r) {
+      const void* sr[9] = {species[r].pos[0], species[r].pos[1], species[r].pos[2], species[r].vel[0],
+                           species[r].vel[1], species[r].vel[2], species[r].q, species[r].cell,
+                           species[r].cell_start};
+      for (int i = 0; i < 9; ++i)
+        for (int j = 0; j < 9; ++j)
+          if (tg[i] && tg[i] == sr[j]) return fail(ECSIM_EINVAL, "%s: dst[%d] aliases species[%d]", who, s, r);
+    }
+  }
+  int64_t np_total = 0;
+  for (int s = 0; s < nspecies; ++s) np_total += a[s].np;
+  const bool f32 = species[0].prec == ECSIM_F32;
+  const size_t need = tiled_workspace_bytes(g, np_total, f32);
+  if (!ws || ws_bytes < need)
+    return fail(ECSIM_EWORKSPACE, "%s: workspace of %zu bytes needed, %zu given", who, need, ws ? ws_bytes : 0);
+  const size_t esz = f32 ? 4 : 8;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (!(flags & ECSIM_ACCUMULATE)) {
+    if ((e = launch_zero(J, esz * 3 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_move_moments_regroup zero J");
+    if ((e = launch_zero(M, esz * 126 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_move_moments_regroup zero M");
+  }
+  e = launch_move_deposit_regroup(g, f32, a, d, nspecies, E_node, B_node, B_next, J, M, ke_out, ws, st);
+  if (e != hipSuccess) return hip_fail(e, who);
+  return ECSIM_OK;
+}
+
 ecsim_status ecsim_mass_apply(const ecsim_grid* grid, int32_t m_prec, const void* M, const double* x, double a,
                               double b, double* y, void* stream) {
   Grid g;

@@ -92,6 +92,18 @@ struct StrayData {
   int32_t* sp;
 };
 
+// Where the regrouping deposit writes a species' particles in cell order, and
+// the cell ranges (start[c] .. start[c + 1]) it writes them in.
+template <typename T>
+struct RegroupDst {
+  T* pos[3];
+  T* vel[3];
+  T* q;              // NULL for a constant-charge species
+  int32_t* cell;     // FP32 form only
+  int32_t* start;
+  int np;
+};
+
 template <typename T>
 struct TArgs {
   TSpecies<T> s[kMaxTiledSpecies];
@@ -109,6 +121,11 @@ struct TArgs {
   const void* zero;       // 64 zero bytes: the load target of idle lanes
   void* sink;             // the store target of idle lanes (never read)
   double* ke;
+  // regrouping (NULL stay: off): per (species, cell) the particles that stayed
+  // in their range's cell and the listed strays, and the targets
+  int* stay;
+  int* scount;
+  RegroupDst<T> dst[kMaxTiledSpecies];
 };
 
 // Kahan compensated summation: the true running sum is s - c.
@@ -437,6 +454,19 @@ __device__ __forceinline__ void brick_origin(int ntx, int nty, int ntz, int& x0,
   z0 = (b / (ntx * nty)) * TZ;
 }
 
+// regrouping: where a cell's particles of each species start in the targets
+struct DStart {
+  int v[kMaxTiledSpecies];
+};
+template <typename T>
+__device__ __forceinline__ DStart load_dstart(const TArgs<T>& args, const BrickCell& c) {
+  DStart d;
+  const int cl = c.valid ? c.cell : 0;
+#pragma unroll
+  for (int s = 0; s < kMaxTiledSpecies; ++s) d.v[s] = gld(args.dst[s < args.ns ? s : 0].start + cl);
+  return d;
+}
+
 // cell range loads, issued one cell (pair) ahead of their use
 struct RangeLd {
   int lo[kSlots5], hi[kSlots5];
@@ -607,6 +637,7 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   __shared__ T fld[MOVE ? 6 * HN : 1];
   __shared__ int rbeg[NR];
   __shared__ int roff[NR + 1];
+  __shared__ int rleft[NR];   // regrouping: particles of each range listed as strays
   __shared__ int wsum[NW];
   __shared__ double red[NW];
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
@@ -635,6 +666,7 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
       n = cs[c.cell + 1] - b0;
     }
     rbeg[tid] = b0;
+    rleft[tid] = 0;
   }
   int incl = n;
 #pragma unroll
@@ -791,6 +823,7 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
       stray = pd.ok && (inbox ? pcell != gc.cell : true);
       if (pd.ok && !inbox) item |= kUnmoved;
       lcell = inbox ? pcell : gc.cell;
+      if (args.stay && stray) atomicAdd(&rleft[r_cur], 1);
     } else {
       stray = pd.ok && pcell0 != gc.cell;
       lcell = pcell0;
@@ -868,12 +901,23 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
     }
   }
   __syncthreads();
+  if (MOVE && args.stay && tid < NR) {
+    const int s = tid % kMaxTiledSpecies;
+    const BrickCell c = brick_cell<TX, TY, TZ>(g, x0, y0, z0, tid / kMaxTiledSpecies);
+    if (c.valid && s < args.ns) args.stay[(int64_t)s * g.nn + c.cell] = roff[tid + 1] - roff[tid] - rleft[tid];
+  }
   ws.copy_out(args, wbuf, lane, wst[wave]);
 }
 // ---------------------------------------------------------------------------
 // tiled deposit
 // ---------------------------------------------------------------------------
-template <typename T, int TX, int TY, int TZ, int NW>
+// With REGROUP the deposit also writes every particle it takes (the cell's own
+// range particles still in the cell, then its strays) to the targets, species
+// by species in cell order: the next pass's grouping, without a separate sort.
+template <typename T>
+using LdsDst = const __attribute__((address_space(3))) RegroupDst<T>;
+
+template <typename T, int TX, int TY, int TZ, int NW, bool REGROUP>
 __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz,
                                                      T* __restrict__ J, T* __restrict__ M) {
   using MF = Mfma<T>;
@@ -886,7 +930,9 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
   __shared__ __attribute__((aligned(16))) T smem[NW * WREC + NCELL * SCS];
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
   __shared__ PtrSet<T> lptr_tab[kZeroSlot + 1];
+  __shared__ RegroupDst<T> ldst_tab[REGROUP ? kMaxTiledSpecies : 1];
   LdsPtrSet<T>* const lptr = (LdsPtrSet<T>*)lptr_tab;
+  LdsDst<T>* const ldst = (LdsDst<T>*)ldst_tab;
   T* const scell = smem + NW * WREC;
 
   const int tid = threadIdx.x;
@@ -902,6 +948,9 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
   for (int i = tid; i < NCELL * SCS; i += NW * 64) scell[i] = T(0);
   for (int i = tid; i < NW * WREC; i += NW * 64) smem[i] = T(0);
   fill_tables(args, lsp, lptr_tab, tid);
+  if constexpr (REGROUP) {
+    if (tid < kMaxTiledSpecies) ldst_tab[tid] = args.dst[tid < args.ns ? tid : 0];
+  }
   __syncthreads();
 
   T* const wrec = smem + wave * WREC;
@@ -924,15 +973,19 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
   T sv = load_stage(pc);
   Ranges rg = make_ranges<T, kSlots5>(args, load_ranges<T, kSlots5>(args, lsp, pc), pc);
   PData<T> pd = load_dep<T>(lptr, rg, hl);
+  DStart dsn{};
+  if constexpr (REGROUP) dsn = load_dstart(args, pc);
 
   for (int pair = wave; pair < NPAIR; pair += NW) {
     const bool has_next = pair + NW < NPAIR;   // wave-uniform
     const BrickCell nc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, 2 * (has_next ? pair + NW : pair) + half);
     RangeLd nrl{};
     T nsv = T(0);
+    const DStart dsc = dsn;
     if (has_next) {
       nrl = load_ranges<T, kSlots5>(args, lsp, nc);
       nsv = load_stage(nc);
+      if constexpr (REGROUP) dsn = load_dstart(args, nc);
     }
     const Ranges cr = rg;
     const int lc = pc.lc;
@@ -953,6 +1006,9 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
     if (hl < 24) stage[hl] = sv;
     wave_sync();
 
+    // regrouping: the cell's particles written so far, per species
+    int run[kMaxTiledSpecies] = {0, 0, 0, 0};
+    (void)dsc;
     // running sums of the two cells: [cell][tile][reg]
     T S[2][2][4], C[2][2][4];
 #pragma unroll
@@ -968,12 +1024,12 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
       // ---- 1. particle lanes: one record column per lane ----
       // Every lane runs the same arithmetic; lanes whose particle is not in
       // the cell (or that hold none) carry zero charge, so zero values.
+      bool keep;
       {
         const TSpecies<T>& sp = lsp[dep_species(pd)];
         const Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
         // in the cell: FP32 compares the stored cell index (the weights need
         // only the offsets), FP64 the cell of the stencil
-        bool keep;
         if constexpr (sizeof(T) == 4) keep = pd.ok && pd.c == cell;
         else keep = pd.ok && ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]) == cell;
         T W[8];
@@ -984,6 +1040,34 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
         particle_record(ps, B1, Vec3<T>{pd.v0, pd.v1, pd.v2}, keep ? dep_charge(pd, lptr) : T(0), sp, r);
 #pragma unroll
         for (int i = 0; i < 39; ++i) wrec[i * kSlots + lane] = r[i];
+      }
+      if constexpr (REGROUP) {
+        // target index: the cell's start for the species, the particles of the
+        // species written so far in this cell, and the lanes before this one
+        // in its half (one cell per half) taking the same species
+        const int sl = dep_species(pd);
+        const uint32_t below = (1u << hl) - 1u;
+        int my = -1;
+#pragma unroll
+        for (int s = 0; s < kMaxTiledSpecies; ++s) {
+          if (s < args.ns) {   // wave-uniform
+            const uint64_t m = __ballot(keep && sl == s);
+            const uint32_t hm = half ? (uint32_t)(m >> 32) : (uint32_t)m;
+            if (sl == s) my = dsc.v[s] + run[s] + __popc(hm & below);
+            run[s] += __popc(hm);
+          }
+        }
+        LdsDst<T>& D = ldst[sl];
+        if (keep && my >= 0 && my < D.np) {
+          gst(D.pos[0] + my, pd.x0);
+          gst(D.pos[1] + my, pd.x1);
+          gst(D.pos[2] + my, pd.x2);
+          gst(D.vel[0] + my, pd.v0);
+          gst(D.vel[1] + my, pd.v1);
+          gst(D.vel[2] + my, pd.v2);
+          if (D.q) gst(D.q + my, dep_charge(pd, lptr));
+          if constexpr (sizeof(T) == 4) gst(D.cell + my, pd.c);
+        }
       }
       wave_sync();
       // prefetch the next block (of this pair, else of the next pair) while
@@ -1312,6 +1396,7 @@ __global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
       // leaves the list (cell -1)
       const int range_cell = args.stray_cell[i];
       args.stray_cell[i] = ncell == range_cell ? -1 : ncell;
+      if (args.stay && ncell == range_cell) atomicAdd(args.stay + (int64_t)s * g.nn + range_cell, 1);
       args.stray_item[i] = item & ~kUnmoved;
       if (args.ke) {
         const double vx = v.x, vy = v.y, vz = v.z;
@@ -1334,7 +1419,9 @@ __global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
 // stray list: rank by cell, then scatter into cell order
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_stray_rank(const int* __restrict__ count, const int* __restrict__ cellv,
-                                                    int* __restrict__ counts, int* __restrict__ ranks) {
+                                                    int* __restrict__ counts, int* __restrict__ ranks,
+                                                    const int* __restrict__ items, int* __restrict__ scount,
+                                                    int64_t nn) {
   // one returning atomic per stray, all lanes at once: strays of a wavefront
   // mostly lie in different cells, so a per-key leader loop would serialise
   // (four entries per thread and pass, their atomics in flight together)
@@ -1349,6 +1436,31 @@ __global__ void __launch_bounds__(256) k_stray_rank(const int* __restrict__ coun
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (c[u] >= 0) ranks[i0 + u * stride] = r[u];
+    if (scount) {   // regrouping: listed strays per (species, cell)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (c[u] >= 0) {
+          const int sp = (items[i0 + u * stride] >> kItemShift) & (kMaxTiledSpecies - 1);
+          atomicAdd(scount + (int64_t)sp * nn + c[u], 1);
+        }
+    }
+  }
+}
+
+// regrouping: the particles of (species, cell) after the pass, in place of the
+// stray counts
+__global__ void __launch_bounds__(256) k_regroup_total(int* __restrict__ scount, const int* __restrict__ stay,
+                                                       int64_t n) {
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) scount[i] += stay[i];
+}
+
+// regrouping: the cell ranges of each species from the scan over (species, cell)
+template <typename T>
+__global__ void __launch_bounds__(256) k_regroup_starts(TArgs<T> args, const int* __restrict__ scan, int64_t nn) {
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < (int64_t)args.ns * (nn + 1); i += (int64_t)gridDim.x * 256) {
+    const int s = (int)(i / (nn + 1));
+    const int64_t c = i % (nn + 1);
+    args.dst[s].start[c] = scan[s * nn + c] - scan[s * nn];
   }
 }
 
@@ -1414,7 +1526,16 @@ struct StrayWs {
   int* counts;
   int* start;
   int* scan_sums;
+  int* stay;       // regrouping: [species][cell] stayers, strays (then totals), their scan
+  int* scount;
+  int* rscan;
+  int* rsums;
 };
+
+// regrouping arrays: [species][cell] for up to kMaxTiledSpecies species, and
+// the sums of a scan over them
+constexpr size_t kRsums = 1056;
+
 
 StrayWs carve(const Grid& g, int64_t cap, size_t esz, void* ws) {
   char* w = (char*)ws;
@@ -1451,6 +1572,14 @@ StrayWs carve(const Grid& g, int64_t cap, size_t esz, void* ws) {
   s.start = (int*)w;
   w += align256(sizeof(int) * (size_t)(g.nn + 1));
   s.scan_sums = (int*)w;
+  w += align256(sizeof(int) * (size_t)((g.nn + 1023) / 1024 + 1));
+  s.stay = (int*)w;
+  w += align256(sizeof(int) * kMaxTiledSpecies * (size_t)g.nn);
+  s.scount = (int*)w;
+  w += align256(sizeof(int) * kMaxTiledSpecies * (size_t)g.nn);
+  s.rscan = (int*)w;
+  w += align256(sizeof(int) * (kMaxTiledSpecies * (size_t)g.nn + 1));
+  s.rsums = (int*)w;
   return s;
 }
 
@@ -1481,7 +1610,8 @@ TArgs<T> make_args(const Grid& g, const SpeciesArgs* sp, int ns) {
 // grouped pass (move or check) -> [stray mover] -> stray counting sort -> deposit
 template <typename T, int TX, int TY, int TZ, int NW>
 hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove, const void* Bmove,
-                 const void* Bdep, void* J, void* M, double* ke, bool move, void* ws, hipStream_t st) {
+                 const void* Bdep, void* J, void* M, double* ke, bool move, void* ws, hipStream_t st,
+                 const SpeciesArgs* dst = nullptr) {
   const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
   const int ntiles = ntx * nty * ntz;
   int64_t cap = 0;
@@ -1514,6 +1644,21 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
   a.ul.q = (T*)w.udata[6];
   a.ul.cell = w.ucell;
   a.ul.sp = nullptr;
+  const bool regroup = dst != nullptr;
+  if (regroup) {
+    a.stay = w.stay;
+    a.scount = w.scount;
+    for (int s = 0; s < ns; ++s) {
+      for (int d = 0; d < 3; ++d) {
+        a.dst[s].pos[d] = (T*)dst[s].pos[d];
+        a.dst[s].vel[d] = (T*)dst[s].vel[d];
+      }
+      a.dst[s].q = (T*)dst[s].q;
+      a.dst[s].cell = dst[s].cell;
+      a.dst[s].start = const_cast<int32_t*>(dst[s].cell_start);
+      a.dst[s].np = dst[s].np;
+    }
+  }
   constexpr int kGroupWaves = 4;   // 4-wave workgroups: three fit a CU at the mover's register count
   if (move) {
     hipLaunchKernelGGL((k_group<T, TX, TY, TZ, kGroupWaves, true>), dim3(ntiles), dim3(kGroupWaves * 64), 0, st, g,
@@ -1527,14 +1672,27 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // strays: counting sort by cell
   if ((e = launch_zero(w.counts, sizeof(int) * (size_t)g.nn, st)) != hipSuccess) return e;
+  const int64_t nsn = (int64_t)ns * g.nn;
+  if (regroup && (e = launch_zero(w.scount, sizeof(int) * (size_t)nsn, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_stray_rank, dim3(1024), dim3(256), 0, st, (const int*)w.count, (const int*)w.cell, w.counts,
-                     w.rank);
+                     w.rank, (const int*)w.item, regroup ? w.scount : nullptr, g.nn);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_exclusive_scan(w.counts, g.nn, w.start, w.scan_sums, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_stray_scatter<T>, dim3(1024), dim3(256), 0, st, a, (const int*)w.rank);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_deposit<T, TX, TY, TZ, NW>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty, ntz,
-                     (T*)J, (T*)M);
+  if (regroup) {
+    // the species' cell ranges after the pass: stayers plus arriving strays
+    hipLaunchKernelGGL(k_regroup_total, dim3(1024), dim3(256), 0, st, w.scount, (const int*)w.stay, nsn);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_exclusive_scan(w.scount, nsn, w.rscan, w.rsums, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_regroup_starts<T>, dim3(1024), dim3(256), 0, st, a, (const int*)w.rscan, g.nn);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_deposit<T, TX, TY, TZ, NW, true>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty,
+                       ntz, (T*)J, (T*)M);
+  } else {
+    hipLaunchKernelGGL((k_deposit<T, TX, TY, TZ, NW, false>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty,
+                       ntz, (T*)J, (T*)M);
+  }
   return hipGetLastError();
 }
 
@@ -1565,12 +1723,15 @@ hipError_t launch_diagnostics_tiled(const Grid& g, bool f32, const SpeciesArgs* 
   return run_diag<double, 4, 4, 2, 4>(g, sp, ns, rho, Jd, P, zero, st);
 }
 
+int64_t regroup_max_entries() { return (int64_t)1024 * 1024; }   // the scan's limit: 1024 tiles of 1024
+
 size_t tiled_workspace_bytes(const Grid& g, int64_t np_total, bool f32) {
   const int64_t nscan = (g.nn + 1023) / 1024 + 1;
   const size_t esz = f32 ? 4 : 8;
   return 768 + 6 * align256(sizeof(int) * (size_t)np_total) + 14 * align256(esz * (size_t)np_total) +
          align256(sizeof(int) * (size_t)g.nn) + align256(sizeof(int) * (size_t)(g.nn + 1)) +
-         align256(sizeof(int) * (size_t)nscan);
+         align256(sizeof(int) * (size_t)nscan) + 2 * align256(sizeof(int) * kMaxTiledSpecies * (size_t)g.nn) +
+         align256(sizeof(int) * (kMaxTiledSpecies * (size_t)g.nn + 1)) + sizeof(int) * kRsums;
 }
 
 bool tiled_species_ok(const SpeciesArgs* sp, int ns) {
@@ -1589,6 +1750,18 @@ hipError_t launch_deposit_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, 
   }
   if (f32) return run_T<float, 4, 4, 2, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
   return run_T<double, 4, 4, 2, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
+}
+
+hipError_t launch_move_deposit_regroup(const Grid& g, bool f32, const SpeciesArgs* sp, const SpeciesArgs* dst, int ns,
+                                       const void* E, const void* B, const void* Bnext, void* J, void* M, double* ke,
+                                       void* ws, hipStream_t st) {
+  if ((int64_t)ns * g.nn > regroup_max_entries()) return hipErrorInvalidValue;
+  if (g.nz == 1) {
+    if (f32) return run_T<float, 8, 4, 1, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st, dst);
+    return run_T<double, 8, 4, 1, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st, dst);
+  }
+  if (f32) return run_T<float, 4, 4, 2, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st, dst);
+  return run_T<double, 4, 4, 2, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st, dst);
 }
 
 hipError_t launch_move_deposit(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* E, const void* B,

@@ -44,6 +44,13 @@ hipError_t launch_deposit_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, 
 hipError_t launch_move_deposit(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* E,
                                const void* B, const void* Bnext, void* J, void* M, double* ke, void* ws,
                                hipStream_t st);
+// Fused mover + deposit that also regroups: each species' particles are
+// written to dst[s] in cell order (the deposit's order) and dst[s].cell_start
+// receives the ranges. Needs nspecies * cells <= regroup_max_entries().
+hipError_t launch_move_deposit_regroup(const Grid& g, bool f32, const SpeciesArgs* sp, const SpeciesArgs* dst, int ns,
+                                       const void* E, const void* B, const void* Bnext, void* J, void* M, double* ke,
+                                       void* ws, hipStream_t st);
+int64_t regroup_max_entries();
 // exclusive scan of n ints into out[0..n], out[n] = total; sums: >= n/1024 + 2 ints
 hipError_t launch_exclusive_scan(const int* in, int64_t n, int* out, int* sums, hipStream_t st);
 

@@ -61,6 +61,8 @@ def lib():
             "ecsim_moments": [P, P, ctypes.c_int32, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32, P],
             "ecsim_move_moments": [P, P, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32,
                                    P],
+            "ecsim_move_moments_regroup": [P, P, P, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_size_t,
+                                           ctypes.c_uint32, P],
             "ecsim_diagnostics": [P, P, ctypes.c_int32, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32, P],
             "ecsim_diagnostics_workspace_size": [P, ctypes.c_int32, ctypes.c_uint32, P],
             "ecsim_mass_apply": [P, ctypes.c_int32, P, P, ctypes.c_double, ctypes.c_double, P, P],
@@ -82,7 +84,8 @@ def lib():
 
 
 EXPORTED = ["ecsim_last_error", "ecsim_version", "ecsim_workspace_size", "ecsim_move", "ecsim_moments",
-            "ecsim_move_moments", "ecsim_diagnostics", "ecsim_diagnostics_workspace_size",
+            "ecsim_move_moments", "ecsim_move_moments_regroup", "ecsim_diagnostics",
+            "ecsim_diagnostics_workspace_size",
             "ecsim_mass_apply", "ecsim_moments_backward", "ecsim_sort", "ecsim_centres_to_nodes", "ecsim_to_f32",
             "ecsim_solve_workspace_size", "ecsim_field_solve", "ecsim_field_energy"]
 
@@ -269,6 +272,25 @@ def move_moments(grid: Grid, species: Sequence[Species], E: torch.Tensor, B: tor
                                     _ptr(J), _ptr(M), _ptr(ke), _ptr(ws), ws.numel(), int(flags), _stream(stream)))
 
 
+def move_moments_regroup(grid: Grid, species: Sequence[Species], dst: Sequence[Species], E: torch.Tensor,
+                         B: torch.Tensor, B_next: torch.Tensor, J: torch.Tensor, M: torch.Tensor,
+                         ke: Optional[torch.Tensor] = None, flags: int = 0, ws: Optional[torch.Tensor] = None,
+                         stream=None):
+    """The fused pass of move_moments that also writes each species' moved particles, grouped by cell,
+    into dst (same sizes; a cell_start is allocated where dst has none) for the next pass."""
+    for d in dst:
+        if d.cell_start is None:
+            d.cell_start = torch.empty(grid.nn + 1, dtype=torch.int32, device=J.device)
+    arr = (_Particles * len(species))(*[s.c() for s in species])
+    darr = (_Particles * len(dst))(*[d.c() for d in dst])
+    if ws is None:
+        ws = torch.empty(workspace_size(grid, _total(species), species[0].prec), dtype=torch.uint8,
+                         device=J.device)
+    _check(lib().ecsim_move_moments_regroup(ctypes.byref(grid.c()), arr, darr, len(species), _ptr(E), _ptr(B),
+                                            _ptr(B_next), _ptr(J), _ptr(M), _ptr(ke), _ptr(ws), ws.numel(),
+                                            int(flags), _stream(stream)))
+
+
 def mass_apply(grid: Grid, M: torch.Tensor, x: torch.Tensor, y: torch.Tensor, a: float = 1.0, b: float = 0.0,
                stream=None):
     """y = a (M x) + b y with M in FP32 or FP64 and x, y FP64 (3, Nn)."""
@@ -351,11 +373,14 @@ class Simulation:
     particles are re-sorted by cell before each deposit and the tiled deposit
     is used; between re-sorts (every ``sort_every`` steps) the cell ranges
     are a stale grouping that the deposit corrects for. With ``fused=True``
-    the mover and the next step's moments run as one pass.
+    the mover and the next step's moments run as one pass; with
+    ``regroup=True`` as well, that pass also writes the particles grouped by
+    cell into a second set of arrays (ecsim_move_moments_regroup), so the
+    grouping is exact every step and no separate re-sort runs.
     """
 
     def __init__(self, plasma, prec: int = F64, device="cuda", tol: float = 1e-10, restart: int = 30,
-                 sort: bool = True, fused: bool = False, sort_every: int = 4):
+                 sort: bool = True, fused: bool = False, sort_every: int = 4, regroup: bool = False):
         from . import inputs as I
         self.grid = Grid(plasma.n, plasma.h, plasma.dt)
         self.prec = prec
@@ -363,6 +388,7 @@ class Simulation:
         self.restart = restart
         self.do_sort = sort or fused
         self.fused = fused
+        self.regroup = bool(regroup and fused)
         self.sort_every = max(1, int(sort_every))
         self.nstep = 0
         self.primed = False
@@ -452,6 +478,11 @@ class Simulation:
     def fused_particles(self, ke: Optional[torch.Tensor] = None):
         """The fused particle pass proper (fused_fields() first)."""
         Et = self.Et_p if self.prec == F32 else self.E_theta
+        if self.regroup:
+            move_moments_regroup(self.grid, self.species, self._spare, Et, self.BN_p, self.BN_next_p, self.J, self.M,
+                                 ke, ws=self.ws)
+            self.species, self._spare = list(self._spare), list(self.species)
+            return
         move_moments(self.grid, self.species, Et, self.BN_p, self.BN_next_p, self.J, self.M, ke, ws=self.ws)
 
     def fused_pass(self, ke: Optional[torch.Tensor] = None):
@@ -467,7 +498,7 @@ class Simulation:
         else:
             self.BN_p, self.BN_next_p = self.BN, self.BN_next
         self.nstep += 1
-        if self.nstep % self.sort_every == 0:
+        if not self.regroup and self.nstep % self.sort_every == 0:
             self.sort_particles()
 
     def step(self):

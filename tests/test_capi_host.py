@@ -201,3 +201,39 @@ def test_diagnostics_workspace_size(E):
     fake = ctypes.c_void_p(0x1000)
     arr = (E._Particles * 1)(_particles(E, prec=E.F32, cell=True))
     assert L.ecsim_diagnostics(ctypes.byref(g), arr, 1, fake, fake, fake, None, 0, 0, None) == E.EWORKSPACE
+
+
+def test_move_moments_regroup_validation(E):
+    """ecsim_move_moments_regroup rejects mismatched, incomplete or aliasing targets before any launch."""
+    L = E.lib()
+    g = _grid(E)
+    fake = ctypes.c_void_p(0x1000)
+    gp = lambda p, cs: (setattr(p, "cell_start", cs), p)[1]
+    src = (E._Particles * 1)(gp(_particles(E, prec=E.F32, cell=True, ptr=0x1000), 0x5000))
+
+    def call(dst, ns=1, s=src, ws=fake, wsb=1 << 40):
+        return L.ecsim_move_moments_regroup(ctypes.byref(g), s, dst, ns, fake, fake, fake, fake, fake, None, ws, wsb,
+                                            0, None)
+
+    good = lambda **kw: gp(_particles(E, prec=E.F32, cell=True, ptr=0x9000, **kw), 0x6000)
+    assert call(None) == E.EINVAL
+    assert call((E._Particles * 1)(gp(_particles(E, prec=E.F32, cell=True, ptr=0x9000), None))) == E.EINVAL
+    assert b"cell_start" in L.ecsim_last_error()
+    assert call((E._Particles * 1)(good(np_=9))) == E.EINVAL                  # size differs
+    assert call((E._Particles * 1)(gp(_particles(E, prec=E.F64, ptr=0x9000), 0x6000))) == E.EINVAL   # precision
+    d = good()
+    d.q = ctypes.c_void_p(0x9100)                                             # charge array where the source has none
+    assert call((E._Particles * 1)(d)) == E.EINVAL
+    d = good()
+    d.vel[2] = ctypes.c_void_p(0x1000)                                        # aliases a source array
+    assert call((E._Particles * 1)(d)) == E.EINVAL
+    assert b"alias" in L.ecsim_last_error()
+    d = good()
+    d.cell_start = ctypes.c_void_p(0x5000)                                    # aliases the source ranges
+    assert call((E._Particles * 1)(d)) == E.EINVAL
+    assert call((E._Particles * 1)(good()), ws=None, wsb=0) == E.EWORKSPACE
+    # species x cells above the scan's limit
+    big = E.Grid((128, 128, 65), (0.5,) * 3, 0.1).c()   # 1,064,960 cells: every call here fails before a launch
+    assert L.ecsim_move_moments_regroup(ctypes.byref(big), src, (E._Particles * 1)(good()), 1, fake, fake, fake,
+                                        fake, fake, None, fake, 1 << 40, 0, None) == E.EINVAL
+    assert b"exceeds" in L.ecsim_last_error()

@@ -258,6 +258,118 @@ def test_move_moments_fused(E, O, I, prec, n, ppc, vscale):
     assert abs(host(ke)[0] - K) <= (1e-12 if prec == "f64" else 1e-6) * K
 
 
+def species_state(sd, prec):
+    """Rows (cell or position, velocity, charge) of a species' particles, in a fixed order."""
+    cols = [host(sd.cell).astype(np.float64)] if prec == "f32" else []
+    cols += list(host(sd.pos).astype(np.float64)) + list(host(sd.vel).astype(np.float64))
+    if sd.q is not None:
+        cols.append(host(sd.q).astype(np.float64))
+    rows = np.stack(cols)
+    return rows[:, np.lexsort(rows[::-1])]
+
+
+def check_grouping(I, p, sd, prec):
+    """dst ranges: 0 .. np, non-decreasing, and every particle inside its range's cell."""
+    cs = host(sd.cell_start).astype(np.int64)
+    assert cs[0] == 0 and cs[-1] == sd.np and np.all(np.diff(cs) >= 0)
+    if prec == "f32":
+        cells = host(sd.cell).astype(np.int64)
+    else:
+        x = host(sd.pos)
+        ijk = [np.floor(x[d] / p.h[d]).astype(np.int64) for d in range(3)]
+        cells = ijk[0] + p.n[0] * (ijk[1] + p.n[1] * ijk[2])
+    assert np.array_equal(cells, np.repeat(np.arange(p.nn), np.diff(cs)))
+
+
+def regroup_case(E, I, p, prec):
+    if prec == "f64":
+        sp = [E.Species.from_f64(s.qom, s.x, s.v, s.q) for s in p.species]
+        xs, vs, qs = [s.x for s in p.species], [s.v for s in p.species], [s.q for s in p.species]
+        return sp, xs, vs, qs, torch.float64, TOL64
+    st = I.to_f32_state(p)
+    sp = [E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"]) for s, f in zip(p.species, st)]
+    xs, vs, qs = [f["x64"] for f in st], [f["v64"] for f in st], [f["q64"] for f in st]
+    return sp, xs, vs, qs, torch.float32, TOL32
+
+
+def run_regroup_passes(E, O, I, p, prec, En, BN, Bnext, passes=2):
+    """Regrouping fused passes against the oracle: J, M and the kinetic energy
+    each pass, the targets' grouping, the targets holding exactly the moved
+    particles, and the final states (matched through their x velocities)."""
+    grid = E.Grid(p.n, p.h, p.dt)
+    sp, xs, vs, qs, tdt, tol = regroup_case(E, I, p, prec)
+    if prec == "f64":
+        Ec, Bc, Bnc = En, BN, Bnext
+    else:
+        Ec, Bc, Bnc = round32(En), round32(BN), round32(Bnext)
+    sp = sorted_species(E, grid, sp)
+    dst = [s.empty_like() for s in sp]
+    J = torch.full((3, p.nn), 7.0, dtype=tdt, device="cuda")
+    M = torch.full((14, 9, p.nn), 7.0, dtype=tdt, device="cuda")
+    for it in range(passes):
+        ke = torch.zeros(1, dtype=torch.float64, device="cuda")
+        E.move_moments_regroup(grid, sp, dst, dev(Ec, tdt), dev(Bc, tdt), dev(Bnc, tdt), J, M, ke)
+        x1s, v1s = [], []
+        for s, x, v in zip(p.species, xs, vs):
+            x1, v1 = O.move(p.n, p.h, p.dt, x, v, s.qom, Ec, Bc)
+            x1s.append(x1)
+            v1s.append(v1)
+        xs, vs = x1s, v1s
+        Jo, Mo = oracle_moments(O, p, xs, vs, qs, Bnc)
+        assert rel(host(J), Jo) < tol
+        assert rel(host(M), Mo) < tol
+        K = sum(O.kinetic(v, q, s.qom) for s, v, q in zip(p.species, vs, qs))
+        assert abs(host(ke)[0] - K) <= (1e-12 if prec == "f64" else 1e-6) * max(K, 1e-300)
+        for s, d in zip(sp, dst):
+            check_grouping(I, p, d, prec)
+            assert np.array_equal(species_state(s, prec), species_state(d, prec))
+        sp, dst = dst, sp
+    # match each particle to the oracle's through its whole velocity (nearest
+    # neighbour; one component alone can tie within FP32 rounding)
+    from scipy.spatial import cKDTree
+    for d, x, v in zip(sp, xs, vs):
+        if d.np == 0:
+            continue
+        vg = host(d.vel).astype(np.float64)
+        idx = cKDTree(v.T).query(vg.T)[1]
+        assert np.unique(idx).size == d.np
+        assert rel(vg, v[:, idx]) < tol
+        xd = host(d.pos) if prec == "f64" else I.decode_f32(host(d.cell), host(d.pos), p.n, p.h)
+        assert periodic_rel(xd, x[:, idx], p.L) < tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,ppc,vscale", [((8, 8, 8), 27, 1.0), ((6, 5, 4), 9, 40.0), ((2, 3, 2), 7, 20.0),
+                                           ((13, 7, 5), 3, 5.0), ((9, 5, 1), 12, 10.0), ((16, 1, 1), 20, 10.0)])
+def test_move_moments_regroup(E, O, I, prec, n, ppc, vscale):
+    """ecsim_move_moments_regroup: two passes, each regrouping into the other
+    set of arrays. Scaled velocities send many particles out of their cell,
+    some beyond the workgroup's box (moved by the stray mover), some back."""
+    say("move+moments regroup", prec, n, ppc, vscale)
+    p, En, BN = make_case(I, n, ppc, 23)
+    for s in p.species:
+        s.v = s.v * vscale
+    rng = np.random.default_rng(24)
+    run_regroup_passes(E, O, I, p, prec, En, BN, BN + 0.01 * rng.standard_normal(BN.shape))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_move_moments_regroup_four_species_and_empty(E, O, I, prec):
+    """Four species (per-particle charges on two of them), then a case with an empty species."""
+    import dataclasses
+    say("regroup four species", prec)
+    p, En, BN = make_case(I, (7, 6, 5), 8, 25)
+    rng = np.random.default_rng(26)
+    e, i = p.species
+    extra = [dataclasses.replace(e, name="e2", qom=-0.5, q=e.q * (1.0 + 0.5 * rng.random(e.np)),
+                                 v=e.v[:, ::-1].copy() * 8.0),
+             dataclasses.replace(i, name="i2", qom=0.1, q=i.q * (1.0 + 0.5 * rng.random(i.np)), v=i.v * 3.0)]
+    p.species = [e, i] + extra
+    run_regroup_passes(E, O, I, p, prec, En, BN, BN + 0.01 * rng.standard_normal(BN.shape))
+    p.species = [e, dataclasses.replace(i, q=i.q[:0], x=i.x[:, :0], v=i.v[:, :0])]
+    run_regroup_passes(E, O, I, p, prec, En, BN, BN, passes=1)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_moments_stale_grouping(E, O, I, prec):
     """ecsim_moments with a cell_start left stale by a move (the stray path of the plain deposit)."""
@@ -533,7 +645,7 @@ def test_two_dimensional_run(E, O, I, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("sort", [False, True, "fused"])
+@pytest.mark.parametrize("sort", [False, True, "fused", "regroup"])
 def test_small_workload_ten_steps(E, O, I, prec, sort):
     """8^3 cells, 27 ppc x 2 species, 10 steps: state parity and energy drift."""
     say("config-0 ten steps", prec, sort)
@@ -541,6 +653,8 @@ def test_small_workload_ten_steps(E, O, I, prec, sort):
     P = E.F64 if prec == "f64" else E.F32
     if sort == "fused":
         sim = E.Simulation(p, prec=P, tol=1e-10, fused=True, sort_every=3)
+    elif sort == "regroup":
+        sim = E.Simulation(p, prec=P, tol=1e-10, fused=True, regroup=True)
     else:
         sim = E.Simulation(p, prec=P, tol=1e-10, sort=sort)
     if prec == "f32":
