@@ -9,9 +9,12 @@ electron density perturbed by 1% cos(2 pi x / L_x), B0 = (0, 0, 0.2), E = 0.
 One step is the scheme's step: FP64 GMRES field solve (tol 1e-10) for
 E^{n+theta}, then one fused particle pass -- mover with (E^{n+theta}, B^n) and
 the moment gather (J-hat, M) at the new positions with B^{n+1}, i.e. the next
-step's moments -- with a cell re-sort every --sort-every steps. The metric is
-particles per second through mover + moments (the fused pass plus the
-amortised re-sort), in the FP32 storage form (headline) and the FP64 form;
+step's moments -- which also writes the particles regrouped by cell for the
+next step (ecsim_move_moments_regroup; with --no-regroup, the fused pass on a
+stale grouping plus a counting re-sort every --sort-every steps instead). The
+metric is particles per second through mover + moments (the fused pass, plus
+the amortised re-sort where one runs), in the FP32 storage form (headline)
+and the FP64 form;
 the field solve runs in every step and is reported separately. Times are HIP
 events on the stream the kernels run on, inside a region bracketed by device
 synchronisation.
@@ -34,8 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE passes summarised in the profile named below
 # (scaled by a 1 GiB device copy). Valid only for the kernel sources whose
 # hash is recorded; any change to them makes the figure stale (reported null).
-TRAFFIC = {"sources_sha256": "eedf055d6ca835650ffb04f1eb270e69a22e45d36b106004c3272a296ff13de8",
-           "bytes_per_call": 3872993908,
+TRAFFIC = {"sources_sha256": "e8014e74fd940b27edaa4b80de0895bbcba6569ee2916a2d66657da144f4143a",
+           "bytes_per_call": 4947117204,
+           "regroup": True,
            "profile": "profiles/move_moments_64cubed_fp32.md"}
 
 
@@ -64,6 +68,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8, help="oracle runs on 1/cpu-sample of the particles")
     ap.add_argument("--sort-every", type=int, default=4)
+    ap.add_argument("--regroup", dest="regroup", action="store_true", default=True,
+                    help="fused path: the pass regroups the particles by cell (no separate re-sort; default)")
+    ap.add_argument("--no-regroup", dest="regroup", action="store_false",
+                    help="fused path: re-sort with a counting sort every --sort-every steps instead")
     ap.add_argument("--no-error", action="store_true", help="skip the FP32-vs-FP64 error measurement")
     ap.add_argument("--calib-copy", action="store_true", help="end with a 1 GiB device copy (byte-counter reference)")
     ap.add_argument("--no-extras", action="store_true", help="skip the apply and adjoint timings")
@@ -96,7 +104,8 @@ def run_form(prec, args, plasma):
     from paper_2603_16624_amd import ecsim as E
     P = E.F32 if prec == "f32" else E.F64
     fused = args.path == "fused"
-    sim = E.Simulation(plasma, prec=P, tol=1e-10, fused=fused, sort=True, sort_every=args.sort_every)
+    sim = E.Simulation(plasma, prec=P, tol=1e-10, fused=fused, sort=True, sort_every=args.sort_every,
+                       regroup=fused and args.regroup)
     st = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)
     if fused:
@@ -132,7 +141,7 @@ def run_form(prec, args, plasma):
             else:
                 sim.BN_p, sim.BN_next_p = sim.BN, sim.BN_next
         sim.nstep += 1
-        sorted_now = sim.nstep % sim.sort_every == 0
+        sorted_now = not sim.regroup and sim.nstep % sim.sort_every == 0
         if sorted_now:
             sim.sort_particles()
         e[5].record(st)
@@ -446,14 +455,17 @@ def main():
         print("[bench] copy calibration done", file=sys.stderr, flush=True)
     nbytes = r32["bytes_per_step"]
     if args.path == "fused":
-        kname = "ecsim_move_moments (FP32): fused mover + moment gather, incl. its stray passes"
+        kname = ("ecsim_move_moments_regroup (FP32): fused mover + moment gather + regrouping, incl. its stray "
+                 "passes" if args.regroup else
+                 "ecsim_move_moments (FP32): fused mover + moment gather, incl. its stray passes")
         kms = r32["kernel_ms"]
     else:
         kname = "ecsim_move + ecsim_moments (FP32, tiled, stale grouping)"
         kms = r32["kernel_ms"] + r32["moments_ms"]
     achieved = nbytes / (kms * 1e-3) / 1e9
     traffic = None
-    if args.path == "fused" and TRAFFIC["bytes_per_call"] and TRAFFIC["sources_sha256"] == kernel_sources_sha256():
+    if (args.path == "fused" and args.regroup == TRAFFIC["regroup"] and TRAFFIC["bytes_per_call"]
+            and TRAFFIC["sources_sha256"] == kernel_sources_sha256()):
         traffic = TRAFFIC["bytes_per_call"]
     keys = ("fields_ms", "kernel_ms", "moments_ms", "sort_ms", "solve_ms", "full_step_ms")
     out = {
@@ -471,7 +483,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{plasma.name}; FP32 offset+cell storage, FP32 mover and deposit "
                                f"(Kahan-combined MFMA block sums), FP64 GMRES (tol 1e-10), "
-                               f"{args.path} path, re-sort every {args.sort_every} steps",
+                               + (f"{args.path} path, regrouped by cell in the pass every step"
+                                  if args.path == "fused" and args.regroup
+                                  else f"{args.path} path, re-sort every {args.sort_every} steps"),
                    "cells": list(plasma.n), "particles": plasma.n_particles, "ppc_per_species": args.ppc,
                    "parallelism": "single GPU"},
         "hbm_frac": r32["hbm_frac_pass"],

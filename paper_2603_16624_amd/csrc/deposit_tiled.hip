@@ -914,9 +914,6 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
 // With REGROUP the deposit also writes every particle it takes (the cell's own
 // range particles still in the cell, then its strays) to the targets, species
 // by species in cell order: the next pass's grouping, without a separate sort.
-template <typename T>
-using LdsDst = const __attribute__((address_space(3))) RegroupDst<T>;
-
 template <typename T, int TX, int TY, int TZ, int NW, bool REGROUP>
 __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz,
                                                      T* __restrict__ J, T* __restrict__ M) {
@@ -930,9 +927,7 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
   __shared__ __attribute__((aligned(16))) T smem[NW * WREC + NCELL * SCS];
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
   __shared__ PtrSet<T> lptr_tab[kZeroSlot + 1];
-  __shared__ RegroupDst<T> ldst_tab[REGROUP ? kMaxTiledSpecies : 1];
   LdsPtrSet<T>* const lptr = (LdsPtrSet<T>*)lptr_tab;
-  LdsDst<T>* const ldst = (LdsDst<T>*)ldst_tab;
   T* const scell = smem + NW * WREC;
 
   const int tid = threadIdx.x;
@@ -948,9 +943,6 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
   for (int i = tid; i < NCELL * SCS; i += NW * 64) scell[i] = T(0);
   for (int i = tid; i < NW * WREC; i += NW * 64) smem[i] = T(0);
   fill_tables(args, lsp, lptr_tab, tid);
-  if constexpr (REGROUP) {
-    if (tid < kMaxTiledSpecies) ldst_tab[tid] = args.dst[tid < args.ns ? tid : 0];
-  }
   __syncthreads();
 
   T* const wrec = smem + wave * WREC;
@@ -1042,31 +1034,34 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
         for (int i = 0; i < 39; ++i) wrec[i * kSlots + lane] = r[i];
       }
       if constexpr (REGROUP) {
-        // target index: the cell's start for the species, the particles of the
-        // species written so far in this cell, and the lanes before this one
-        // in its half (one cell per half) taking the same species
+        // species by species (a block mostly holds one): the target index is
+        // the cell's start for the species, the particles of the species
+        // written so far in this cell, and the lanes before this one in its
+        // half (one cell per half) taking the same species
         const int sl = dep_species(pd);
         const uint32_t below = (1u << hl) - 1u;
-        int my = -1;
 #pragma unroll
         for (int s = 0; s < kMaxTiledSpecies; ++s) {
           if (s < args.ns) {   // wave-uniform
-            const uint64_t m = __ballot(keep && sl == s);
+            const bool mine = keep && sl == s;
+            const uint64_t m = __ballot(mine);
             const uint32_t hm = half ? (uint32_t)(m >> 32) : (uint32_t)m;
-            if (sl == s) my = dsc.v[s] + run[s] + __popc(hm & below);
+            const int my = dsc.v[s] + run[s] + __popc(hm & below);
             run[s] += __popc(hm);
+            if (m) {   // wave-uniform
+              const RegroupDst<T>& D = args.dst[s];
+              if (mine && my >= 0 && my < D.np) {
+                gst(D.pos[0] + my, pd.x0);
+                gst(D.pos[1] + my, pd.x1);
+                gst(D.pos[2] + my, pd.x2);
+                gst(D.vel[0] + my, pd.v0);
+                gst(D.vel[1] + my, pd.v1);
+                gst(D.vel[2] + my, pd.v2);
+                if (D.q) gst(D.q + my, pd.q);   // a per-particle charge: its raw load is the charge
+                if constexpr (sizeof(T) == 4) gst(D.cell + my, pd.c);
+              }
+            }
           }
-        }
-        LdsDst<T>& D = ldst[sl];
-        if (keep && my >= 0 && my < D.np) {
-          gst(D.pos[0] + my, pd.x0);
-          gst(D.pos[1] + my, pd.x1);
-          gst(D.pos[2] + my, pd.x2);
-          gst(D.vel[0] + my, pd.v0);
-          gst(D.vel[1] + my, pd.v1);
-          gst(D.vel[2] + my, pd.v2);
-          if (D.q) gst(D.q + my, dep_charge(pd, lptr));
-          if constexpr (sizeof(T) == 4) gst(D.cell + my, pd.c);
         }
       }
       wave_sync();
