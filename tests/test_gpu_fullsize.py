@@ -149,7 +149,7 @@ def test_fused_pass_full_size_sampled(E, O, plasma, prec):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_energy_conservation_full_size(E, O, plasma, prec):
-    """Ten steps (fused pass, re-sort every 4) at 64^3 x 64 ppc x 2 species: the
+    """Ten steps (the regrouping fused pass) at 64^3 x 64 ppc x 2 species: the
     total energy K + W_E + W_B stays within the GMRES tolerance of its start
     (Sec. II, exact energy conservation of the semi-implicit scheme). In the
     FP32 form each particle's stored velocity is rounded once per step; over
@@ -159,7 +159,7 @@ def test_energy_conservation_full_size(E, O, plasma, prec):
     p = copy.deepcopy(plasma)
     say("full-size energy", prec, p.name)
     P = E.F64 if prec == "f64" else E.F32
-    sim = E.Simulation(p, prec=P, tol=1e-10, fused=True, sort_every=4)
+    sim = E.Simulation(p, prec=P, tol=1e-10, fused=True, regroup=True)
     if prec == "f32":
         for s, f in zip(p.species, I.to_f32_state(p)):
             s.x, s.v, s.q = f["x64"], f["v64"], f["q64"]
@@ -176,3 +176,68 @@ def test_energy_conservation_full_size(E, O, plasma, prec):
     assert drift <= 1e-10
     del sim
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_regroup_pass_full_size_sampled(E, O, plasma, prec):
+    """One regrouping pass (ecsim_move_moments_regroup, as benchmarked) at the
+    benchmark size: every particle of the targets lies inside its new cell
+    range (all 33.5M checked), the targets hold each species' count, and J and
+    the 14 blocks at sampled nodes match the oracle's moments of the
+    regrouped particles within one cell of them (the GPU's moved state; the
+    move itself is checked per particle by the fused-pass test above)."""
+    from paper_2603_16624_amd import inputs as I
+    p = plasma
+    say("full-size regroup pass", prec, p.name)
+    En, BN, Bnext = node_fields(p)
+    grid = E.Grid(p.n, p.h, p.dt)
+    if prec == "f64":
+        sp = [E.Species.from_f64(s.qom, s.x, s.v, s.q) for s in p.species]
+        Ec, Bc, Bnc, tdt = En, BN, Bnext, torch.float64
+    else:
+        st = I.to_f32_state(p)
+        sp = [E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"]) for s, f in zip(p.species, st)]
+        Ec, Bc, Bnc, tdt = round32(En), round32(BN), round32(Bnext), torch.float32
+        del st
+    grouped = []
+    for s in sp:
+        d = s.empty_like()
+        E.sort(grid, s, d, torch.empty(grid.nn + 1, dtype=torch.int32, device="cuda"))
+        grouped.append(d)
+    del sp
+    dst = [s.empty_like() for s in grouped]
+    J = torch.empty((3, p.nn), dtype=tdt, device="cuda")
+    M = torch.empty((14, 9, p.nn), dtype=tdt, device="cuda")
+    E.move_moments_regroup(grid, grouped, dst, dev(Ec, tdt), dev(Bc, tdt), dev(Bnc, tdt), J, M)
+    del grouped
+    rng = np.random.default_rng(91 + (prec == "f32"))
+    nodes = rng.choice(p.nn, size=NNODES, replace=False)
+    near = np.zeros(p.nn, dtype=bool)
+    nx, ny, nz = p.n
+    for gnode in nodes:
+        gx, gy, gz = gnode % nx, (gnode // nx) % ny, gnode // (nx * ny)
+        for dz in range(-2, 2):
+            for dy in range(-2, 2):
+                for dx in range(-2, 2):
+                    near[(gx + dx) % nx + nx * (((gy + dy) % ny) + ny * ((gz + dz) % nz))] = True
+    Jo = np.zeros((3, p.nn))
+    M27 = np.zeros((27, 9, p.nn))
+    for s, d in zip(p.species, dst):
+        cs = host(d.cell_start).astype(np.int64)
+        assert cs[0] == 0 and cs[-1] == s.np and np.all(np.diff(cs) >= 0)
+        if prec == "f64":
+            x = host(d.pos)
+            cells = cells_of(x, p.n, p.h)
+        else:
+            cells = host(d.cell).astype(np.int64)
+            x = I.decode_f32(cells, host(d.pos), p.n, p.h)
+        assert np.array_equal(cells, np.repeat(np.arange(p.nn), np.diff(cs)))
+        idx = np.nonzero(near[cells])[0]
+        v = host(d.vel).astype(np.float64)[:, idx]
+        q = host(d.q).astype(np.float64)[idx] if d.q is not None else float(d.q_const)
+        O.moments(p.n, p.h, p.dt, x[:, idx], v, q, s.qom, Bnc, Jo, M27)
+        del x, cells
+    Mo = O.m14(p.n, M27)
+    tol = TOL[prec]
+    assert rel(host(J)[:, nodes], Jo[:, nodes]) < tol
+    assert rel(host(M)[:, :, nodes], Mo[:, :, nodes]) < tol

@@ -1,7 +1,8 @@
 """The double Harris current sheet at full size in the FP32 form: 256 x 128 x 8
 periodic cells, 128 particles per cell per species (67,108,864 particles),
 each particle carrying the charge of the local sheet-plus-background density.
-Twenty steps of the scheme (moments -> GMRES -> mover, Sec. II), with the
+Twenty steps of the scheme (moments -> GMRES -> mover, Sec. II; the fused
+pass regroups the particles by cell every step, as benchmarked), with the
 adjoint of mover -> moments evaluated on the last step's state.
 
 Checked against the FP64 oracle fed the FP32 values widened exactly
@@ -69,7 +70,7 @@ def test_harris_twenty_steps_with_adjoint(E, O):
     from paper_2603_16624_amd import inputs as I
     p = I.harris()
     say("double Harris", p.name, p.n_particles)
-    sim = E.Simulation(p, prec=E.F32, tol=1e-10, fused=True, sort_every=4)
+    sim = E.Simulation(p, prec=E.F32, tol=1e-10, fused=True, regroup=True)
     assert all(s.q is not None for s in sim.species)
     K0 = 0.0
     for ps, s in zip(p.species, sim.species):
