@@ -366,6 +366,59 @@ def harris_rate(args):
     return out
 
 
+def four_species_2d_rate(steps=5):
+    """The paper's four-species 2D shape, 256 x 128 x 1 cells x 4 species x
+    3600 particles per cell (471,859,200 particles), FP32 form: the
+    regrouping fused pass (ecsim_move_moments_regroup) with fixed fields
+    (E small noise, B0 = (0, 0, 0.2) with noise), one untimed pass, then
+    `steps` timed with HIP events on the pass's stream. The field solve is
+    not run (it is outside the metric)."""
+    import numpy as np
+    import torch
+    from paper_2603_16624_amd import ecsim as E
+    from paper_2603_16624_amd import inputs as I
+    t0 = time.perf_counter()
+    sp, grid, nn, npart = [], None, 0, 0
+    for d in I.four_species_2d_f32():
+        if grid is None:
+            grid = E.Grid(d["n"], d["h"], d["dt"])
+            nn = grid.nn
+        s = E.Species.from_f32(d["qom"], d["cell"], d["off"], d["v"], d["q"])
+        s.cell_start = torch.as_tensor(d["cell_start"]).to("cuda")
+        npart += s.np
+        sp.append(s)
+        del d
+    gen_s = time.perf_counter() - t0
+    rng = np.random.default_rng(5008)
+    Ed = torch.as_tensor(1e-3 * rng.standard_normal((3, nn)), dtype=torch.float32).to("cuda")
+    Bd = torch.as_tensor(np.array([[0.0], [0.0], [0.2]]) + 0.02 * rng.standard_normal((3, nn)),
+                         dtype=torch.float32).to("cuda")
+    dst = [s.empty_like() for s in sp]
+    J = torch.empty((3, nn), dtype=torch.float32, device="cuda")
+    M = torch.empty((14, 9, nn), dtype=torch.float32, device="cuda")
+    ws = torch.empty(E.workspace_size(grid, npart, E.F32), dtype=torch.uint8, device="cuda")
+    st = torch.cuda.current_stream()
+    times = []
+    for it in range(steps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        E.move_moments_regroup(grid, sp, dst, Ed, Bd, Bd, J, M, ws=ws)
+        b.record(st)
+        torch.cuda.synchronize()
+        if it:
+            times.append(a.elapsed_time(b))
+        sp, dst = dst, sp
+    ms = _median(times)
+    nbytes = algorithmic_bytes("f32", npart, nn)
+    out = {"workload": "256x128x1 cells x 4 species x 3600 ppc (2D), FP32, regrouping pass, fixed fields",
+           "particles": npart, "pass_ms": ms, "particles_per_s": npart / (ms * 1e-3),
+           "hbm_frac_pass": nbytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), "generation_s": gen_s,
+           "wall_s": time.perf_counter() - t0}
+    del sp, dst, J, M, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_time():
     """Adjoint of mover -> moments (ecsim_moments_backward through the mover) on the
     32^3 x 27 ppc x 2 species workload (1,769,472 particles), FP64 and FP32: time
@@ -438,7 +491,7 @@ def main():
     if not args.no_error:
         err = fixed_error(plasma)
         print(f"[bench] fixed error: {json.dumps(err)}", file=sys.stderr, flush=True)
-    apply = adjoint = diag = two_d = harris = None
+    apply = adjoint = diag = two_d = harris = four_2d = None
     if not args.no_extras:
         apply = mass_apply_rate(args.n)
         print(f"[bench] mass apply: {json.dumps(apply)}", file=sys.stderr, flush=True)
@@ -450,6 +503,8 @@ def main():
         print(f"[bench] 2d: {json.dumps(two_d)}", file=sys.stderr, flush=True)
         harris = harris_rate(args)
         print(f"[bench] harris: {json.dumps(harris)}", file=sys.stderr, flush=True)
+        four_2d = four_species_2d_rate()
+        print(f"[bench] 2d four species: {json.dumps(four_2d)}", file=sys.stderr, flush=True)
     if args.calib_copy:
         calibrate_copy()
         print("[bench] copy calibration done", file=sys.stderr, flush=True)
@@ -506,6 +561,7 @@ def main():
         "diagnostics": diag,
         "reduced_2d": two_d,
         "double_harris": harris,
+        "four_species_2d": four_2d,
     }
     print(json.dumps(out), flush=True)
 

@@ -91,8 +91,9 @@ const char *ecsim_last_error(void);
 const char *ecsim_version(void);
 
 /* Bytes of device workspace that ecsim_sort, ecsim_moments (with
- * ECSIM_SORTED) and ecsim_move_moments need for `np` particles in total (all
- * species of one call) of precision `prec` on this grid (host, synchronous). */
+ * ECSIM_SORTED), ecsim_move_moments and ecsim_move_moments_regroup need for
+ * `np` particles in total (all species of one call) of precision `prec` on
+ * this grid (host, synchronous). */
 ecsim_status ecsim_workspace_size(const ecsim_grid *grid, int64_t np, int32_t prec,
                                   uint32_t flags, size_t *bytes /* host out */);
 

@@ -267,6 +267,36 @@ def harris(n=(256, 128, 8), ppc: int = 128, k: int = 4) -> Plasma:
                   name=f"double Harris {n[0]}x{n[1]}x{n[2]} x {ppc} ppc x 2 species")
 
 
+def four_species_2d_f32(n=(256, 128, 1), ppc: int = 3600, k: int = 6, dt: float = 0.1):
+    """The paper's four-species 2D shape (Sec. IV: 256 x 128 cells, 4 species x
+    3600 particles per cell, 471,859,200 particles) as a synthetic stand-in,
+    generated directly in the FP32 storage form and already grouped by cell
+    (ppc particles of each species per cell, in cell order), one species at a
+    time so that no FP64 copy of the state is held. Species: two counter-
+    streaming electron beams (drift +-0.1 along x, v_th 0.05) and two ion
+    species (q/m 1/25 and 1/50, v_th 0.01) of equal densities, neutral in
+    total. Yields per species: name, qom, q (per-particle charge, constant),
+    cell int32 (N,), off float32 (3, N), v float32 (3, N), cell_start int32
+    (cells + 1,)."""
+    n = tuple(int(a) for a in n)
+    h = (0.5, 0.5, 0.5)
+    nc = n[0] * n[1] * n[2]
+    vcell = h[0] * h[1] * h[2]
+    specs = [("electrons+x", ELECTRON_QOM, -0.5 / FOURPI, 0.05, 0.1),
+             ("electrons-x", ELECTRON_QOM, -0.5 / FOURPI, 0.05, -0.1),
+             ("ions", ION_QOM, 0.5 / FOURPI, 0.01, 0.0),
+             ("heavy ions", ION_QOM / 2.0, 0.5 / FOURPI, 0.01, 0.0)]
+    cell = np.repeat(np.arange(nc, dtype=np.int32), ppc)
+    cell_start = (np.arange(nc + 1, dtype=np.int64) * ppc).astype(np.int32)
+    for s, (name, qom, rho, vth, drift) in enumerate(specs):
+        g = rng(k, s, 0)
+        off = g.random((3, nc * ppc), dtype=np.float32)
+        v = (vth * rng(k, s, 1).standard_normal((3, nc * ppc), dtype=np.float32)).astype(np.float32)
+        v[0] += np.float32(drift)
+        yield dict(name=name, qom=qom, q=rho * vcell / ppc, cell=cell, off=off, v=v, cell_start=cell_start,
+                   n=n, h=h, dt=dt)
+
+
 def single_particle(n=(4, 4, 4), h=(0.5, 0.5, 0.5), dt=0.1, x=(1.1, 0.7, 1.3),
                     v=(0.03, -0.02, 0.01), q=-1e-3, qom=-1.0, b=(0.0, 0.0, 0.2),
                     e=(0.0, 0.0, 0.0)) -> Plasma:

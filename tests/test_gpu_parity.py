@@ -204,12 +204,15 @@ def test_moments_sorted_tiled(E, O, I, n, ppc, prec):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("n,ppc,vscale", [((8, 8, 8), 27, 1.0), ((6, 5, 4), 9, 40.0), ((2, 3, 2), 7, 20.0),
-                                           ((13, 7, 5), 3, 5.0), ((8, 6, 1), 12, 10.0), ((16, 1, 1), 20, 10.0)])
+                                           ((13, 7, 5), 3, 5.0), ((8, 6, 1), 12, 10.0), ((16, 1, 1), 20, 10.0),
+                                           ((8, 4, 1), 300, 2.0), ((4, 4, 2), 150, 2.0)])
 def test_move_moments_fused(E, O, I, prec, n, ppc, vscale):
     """Fused mover + deposit (two passes on one stale grouping) against the oracle's move then moments.
 
     Scaled velocities make many particles leave their cell (the stray path),
-    some by more than one cell."""
+    some by more than one cell. The last two cases put 19,200 particles in one
+    brick, more than the grouping pass maps position by position (8192), so
+    it locates their ranges by binary search."""
     say("move+moments fused", prec, n, ppc, vscale)
     p, En, BN = make_case(I, n, ppc, 17)
     for s in p.species:
@@ -340,7 +343,8 @@ def run_regroup_passes(E, O, I, p, prec, En, BN, Bnext, passes=2):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("n,ppc,vscale", [((8, 8, 8), 27, 1.0), ((6, 5, 4), 9, 40.0), ((2, 3, 2), 7, 20.0),
-                                           ((13, 7, 5), 3, 5.0), ((9, 5, 1), 12, 10.0), ((16, 1, 1), 20, 10.0)])
+                                           ((13, 7, 5), 3, 5.0), ((9, 5, 1), 12, 10.0), ((16, 1, 1), 20, 10.0),
+                                           ((8, 4, 1), 300, 2.0), ((4, 4, 2), 150, 2.0)])
 def test_move_moments_regroup(E, O, I, prec, n, ppc, vscale):
     """ecsim_move_moments_regroup: two passes, each regrouping into the other
     set of arrays. Scaled velocities send many particles out of their cell,
