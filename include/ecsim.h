@@ -186,8 +186,9 @@ ecsim_status ecsim_move_moments(const ecsim_grid *grid, const ecsim_particles *s
  * it, then the particles that arrived), and writes each species' particles in
  * that order to dst[s], whose cell_start receives the new ranges. The paper
  * does not sort its particles (Sec. III); here the grouping that the tiled
- * deposit relies on is kept exact every step at the cost of one more write of
- * the particle state, in place of a separate sort.
+ * deposit relies on is renewed at the cost of one more write of the particle
+ * state, in place of a separate sort. Called every few steps (ecsim_move_moments
+ * in between, on the grouping as it goes stale) it costs least per step.
  *   species: as for ecsim_move_moments (grouped, cell_start required); their
  *            arrays are moved in place and are no longer grouped afterwards.
  *   dst:     nspecies targets (device arrays) of the same precision and sizes,

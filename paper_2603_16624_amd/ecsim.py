@@ -374,9 +374,10 @@ class Simulation:
     is used; between re-sorts (every ``sort_every`` steps) the cell ranges
     are a stale grouping that the deposit corrects for. With ``fused=True``
     the mover and the next step's moments run as one pass; with
-    ``regroup=True`` as well, that pass also writes the particles grouped by
-    cell into a second set of arrays (ecsim_move_moments_regroup), so the
-    grouping is exact every step and no separate re-sort runs.
+    ``regroup=True`` as well, every ``sort_every``-th pass also writes the
+    particles grouped by cell into a second set of arrays
+    (ecsim_move_moments_regroup) in place of a separate re-sort, and the
+    passes in between run on that grouping as it goes stale.
     """
 
     def __init__(self, plasma, prec: int = F64, device="cuda", tol: float = 1e-10, restart: int = 30,
@@ -478,12 +479,16 @@ class Simulation:
     def fused_particles(self, ke: Optional[torch.Tensor] = None):
         """The fused particle pass proper (fused_fields() first)."""
         Et = self.Et_p if self.prec == F32 else self.E_theta
-        if self.regroup:
+        if self.regroup_now():
             move_moments_regroup(self.grid, self.species, self._spare, Et, self.BN_p, self.BN_next_p, self.J, self.M,
                                  ke, ws=self.ws)
             self.species, self._spare = list(self._spare), list(self.species)
             return
         move_moments(self.grid, self.species, Et, self.BN_p, self.BN_next_p, self.J, self.M, ke, ws=self.ws)
+
+    def regroup_now(self) -> bool:
+        """Whether the coming fused pass regroups (the last pass of each period of sort_every)."""
+        return self.regroup and (self.nstep + 1) % self.sort_every == 0
 
     def fused_pass(self, ke: Optional[torch.Tensor] = None):
         """Mover with (E^{n+theta}, B^n), then the moments at x^{n+1/2} with B^{n+1}."""

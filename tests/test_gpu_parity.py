@@ -295,10 +295,12 @@ def regroup_case(E, I, p, prec):
     return sp, xs, vs, qs, torch.float32, TOL32
 
 
-def run_regroup_passes(E, O, I, p, prec, En, BN, Bnext, passes=2):
+def run_regroup_passes(E, O, I, p, prec, En, BN, Bnext, passes=2, plain_first=False):
     """Regrouping fused passes against the oracle: J, M and the kinetic energy
     each pass, the targets' grouping, the targets holding exactly the moved
-    particles, and the final states (matched through their x velocities)."""
+    particles, and the final states (matched through their whole velocities).
+    With plain_first, a fused pass without regrouping goes first, so the first
+    regrouping starts from a stale grouping."""
     grid = E.Grid(p.n, p.h, p.dt)
     sp, xs, vs, qs, tdt, tol = regroup_case(E, I, p, prec)
     if prec == "f64":
@@ -309,6 +311,14 @@ def run_regroup_passes(E, O, I, p, prec, En, BN, Bnext, passes=2):
     dst = [s.empty_like() for s in sp]
     J = torch.full((3, p.nn), 7.0, dtype=tdt, device="cuda")
     M = torch.full((14, 9, p.nn), 7.0, dtype=tdt, device="cuda")
+    if plain_first:
+        E.move_moments(grid, sp, dev(Ec, tdt), dev(Bc, tdt), dev(Bnc, tdt), J, M)
+        x1s, v1s = [], []
+        for s, x, v in zip(p.species, xs, vs):
+            x1, v1 = O.move(p.n, p.h, p.dt, x, v, s.qom, Ec, Bc)
+            x1s.append(x1)
+            v1s.append(v1)
+        xs, vs = x1s, v1s
     for it in range(passes):
         ke = torch.zeros(1, dtype=torch.float64, device="cuda")
         E.move_moments_regroup(grid, sp, dst, dev(Ec, tdt), dev(Bc, tdt), dev(Bnc, tdt), J, M, ke)
@@ -355,6 +365,20 @@ def test_move_moments_regroup(E, O, I, prec, n, ppc, vscale):
         s.v = s.v * vscale
     rng = np.random.default_rng(24)
     run_regroup_passes(E, O, I, p, prec, En, BN, BN + 0.01 * rng.standard_normal(BN.shape))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,ppc,vscale", [((6, 5, 4), 9, 40.0), ((9, 5, 1), 12, 10.0), ((4, 4, 2), 150, 2.0)])
+def test_move_moments_regroup_from_stale_grouping(E, O, I, prec, n, ppc, vscale):
+    """A fused pass without regrouping, then two regrouping passes: the first
+    regroups particles that left their ranges a pass earlier (as every
+    sort_every-th pass of the loop does)."""
+    say("regroup from stale", prec, n, ppc, vscale)
+    p, En, BN = make_case(I, n, ppc, 27)
+    for s in p.species:
+        s.v = s.v * vscale
+    rng = np.random.default_rng(28)
+    run_regroup_passes(E, O, I, p, prec, En, BN, BN + 0.01 * rng.standard_normal(BN.shape), plain_first=True)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
