@@ -63,3 +63,24 @@ def test_harris_structure(inputs):
     qe = p.species[0].q.sum()
     qi = p.species[1].q.sum()
     assert abs(qe + qi) < 1e-2 * abs(qi)
+
+
+def test_four_species_2d_structure(inputs):
+    """The four-species 2D stand-in, at a reduced size: grouped by cell (ppc of
+    each species per cell, in cell order, ranges as cell_start), offsets in
+    [0, 1), total charge zero, the electron beams drifting +-0.1 along x."""
+    import numpy as np
+    n, ppc = (8, 6, 1), 50
+    sp = list(inputs.four_species_2d_f32(n=n, ppc=ppc))
+    assert len(sp) == 4
+    nc = n[0] * n[1]
+    total = 0.0
+    for d in sp:
+        assert d["cell"].dtype == np.int32 and d["off"].dtype == np.float32 and d["v"].dtype == np.float32
+        assert np.array_equal(d["cell"], np.repeat(np.arange(nc), ppc))
+        assert np.array_equal(d["cell_start"], np.arange(nc + 1) * ppc)
+        assert d["off"].min() >= 0.0 and d["off"].max() < 1.0
+        total += d["q"] * d["cell"].size
+    assert abs(total) < 1e-12 * sum(abs(d["q"]) * d["cell"].size for d in sp)
+    assert abs(sp[0]["v"][0].mean() - 0.1) < 0.01 and abs(sp[1]["v"][0].mean() + 0.1) < 0.01
+    assert abs(sp[0]["v"][1].std() - 0.05) < 0.005 and abs(sp[2]["v"][1].std() - 0.01) < 0.001
