@@ -997,6 +997,14 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
     // corner B of the cell, staged for the lanes of this half
     if (hl < 24) stage[hl] = sv;
     wave_sync();
+    // the cell's corner B in registers, read once per pair (the same values
+    // for every particle of the half's cell); the regrouping deposit, whose
+    // registers would then exceed two waves per SIMD, reads them per block
+    T Bc[24];
+    if constexpr (!REGROUP) {
+#pragma unroll
+      for (int i = 0; i < 24; ++i) Bc[i] = stage[i];
+    }
 
     // regrouping: the cell's particles written so far, per species
     int run[kMaxTiledSpecies] = {0, 0, 0, 0};
@@ -1027,7 +1035,7 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
         T W[8];
 #pragma unroll
         for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
-        const Vec3<T> B1 = gather_staged(W, stage);
+        const Vec3<T> B1 = REGROUP ? gather_staged(W, stage) : gather_staged(W, Bc);
         T r[39];
         particle_record(ps, B1, Vec3<T>{pd.v0, pd.v1, pd.v2}, keep ? dep_charge(pd, lptr) : T(0), sp, r);
 #pragma unroll
