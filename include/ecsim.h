@@ -29,10 +29,24 @@
  *    argument returns ECSIM_EINVAL and launches nothing. A HIP launch or
  *    runtime failure returns ECSIM_EHIP. ecsim_last_error() describes the last
  *    non-OK status of the calling thread. Nothing throws across this ABI.
+ *  - Non-finite values: the kernels of the mover, the moment deposits, the
+ *    diagnostics and the adjoint set a per-device flag when they produce a
+ *    NaN or an infinity (new velocities, deposited node values, gradients);
+ *    no call synchronises to look at it. ecsim_check_finite() (synchronous)
+ *    and ecsim_nonfinite_read() (asynchronous) report and clear it.
  *  - Precision: ECSIM_F64 particles use FP64 fields and outputs. ECSIM_F32
  *    particles store an int32 cell index plus FP32 in-cell offsets in [0,1)
- *    and FP32 velocities, use FP32 node fields, and accumulate J-hat and M in
- *    FP32 with compensated (Neumaier) tile sums.
+ *    and FP32 velocities and use FP32 node fields. Their arithmetic: the
+ *    mover gathers E and B and pushes positions in FP32 but forms the
+ *    rotation alpha_p and the velocity update v^{n+1} = 2 alpha_p u - v^n in
+ *    FP64, rounding v^{n+1} once to FP32 (an FP32 alpha_p would scale |v| by
+ *    the same 1 + O(1e-7) for every particle in a uniform B, a one-way energy
+ *    drift). The moment deposits form alpha_p, the weights and J-hat and M in
+ *    FP32. The grouped (ECSIM_SORTED) deposit sums a cell's particles in
+ *    blocks of 64 on the matrix cores (plain FP32 sums inside a block) and
+ *    combines the blocks with Kahan compensation, then adds each node value
+ *    to J and M with one FP32 atomic per brick of cells; the any-order
+ *    deposit adds every particle's terms with plain FP32 atomics.
  */
 #ifndef ECSIM_H
 #define ECSIM_H
@@ -50,6 +64,7 @@ enum {
   ECSIM_EINVAL = -1,       /* invalid argument (nothing launched)            */
   ECSIM_EHIP = -2,         /* HIP runtime or launch error                    */
   ECSIM_EWORKSPACE = -3,   /* workspace missing or smaller than required     */
+  ECSIM_ENONFINITE = -4,   /* a NaN or infinity was produced (see above)     */
   ECSIM_ENOCONV = -5       /* GMRES did not reach the tolerance              */
 };
 
@@ -59,7 +74,8 @@ enum { ECSIM_F64 = 0, ECSIM_F32 = 1 };
 enum {
   ECSIM_ACCUMULATE = 1,    /* add into J/M (or gE/gB) instead of overwriting */
   ECSIM_SORTED = 2,        /* particles are grouped by cell; cell_start valid */
-  ECSIM_BWD_THROUGH_MOVER = 8 /* backward: differentiate mover -> moments   */
+  ECSIM_BWD_THROUGH_MOVER = 8, /* backward: differentiate mover -> moments  */
+  ECSIM_BWD_OFFSET_GRAD = 16   /* backward, FP32 only: gpos = dL/d(offset)    */
 };
 
 typedef struct {
@@ -89,6 +105,23 @@ const char *ecsim_last_error(void);
 
 /* Library version string (host). */
 const char *ecsim_version(void);
+
+/*
+ * Non-finite values (a NaN or an infinity in an input propagates to the new
+ * velocities, the deposited J-hat, M and diagnostic values, or the adjoint's
+ * particle gradients, where the kernels record it in a per-device flag):
+ *   ecsim_check_finite: synchronous. Waits for `stream`, reads the current
+ *     device's flag and clears it; returns ECSIM_ENONFINITE if any kernel of
+ *     this library on the device (any stream) produced a non-finite value
+ *     since the flag was last cleared, else ECSIM_OK.
+ *   ecsim_nonfinite_read: asynchronous on `stream`; copies the flag into the
+ *     device int32 *flag_out (0 = all finite, 1 = a non-finite value seen) and
+ *     clears it, in stream order.
+ * The field solve reports a non-finite right-hand side or residual itself
+ * (ECSIM_ENONFINITE). The flag is per device and shared by every stream.
+ */
+ecsim_status ecsim_check_finite(void *stream);
+ecsim_status ecsim_nonfinite_read(int32_t *flag_out /* device */, void *stream);
 
 /* Bytes of device workspace that ecsim_sort, ecsim_moments (with
  * ECSIM_SORTED), ecsim_move_moments and ecsim_move_moments_regroup need for
@@ -126,9 +159,11 @@ ecsim_status ecsim_move(const ecsim_grid *grid, const ecsim_particles *sp,
  * All species must share one precision; J, M and B_node are in it.
  * J and M are overwritten unless ECSIM_ACCUMULATE is set. With ECSIM_SORTED
  * every species must carry cell_start (particles grouped by cell ranges) and
- * the tiled deposit is used; a particle that is not in its range's cell is
+ * the tiled deposit is used (at most 4 species of fewer than 2^28 particles
+ * each, else ECSIM_EINVAL); a particle that is not in its range's cell is
  * still deposited correctly, through a slower stray path. Without
- * ECSIM_SORTED a per-particle atomic deposit handles any order.
+ * ECSIM_SORTED a per-particle atomic deposit handles any order and any
+ * number of species.
  * ws/ws_bytes: with ECSIM_SORTED, device workspace of at least
  * ecsim_workspace_size() bytes for the total particle count; else unused.
  */
@@ -148,7 +183,8 @@ ecsim_status ecsim_moments(const ecsim_grid *grid, const ecsim_particles *specie
  * All species share one precision; rho, J and P are in it and are
  * overwritten unless ECSIM_ACCUMULATE is set. With ECSIM_SORTED every species
  * carries cell_start and a tiled kernel is used (a particle outside its
- * range's cell is still counted, through a slower path). Without
+ * range's cell is still counted, through a slower path; at most 4 species of
+ * fewer than 2^28 particles each, else ECSIM_EINVAL). Without
  * ECSIM_SORTED a per-particle atomic kernel takes any order; its FP32 form
  * accumulates in FP64 in the workspace and rounds once into the outputs.
  * ws/ws_bytes: device workspace of ecsim_diagnostics_workspace_size() bytes
@@ -198,7 +234,7 @@ ecsim_status ecsim_move_moments(const ecsim_grid *grid, const ecsim_particles *s
  *            After the call dst[s] holds species s's moved particles in cell
  *            order (positions, velocities, charges, cells) and is what the
  *            next pass takes as `species`.
- * Needs nspecies * cells <= 2^20. Workspace, flags, ke_out and errors as for
+ * Needs nspecies * cells < 2^31. Workspace, flags, ke_out and errors as for
  * ecsim_move_moments (ECSIM_EINVAL also for a mismatched or aliasing target).
  */
 ecsim_status ecsim_move_moments_regroup(const ecsim_grid *grid, const ecsim_particles *species,
@@ -227,8 +263,10 @@ ecsim_status ecsim_mass_apply(const ecsim_grid *grid, int32_t m_prec, const void
  * followed by moments(x', v'; B_node) (same B_node); without it the forward is
  * moments(x, v; B_node) and E_node may be NULL.
  * Outputs: gpos[3], gvel[3] per particle, dL/d(position) and dL/d(velocity),
- * in the particles' precision (F32: position derivative is with respect to the
- * physical coordinate, i.e. dL/d(offset) / h). gE, gB: [3][Nn], accumulated
+ * in the particles' precision. The position derivative is with respect to the
+ * physical coordinate; with ECSIM_BWD_OFFSET_GRAD (FP32 particles only, else
+ * ECSIM_EINVAL) it is with respect to the stored in-cell offset instead, i.e.
+ * h times the physical one. gE, gB: [3][Nn], accumulated
  * (+=) always; gE untouched without ECSIM_BWD_THROUGH_MOVER. gJ: [3][Nn],
  * gM: [14][9][Nn], in the particles' precision. Alpha and the weights are
  * recomputed, not stored.
@@ -240,12 +278,16 @@ ecsim_status ecsim_moments_backward(const ecsim_grid *grid, const ecsim_particle
                                     uint32_t flags, void *stream);
 
 /*
- * Counting sort of one species by cell, out of place: the particles of `src`
- * are written to the arrays of `dst` (same precision and np, no aliasing) in
- * cell order; the order inside a cell is not specified. cell_start_out [Nc+1]
- * receives each cell's range in dst and, if perm_out is not NULL,
- * perm_out[i] (int32) the index in src of the particle now at dst[i].
- * ws: device workspace of ecsim_workspace_size() bytes.
+ * Counting sort of one species by cell, out of place. The paper's moment
+ * gather runs over particles in storage order with atomic updates; its
+ * authors tried sorting the particles (with reductions) and dropped it
+ * (Sec. III). Here grouping by cell is what lets the tiled deposit reduce a
+ * cell's particles before touching memory, and this call is the explicit
+ * sort. The particles of `src` are written to the arrays of `dst` (same
+ * precision and np, no aliasing) in cell order; the order inside a cell is
+ * not specified. cell_start_out [Nc+1] receives each cell's range in dst and,
+ * if perm_out is not NULL, perm_out[i] (int32) the index in src of the
+ * particle now at dst[i]. ws: device workspace of ecsim_workspace_size() bytes.
  */
 ecsim_status ecsim_sort(const ecsim_grid *grid, const ecsim_particles *src,
                         const ecsim_particles *dst, int32_t *cell_start_out,

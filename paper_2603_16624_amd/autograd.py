@@ -11,7 +11,7 @@ only they are saved.
 
 FP64 form: ``pos`` holds absolute positions. FP32 form: ``pos`` holds the
 in-cell offsets and ``cell`` the int32 cell indices; the position gradient is
-then taken with respect to the offsets (the adjoint's d/dx times h).
+then taken with respect to the offsets (the library's ECSIM_BWD_OFFSET_GRAD).
 """
 from typing import Optional
 
@@ -50,9 +50,8 @@ class MoveMoments(torch.autograd.Function):
         gB = torch.zeros_like(B)
         zJ = torch.zeros((3, grid.nn), dtype=pos.dtype, device=pos.device) if gJ is None else gJ.contiguous()
         zM = torch.zeros((14, 9, grid.nn), dtype=pos.dtype, device=pos.device) if gM is None else gM.contiguous()
-        _E.moments_backward(grid, sp, E.detach(), B.detach(), zJ, zM, gpos, gvel, gE, gB, through_mover=True)
-        if ctx.prec == _E.F32:   # d/d(offset) = h d/dx
-            gpos = gpos * torch.tensor(grid.h, dtype=gpos.dtype, device=gpos.device)[:, None]
+        _E.moments_backward(grid, sp, E.detach(), B.detach(), zJ, zM, gpos, gvel, gE, gB, through_mover=True,
+                            offset_grad=ctx.prec == _E.F32)
         return None, None, None, gpos, gvel, gE, gB, None
 
 

@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(kBlock) k_backward(
     const T* __restrict__ q, T q_const, T beta, T dth0, T dth1, T dth2, const T* __restrict__ E,
     const T* __restrict__ B, const T* __restrict__ gJ, const T* __restrict__ gM, T* __restrict__ gx0,
     T* __restrict__ gx1, T* __restrict__ gx2, T* __restrict__ gv0, T* __restrict__ gv1, T* __restrict__ gv2,
-    T* __restrict__ gE, T* __restrict__ gB) {
+    T* __restrict__ gE, T* __restrict__ gB, bool offset_grad) {
   // every lane runs (the gradient scatter works across the wavefront); lanes
   // past the end recompute the last particle and store nothing
   const int lane = threadIdx.x & 63;
@@ -207,6 +207,13 @@ __global__ void __launch_bounds__(kBlock) k_backward(
     gx.y += gxi0[1] / h[1];
     gx.z += gxi0[2] / h[2];
   }
+  if (offset_grad) {   // FP32 form: d/d(offset) = h d/dx
+    gx.x *= h[0];
+    gx.y *= h[1];
+    gx.z *= h[2];
+  }
+  note_nonfinite(g, valid && !(finite(gx.x) && finite(gx.y) && finite(gx.z) && finite(gv.x) && finite(gv.y) &&
+                               finite(gv.z)));
   if (valid) {
     gx0[p] = gx.x;
     gx1[p] = gx.y;
@@ -220,7 +227,7 @@ __global__ void __launch_bounds__(kBlock) k_backward(
 template <typename T, bool CELL>
 hipError_t launch_T(const Grid& g, const SpeciesArgs& sp, const void* E, const void* B, const void* gJ,
                     const void* gM, void* const gpos[3], void* const gvel[3], void* gE, void* gB, bool through,
-                    hipStream_t st) {
+                    bool offset_grad, hipStream_t st) {
   const double beta = sp.qom * g.dt / 2.0;
   dim3 grid((unsigned)((sp.np + kBlock - 1) / kBlock)), block(kBlock);
   auto args = [&](auto kern) {
@@ -229,7 +236,7 @@ hipError_t launch_T(const Grid& g, const SpeciesArgs& sp, const void* E, const v
                        (const T*)sp.vel[2], (const T*)sp.q, (T)sp.q_const, (T)beta, (T)(g.pdt[0] / g.hx),
                        (T)(g.pdt[1] / g.hy), (T)(g.pdt[2] / g.hz), (const T*)E, (const T*)B, (const T*)gJ, (const T*)gM,
                        (T*)gpos[0], (T*)gpos[1], (T*)gpos[2], (T*)gvel[0], (T*)gvel[1], (T*)gvel[2], (T*)gE,
-                       (T*)gB);
+                       (T*)gB, offset_grad);
   };
   if (through)
     args(k_backward<T, CELL, true>);
@@ -242,10 +249,10 @@ hipError_t launch_T(const Grid& g, const SpeciesArgs& sp, const void* E, const v
 
 hipError_t launch_backward(const Grid& g, bool f32, const SpeciesArgs& sp, const void* E, const void* B,
                            const void* gJ, const void* gM, void* const gpos[3], void* const gvel[3], void* gE,
-                           void* gB, bool through_mover, hipStream_t st) {
+                           void* gB, bool through_mover, bool offset_grad, hipStream_t st) {
   if (sp.np == 0) return hipSuccess;
-  if (f32) return launch_T<float, true>(g, sp, E, B, gJ, gM, gpos, gvel, gE, gB, through_mover, st);
-  return launch_T<double, false>(g, sp, E, B, gJ, gM, gpos, gvel, gE, gB, through_mover, st);
+  if (f32) return launch_T<float, true>(g, sp, E, B, gJ, gM, gpos, gvel, gE, gB, through_mover, offset_grad, st);
+  return launch_T<double, false>(g, sp, E, B, gJ, gM, gpos, gvel, gE, gB, through_mover, false, st);
 }
 
 }  // namespace ecsim

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/ecsim.h"
@@ -32,7 +33,37 @@ ecsim_status hip_fail(hipError_t e, const char* where) {
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kTheta = 0.5;
 constexpr double kC = 1.0;
-constexpr int64_t kMaxCells = (int64_t)1 << 20;   // counting-sort scan limit
+
+// The per-device record of non-finite values: kernels of the mover, the
+// moment deposits and the adjoint set it when they produce a value that is not
+// finite; ecsim_check_finite / ecsim_nonfinite_read report and clear it. Every
+// device that runs the library holds its own copy, whose address is looked up
+// once per device.
+__device__ __attribute__((aligned(256))) int g_nonfinite[64];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_flag_mu;
+int* g_flag_ptr[kMaxDevices] = {};
+
+int* device_flag() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_flag_mu);
+  if (!g_flag_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_nonfinite)) != hipSuccess || !p) return nullptr;
+    g_flag_ptr[dev] = (int*)p;
+  }
+  return g_flag_ptr[dev];
+}
+
+// Attaches the current device's non-finite flag to a validated grid, right
+// before the first launch of an entry point.
+ecsim_status bind_flag(Grid& g, const char* who) {
+  g.nonfinite = device_flag();
+  if (!g.nonfinite) return fail(ECSIM_EHIP, "%s: the device's non-finite flag is not accessible", who);
+  return ECSIM_OK;
+}
 
 ecsim_status make_grid(const ecsim_grid* gr, Grid& g) {
   if (!gr) return fail(ECSIM_EINVAL, "grid is NULL");
@@ -55,6 +86,7 @@ ecsim_status make_grid(const ecsim_grid* gr, Grid& g) {
   // the mover's fixPosition step for reduced (1D/2D) runs: no push along a
   // dimension of a single cell
   for (int d = 0; d < 3; ++d) g.pdt[d] = gr->n[d] > 1 ? gr->dt : 0.0;
+  g.nonfinite = nullptr;
   g.div_x = make_fastdiv((uint32_t)g.nx);
   g.div_xy = make_fastdiv((uint32_t)((int64_t)g.nx * g.ny));
   return ECSIM_OK;
@@ -119,6 +151,7 @@ ecsim_status ecsim_move(const ecsim_grid* grid, const ecsim_particles* sp, const
   if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
   if (make_species(sp, a, "ecsim_move") != ECSIM_OK) return ECSIM_EINVAL;
   if (!E_node || !B_node) return fail(ECSIM_EINVAL, "ecsim_move: E_node and B_node are required");
+  if (bind_flag(g, "ecsim_move") != ECSIM_OK) return ECSIM_EHIP;
   hipError_t e = launch_move(g, sp->prec == ECSIM_F32, a, E_node, B_node, ke_out, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "ecsim_move");
   return ECSIM_OK;
@@ -154,7 +187,10 @@ ecsim_status ecsim_moments(const ecsim_grid* grid, const ecsim_particles* specie
   if (!B_node || !J || !M) return fail(ECSIM_EINVAL, "ecsim_moments: B_node, J and M are required");
   const bool f32 = species[0].prec == ECSIM_F32;
   const size_t esz = f32 ? 4 : 8;
-  const bool tiled = (flags & ECSIM_SORTED) && tiled_species_ok(a, nspecies);
+  const bool tiled = (flags & ECSIM_SORTED) != 0;
+  if (tiled && !tiled_species_ok(a, nspecies))
+    return fail(ECSIM_EINVAL, "ecsim_moments: ECSIM_SORTED takes at most 4 species of fewer than 2^28 particles "
+                              "each (without ECSIM_SORTED the any-order deposit takes more)");
   int64_t np_total = 0;
   for (int s = 0; s < nspecies; ++s) np_total += a[s].np;
   if (tiled) {
@@ -162,6 +198,7 @@ ecsim_status ecsim_moments(const ecsim_grid* grid, const ecsim_particles* specie
     if (!ws || ws_bytes < need)
       return fail(ECSIM_EWORKSPACE, "ecsim_moments: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
   }
+  if (bind_flag(g, "ecsim_moments") != ECSIM_OK) return ECSIM_EHIP;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   if (!(flags & ECSIM_ACCUMULATE)) {
@@ -202,11 +239,15 @@ ecsim_status ecsim_diagnostics(const ecsim_grid* grid, const ecsim_particles* sp
   if (!rho || !J || !P) return fail(ECSIM_EINVAL, "ecsim_diagnostics: rho, J and P are required");
   const bool f32 = species[0].prec == ECSIM_F32;
   const size_t esz = f32 ? 4 : 8;
-  const bool tiled = (flags & ECSIM_SORTED) && tiled_species_ok(a, nspecies);
+  const bool tiled = (flags & ECSIM_SORTED) != 0;
+  if (tiled && !tiled_species_ok(a, nspecies))
+    return fail(ECSIM_EINVAL, "ecsim_diagnostics: ECSIM_SORTED takes at most 4 species of fewer than 2^28 "
+                              "particles each (without ECSIM_SORTED the any-order kernel takes more)");
   const size_t need = diag_ws_bytes(g, f32, tiled ? ECSIM_SORTED : 0);
   if (need && (!ws || ws_bytes < need))
     return fail(ECSIM_EWORKSPACE, "ecsim_diagnostics: workspace of %zu bytes needed, %zu given", need,
                 ws ? ws_bytes : 0);
+  if (bind_flag(g, "ecsim_diagnostics") != ECSIM_OK) return ECSIM_EHIP;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   if (!(flags & ECSIM_ACCUMULATE)) {
@@ -240,6 +281,7 @@ ecsim_status ecsim_move_moments(const ecsim_grid* grid, const ecsim_particles* s
   const size_t need = tiled_workspace_bytes(g, np_total, f32);
   if (!ws || ws_bytes < need)
     return fail(ECSIM_EWORKSPACE, "ecsim_move_moments: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
+  if (bind_flag(g, "ecsim_move_moments") != ECSIM_OK) return ECSIM_EHIP;
   const size_t esz = f32 ? 4 : 8;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
@@ -266,9 +308,8 @@ ecsim_status ecsim_move_moments_regroup(const ecsim_grid* grid, const ecsim_part
     return fail(ECSIM_EINVAL, "%s: E_node, B_node, B_next, J and M are required", who);
   if (!tiled_species_ok(a, nspecies))
     return fail(ECSIM_EINVAL, "%s: at most 4 species of fewer than 2^28 particles each", who);
-  if ((int64_t)nspecies * g.nn > regroup_max_entries())
-    return fail(ECSIM_EINVAL, "%s: species x cells = %lld exceeds %lld", who, (long long)nspecies * g.nn,
-                (long long)regroup_max_entries());
+  if ((int64_t)nspecies * g.nn >= ((int64_t)1 << 31))
+    return fail(ECSIM_EINVAL, "%s: species x cells = %lld exceeds 2^31 - 1", who, (long long)nspecies * g.nn);
   for (int s = 0; s < nspecies; ++s) {
     if (make_species(&dst[s], d[s], who) != ECSIM_OK) return ECSIM_EINVAL;
     if (dst[s].prec != species[s].prec || dst[s].np != species[s].np)
@@ -294,6 +335,7 @@ ecsim_status ecsim_move_moments_regroup(const ecsim_grid* grid, const ecsim_part
   const size_t need = tiled_workspace_bytes(g, np_total, f32);
   if (!ws || ws_bytes < need)
     return fail(ECSIM_EWORKSPACE, "%s: workspace of %zu bytes needed, %zu given", who, need, ws ? ws_bytes : 0);
+  if (bind_flag(g, who) != ECSIM_OK) return ECSIM_EHIP;
   const size_t esz = f32 ? 4 : 8;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
@@ -325,17 +367,21 @@ ecsim_status ecsim_moments_backward(const ecsim_grid* grid, const ecsim_particle
   SpeciesArgs a;
   if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
   if (make_species(sp, a, "ecsim_moments_backward") != ECSIM_OK) return ECSIM_EINVAL;
-  if (flags & ~(uint32_t)(ECSIM_BWD_THROUGH_MOVER | ECSIM_ACCUMULATE))
+  if (flags & ~(uint32_t)(ECSIM_BWD_THROUGH_MOVER | ECSIM_ACCUMULATE | ECSIM_BWD_OFFSET_GRAD))
     return fail(ECSIM_EINVAL, "ecsim_moments_backward: unknown flags 0x%x", flags);
   const bool through = flags & ECSIM_BWD_THROUGH_MOVER;
+  const bool offset_grad = (flags & ECSIM_BWD_OFFSET_GRAD) != 0;
+  if (offset_grad && sp->prec != ECSIM_F32)
+    return fail(ECSIM_EINVAL, "ecsim_moments_backward: ECSIM_BWD_OFFSET_GRAD needs FP32 (offset + cell) particles");
   if (!B_node || !gJ || !gM || !gB) return fail(ECSIM_EINVAL, "ecsim_moments_backward: B_node, gJ, gM, gB are required");
   if (through && (!E_node || !gE)) return fail(ECSIM_EINVAL, "ecsim_moments_backward: through the mover needs E_node and gE");
   if (!gpos || !gvel) return fail(ECSIM_EINVAL, "ecsim_moments_backward: gpos and gvel are required");
   if (sp->np > 0)
     for (int d = 0; d < 3; ++d)
       if (!gpos[d] || !gvel[d]) return fail(ECSIM_EINVAL, "ecsim_moments_backward: gpos/gvel[%d] is NULL", d);
+  if (bind_flag(g, "ecsim_moments_backward") != ECSIM_OK) return ECSIM_EHIP;
   hipError_t e = launch_backward(g, sp->prec == ECSIM_F32, a, E_node, B_node, gJ, gM, gpos, gvel, gE, gB, through,
-                                 (hipStream_t)stream);
+                                 offset_grad, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "ecsim_moments_backward");
   return ECSIM_OK;
 }
@@ -345,7 +391,6 @@ ecsim_status ecsim_sort(const ecsim_grid* grid, const ecsim_particles* src, cons
   Grid g;
   SpeciesArgs a, b;
   if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
-  if (g.nn > kMaxCells) return fail(ECSIM_EINVAL, "ecsim_sort: at most %lld cells", (long long)kMaxCells);
   if (make_species(src, a, "ecsim_sort src") != ECSIM_OK) return ECSIM_EINVAL;
   if (make_species(dst, b, "ecsim_sort dst") != ECSIM_OK) return ECSIM_EINVAL;
   if (src->prec != dst->prec || src->np != dst->np) return fail(ECSIM_EINVAL, "ecsim_sort: src and dst differ in precision or np");
@@ -388,6 +433,29 @@ ecsim_status ecsim_field_energy(const ecsim_grid* grid, const double* F, double*
     return fail(ECSIM_EWORKSPACE, "ecsim_field_energy: workspace of %d bytes needed", (int)ECSIM_ENERGY_WS_BYTES);
   hipError_t e = launch_sumsq(F, 3 * g.nn, g.V / (8.0 * kPi), (double*)ws, out, false, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "ecsim_field_energy");
+  return ECSIM_OK;
+}
+
+ecsim_status ecsim_check_finite(void* stream) {
+  int* f = device_flag();
+  if (!f) return fail(ECSIM_EHIP, "ecsim_check_finite: the device's non-finite flag is not accessible");
+  hipError_t e;
+  if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) return hip_fail(e, "ecsim_check_finite");
+  int v = 0;
+  if ((e = hipMemcpy(&v, f, sizeof v, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "ecsim_check_finite");
+  if (v == 0) return ECSIM_OK;
+  const int zero = 0;
+  if ((e = hipMemcpy(f, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "ecsim_check_finite");
+  return fail(ECSIM_ENONFINITE, "a kernel produced a non-finite value since the last check");
+}
+
+ecsim_status ecsim_nonfinite_read(int32_t* flag_out, void* stream) {
+  if (!flag_out) return fail(ECSIM_EINVAL, "ecsim_nonfinite_read: flag_out is NULL");
+  int* f = device_flag();
+  if (!f) return fail(ECSIM_EHIP, "ecsim_nonfinite_read: the device's non-finite flag is not accessible");
+  hipError_t e = launch_take_flag(f, flag_out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "ecsim_nonfinite_read");
   return ECSIM_OK;
 }
 
@@ -480,6 +548,8 @@ ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const voi
   };
   double bnorm2 = 0.0;
   HIPCK(dot_host(bvec, 1, bvec, &bnorm2));
+  if (!std::isfinite(bnorm2))
+    return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the right-hand side is not finite (J, E^n or B^n)");
   const double bnorm = std::sqrt(bnorm2);
   int it = 0;
   double rel = 0.0;
@@ -495,6 +565,8 @@ ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const voi
     HIPCK(launch_axpby(n, -1.0, w, 1.0, V, st));
     double beta2 = 0.0;
     HIPCK(dot_host(V, 1, V, &beta2));
+    if (!std::isfinite(beta2))
+      return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the residual is not finite (M or the iterate)");
     double beta = std::sqrt(beta2);
     rel = beta / bnorm;
     if (rel <= tol) { converged = true; break; }
@@ -515,6 +587,8 @@ ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const voi
       for (int i = 0; i <= j; ++i) hcol[i] += h2[i];
       double hn2 = 0.0;
       HIPCK(dot_host(w, 1, w, &hn2));
+      if (!std::isfinite(hn2))
+        return fail(ECSIM_ENONFINITE, "ecsim_field_solve: a Krylov vector is not finite (M is not finite)");
       double hn = std::sqrt(hn2);
       if (hn > 0.0) HIPCK(launch_scale_copy(n, 1.0 / hn, w, Vj1, st));
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];

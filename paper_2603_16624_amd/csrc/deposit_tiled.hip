@@ -555,6 +555,7 @@ __device__ __forceinline__ void flush_brick(const Grid& g, const T* scell, int x
   constexpr int NX = TX + 1, NY = TY + 1, NZ = TZ + 1, NN = NX * NY * NZ;
   // items: (ij, node) for the mass matrix, then (component, node) for J
   constexpr int NITEM = 9 * NN + 3 * NN;
+  bool bad = false;
   for (int it = tid; it < NITEM; it += nthr) {
     const bool is_m = it < 9 * NN;
     const int ln = is_m ? it % NN : (it - 9 * NN) % NN;
@@ -586,6 +587,7 @@ __device__ __forceinline__ void flush_brick(const Grid& g, const T* scell, int x
           const T x = sb[coff[a] + cls * 9];
           v += cin[a] ? x : T(0);
         }
+        bad = bad || !finite(v);
         if (v != T(0)) unsafeAtomicAdd(M + (int64_t)(k * 9 + sub) * g.nn + gn, v);
       }
     } else {
@@ -595,9 +597,11 @@ __device__ __forceinline__ void flush_brick(const Grid& g, const T* scell, int x
         const T x = sb[coff[a] + 243 + 3 * a];
         v += cin[a] ? x : T(0);
       }
+      bad = bad || !finite(v);
       if (v != T(0)) unsafeAtomicAdd(J + (int64_t)sub * g.nn + gn, v);
     }
   }
+  note_nonfinite(g, bad);
 }
 
 // Records in LDS are stored transposed, rec[row][slot] with a row stride of
@@ -781,6 +785,7 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
         Bp.z = fma(w, fld[5 * HN + nl], Bp.z);
       }
       const Vec3<T> v = advance_velocity(Bp, sp.beta, Vec3<T>{pd.v0, pd.v1, pd.v2}, Ep);
+      note_nonfinite(g, inbox && !(finite(v.x) && finite(v.y) && finite(v.z)));
       T n0, n1, n2;
       int pcell;
       if constexpr (sizeof(T) == 4) {
@@ -1324,6 +1329,7 @@ __global__ void __launch_bounds__(NW * 64) k_diag_tiled(Grid g, TArgs<T> args, i
     }
     const int gx = wrap_once(x0 + nx_, g.nx), gy = wrap_once(y0 + ny_, g.ny), gz = wrap_once(z0 + nz_, g.nz);
     const int64_t gn = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
+    note_nonfinite(g, !finite(sum));
     if (sum != T(0)) unsafeAtomicAdd(diag_target(rho, Jd, P, nn, v, gn), sum);
   }
 }
@@ -1366,6 +1372,7 @@ __global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
       const Vec3<T> Ep = gather(args.Emove, g.nn, W, nd);
       const Vec3<T> Bp = gather(args.Bmove, g.nn, W, nd);
       const Vec3<T> v = advance_velocity(Bp, sp.beta, Vec3<T>{ul.vel[0][i], ul.vel[1][i], ul.vel[2][i]}, Ep);
+      note_nonfinite(g, !(finite(v.x) && finite(v.y) && finite(v.z)));
       T n0, n1, n2;
       int ncell;
       if constexpr (sizeof(T) == 4) {
@@ -1535,10 +1542,6 @@ struct StrayWs {
   int* rsums;
 };
 
-// regrouping arrays: [species][cell] for up to kMaxTiledSpecies species, and
-// the sums of a scan over them
-constexpr size_t kRsums = 1056;
-
 
 StrayWs carve(const Grid& g, int64_t cap, size_t esz, void* ws) {
   char* w = (char*)ws;
@@ -1575,7 +1578,7 @@ StrayWs carve(const Grid& g, int64_t cap, size_t esz, void* ws) {
   s.start = (int*)w;
   w += align256(sizeof(int) * (size_t)(g.nn + 1));
   s.scan_sums = (int*)w;
-  w += align256(sizeof(int) * (size_t)((g.nn + 1023) / 1024 + 1));
+  w += align256(sizeof(int) * (size_t)scan_sums_ints(g.nn));
   s.stay = (int*)w;
   w += align256(sizeof(int) * kMaxTiledSpecies * (size_t)g.nn);
   s.scount = (int*)w;
@@ -1726,15 +1729,14 @@ hipError_t launch_diagnostics_tiled(const Grid& g, bool f32, const SpeciesArgs* 
   return run_diag<double, 4, 4, 2, 4>(g, sp, ns, rho, Jd, P, zero, st);
 }
 
-int64_t regroup_max_entries() { return (int64_t)1024 * 1024; }   // the scan's limit: 1024 tiles of 1024
-
 size_t tiled_workspace_bytes(const Grid& g, int64_t np_total, bool f32) {
-  const int64_t nscan = (g.nn + 1023) / 1024 + 1;
   const size_t esz = f32 ? 4 : 8;
   return 768 + 6 * align256(sizeof(int) * (size_t)np_total) + 14 * align256(esz * (size_t)np_total) +
          align256(sizeof(int) * (size_t)g.nn) + align256(sizeof(int) * (size_t)(g.nn + 1)) +
-         align256(sizeof(int) * (size_t)nscan) + 2 * align256(sizeof(int) * kMaxTiledSpecies * (size_t)g.nn) +
-         align256(sizeof(int) * (kMaxTiledSpecies * (size_t)g.nn + 1)) + sizeof(int) * kRsums;
+         align256(sizeof(int) * (size_t)scan_sums_ints(g.nn)) +
+         2 * align256(sizeof(int) * kMaxTiledSpecies * (size_t)g.nn) +
+         align256(sizeof(int) * (kMaxTiledSpecies * (size_t)g.nn + 1)) +
+         sizeof(int) * (size_t)scan_sums_ints(kMaxTiledSpecies * g.nn);
 }
 
 bool tiled_species_ok(const SpeciesArgs* sp, int ns) {
@@ -1758,7 +1760,6 @@ hipError_t launch_deposit_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, 
 hipError_t launch_move_deposit_regroup(const Grid& g, bool f32, const SpeciesArgs* sp, const SpeciesArgs* dst, int ns,
                                        const void* E, const void* B, const void* Bnext, void* J, void* M, double* ke,
                                        void* ws, hipStream_t st) {
-  if ((int64_t)ns * g.nn > regroup_max_entries()) return hipErrorInvalidValue;
   if (g.nz == 1) {
     if (f32) return run_T<float, 8, 4, 1, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st, dst);
     return run_T<double, 8, 4, 1, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st, dst);

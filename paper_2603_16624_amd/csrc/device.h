@@ -54,7 +54,20 @@ struct Grid {
   FastDiv div_xy;    // by nx * ny
   double pdt[3];     // position push time step per dimension: dt, or 0 along a
                      // dimension of one cell (reduced runs keep positions there)
+  int* nonfinite;    // the device's non-finite flag (set, never cleared, by kernels)
 };
+
+// true unless x is a NaN or an infinity
+template <typename T>
+__device__ __forceinline__ bool finite(T x) {
+  return __builtin_isfinite(x);
+}
+
+// Records that a kernel produced a non-finite value (a vector atomic on the
+// flag; lanes without one do nothing).
+__device__ __forceinline__ void note_nonfinite(const Grid& g, bool bad) {
+  if (bad && g.nonfinite) atomicOr(g.nonfinite, 1);
+}
 
 template <typename T> struct Vec3 { T x, y, z; };
 

@@ -283,6 +283,12 @@ __global__ void __launch_bounds__(kBlock) k_scale_copy(int64_t n, double a, cons
   if (i < n) y[i] = a * x[i];
 }
 
+// the non-finite flag, read and cleared in stream order
+__global__ void k_take_flag(int* __restrict__ flag, int32_t* __restrict__ out) {
+  out[0] = flag[0];
+  flag[0] = 0;
+}
+
 __global__ void __launch_bounds__(kBlock) k_zero(uint32_t* __restrict__ p, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -360,6 +366,11 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
   } else {
     hipLaunchKernelGGL(k_zero, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, st, (uint32_t*)p, n);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_take_flag(int* flag, int32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_take_flag, dim3(1), dim3(1), 0, st, flag, out);
   return hipGetLastError();
 }
 

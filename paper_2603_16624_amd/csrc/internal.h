@@ -46,12 +46,13 @@ hipError_t launch_move_deposit(const Grid& g, bool f32, const SpeciesArgs* sp, i
                                hipStream_t st);
 // Fused mover + deposit that also regroups: each species' particles are
 // written to dst[s] in cell order (the deposit's order) and dst[s].cell_start
-// receives the ranges. Needs nspecies * cells <= regroup_max_entries().
+// receives the ranges.
 hipError_t launch_move_deposit_regroup(const Grid& g, bool f32, const SpeciesArgs* sp, const SpeciesArgs* dst, int ns,
                                        const void* E, const void* B, const void* Bnext, void* J, void* M, double* ke,
                                        void* ws, hipStream_t st);
-int64_t regroup_max_entries();
-// exclusive scan of n ints into out[0..n], out[n] = total; sums: >= n/1024 + 2 ints
+// exclusive scan of n < 2^31 ints into out[0..n], out[n] = total; sums:
+// scratch of scan_sums_ints(n) ints
+int64_t scan_sums_ints(int64_t n);
 hipError_t launch_exclusive_scan(const int* in, int64_t n, int* out, int* sums, hipStream_t st);
 
 size_t sort_workspace_bytes(const Grid& g, int64_t np);
@@ -63,6 +64,8 @@ hipError_t launch_mass_apply(const Grid& g, bool f32, const void* M, const doubl
 hipError_t launch_centres_to_nodes(const Grid& g, const double* BC, double* BN, float* BN32, hipStream_t st);
 hipError_t launch_to_f32(int64_t n, const double* src, float* dst, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+// *out = *flag, then *flag = 0 (one thread, on the stream)
+hipError_t launch_take_flag(int* flag, int32_t* out, hipStream_t st);
 
 // field-solve building blocks (FP64)
 hipError_t launch_curl_C(const Grid& g, const double* E, double* out, hipStream_t st);
@@ -89,6 +92,6 @@ hipError_t launch_sumsq(const double* x, int64_t n, double scale, double* partia
 
 hipError_t launch_backward(const Grid& g, bool f32, const SpeciesArgs& sp, const void* E, const void* B,
                            const void* gJ, const void* gM, void* const gpos[3], void* const gvel[3], void* gE,
-                           void* gB, bool through_mover, hipStream_t st);
+                           void* gB, bool through_mover, bool offset_grad, hipStream_t st);
 
 }  // namespace ecsim

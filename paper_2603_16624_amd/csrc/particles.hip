@@ -60,6 +60,7 @@ __global__ void __launch_bounds__(kBlock) k_move(Grid g, int np, T* __restrict__
     Vec3<T> Ep = gather(E, g.nn, W, nd);
     Vec3<T> Bp = gather(B, g.nn, W, nd);
     Vec3<T> vn = advance_velocity(Bp, beta, Vec3<T>{v0[p], v1[p], v2[p]}, Ep);
+    note_nonfinite(g, !(finite(vn.x) && finite(vn.y) && finite(vn.z)));
     v0[p] = vn.x;
     v1[p] = vn.y;
     v2[p] = vn.z;
@@ -115,6 +116,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_atomic(Grid g, int np, const
   const T cj = qp / V;
   const T cm = (qp * beta) / V;
   const int64_t nn = g.nn;
+  note_nonfinite(g, !(finite(vh.x) && finite(vh.y) && finite(vh.z) && finite(cj) && finite(cm) && finite(W[0]) &&
+                      finite(W[7])));
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     T w = cj * W[c];
@@ -158,6 +161,7 @@ __global__ void __launch_bounds__(kBlock) k_diag_atomic(Grid g, int np, const T*
   const T vx = v0[p], vy = v1[p], vz = v2[p];
   const T f[10] = {c, c * vx, c * vy, c * vz, (c * vx) * vx, (c * vx) * vy, (c * vx) * vz,
                    (c * vy) * vy, (c * vy) * vz, (c * vz) * vz};
+  note_nonfinite(g, !(finite(f[4]) && finite(f[7]) && finite(f[9]) && finite(W[0]) && finite(W[7])));
   const int64_t nn = g.nn;
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
@@ -269,11 +273,14 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_sums(int* __restrict__ sums
   if (threadIdx.x == 0) *total = t;
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_scan_add(int* __restrict__ out, int n, const int* __restrict__ sums) {
+__global__ void __launch_bounds__(kScanBlock) k_scan_add(int* __restrict__ out, int n, const int* __restrict__ sums,
+                                                         const int* __restrict__ total_src) {
   int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   int add = sums[blockIdx.x];
   for (int i = 0; i < kScanItems; ++i)
     if (base + i < n) out[base + i] += add;
+  // a scan over more than one level of tiles: the total comes from the level above
+  if (total_src && blockIdx.x == 0 && threadIdx.x == 0) out[n] = *total_src;
 }
 
 template <typename T, bool CELL>
@@ -391,15 +398,40 @@ size_t sort_workspace_bytes(const Grid& g, int64_t np) {
   int64_t nc = g.nn;
   int64_t ntiles = (nc + kScanTile - 1) / kScanTile;
   return align256(sizeof(int) * (size_t)np) * 2 + align256(sizeof(int) * (size_t)nc) +
-         align256(sizeof(int) * (size_t)(ntiles + 1));
+         align256(sizeof(int) * (size_t)scan_sums_ints(nc));
+}
+
+// Scratch of the scan: one sum per tile at each level above the first (a
+// level's sums are scanned, recursively, into the space after them).
+int64_t scan_sums_ints(int64_t n) {
+  int64_t total = 2;
+  for (int64_t m = (n + kScanTile - 1) / kScanTile; ; m = (m + kScanTile - 1) / kScanTile) {
+    total += 2 * (m + 1);
+    if (m <= kScanTile) break;
+  }
+  return total;
 }
 
 hipError_t launch_exclusive_scan(const int* in, int64_t n, int* out, int* sums, hipStream_t st) {
-  const int ntiles = (int)((n + kScanTile - 1) / kScanTile);
-  if (ntiles > kScanTile) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kScanBlock), 0, st, in, (int)n, out, sums);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, sums, ntiles, out + n);
-  hipLaunchKernelGGL(k_scan_add, dim3(ntiles), dim3(kScanBlock), 0, st, out, (int)n, sums);
+  if (n < 0 || n >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  if (ntiles <= kScanTile) {
+    const unsigned nb = (unsigned)(ntiles > 0 ? ntiles : 1);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(kScanBlock), 0, st, in, (int)n, out, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, sums, (int)ntiles, out + n);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanBlock), 0, st, out, (int)n, (const int*)sums,
+                       (const int*)nullptr);
+    return hipGetLastError();
+  }
+  // more tiles than one block scans: the tile sums are scanned recursively
+  // into scan (ntiles + 1 values, the last one the total)
+  int* scan = sums + ntiles + 1;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanBlock), 0, st, in, (int)n, out, sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_exclusive_scan(sums, ntiles, scan, scan + ntiles + 1, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)ntiles), dim3(kScanBlock), 0, st, out, (int)n, (const int*)scan,
+                     (const int*)(scan + ntiles));
   return hipGetLastError();
 }
 

@@ -18,9 +18,9 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libecsim.so")
 
-OK, EINVAL, EHIP, EWORKSPACE, ENOCONV = 0, -1, -2, -3, -5
+OK, EINVAL, EHIP, EWORKSPACE, ENONFINITE, ENOCONV = 0, -1, -2, -3, -4, -5
 F64, F32 = 0, 1
-ACCUMULATE, SORTED, BWD_THROUGH_MOVER = 1, 2, 8
+ACCUMULATE, SORTED, BWD_THROUGH_MOVER, BWD_OFFSET_GRAD = 1, 2, 8, 16
 ENERGY_WS_BYTES = 2048
 
 
@@ -74,6 +74,8 @@ def lib():
             "ecsim_field_solve": [P, ctypes.c_int32, P, P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                   P, P, P, P, ctypes.c_size_t, P, P, P],
             "ecsim_field_energy": [P, P, P, P, ctypes.c_size_t, P],
+            "ecsim_check_finite": [P],
+            "ecsim_nonfinite_read": [P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -87,7 +89,8 @@ EXPORTED = ["ecsim_last_error", "ecsim_version", "ecsim_workspace_size", "ecsim_
             "ecsim_move_moments", "ecsim_move_moments_regroup", "ecsim_diagnostics",
             "ecsim_diagnostics_workspace_size",
             "ecsim_mass_apply", "ecsim_moments_backward", "ecsim_sort", "ecsim_centres_to_nodes", "ecsim_to_f32",
-            "ecsim_solve_workspace_size", "ecsim_field_solve", "ecsim_field_energy"]
+            "ecsim_solve_workspace_size", "ecsim_field_solve", "ecsim_field_energy", "ecsim_check_finite",
+            "ecsim_nonfinite_read"]
 
 
 def _check(status: int):
@@ -301,13 +304,14 @@ def mass_apply(grid: Grid, M: torch.Tensor, x: torch.Tensor, y: torch.Tensor, a:
 
 def moments_backward(grid: Grid, sp: Species, E: Optional[torch.Tensor], B: torch.Tensor, gJ: torch.Tensor,
                      gM: torch.Tensor, gpos: torch.Tensor, gvel: torch.Tensor, gE: Optional[torch.Tensor],
-                     gB: torch.Tensor, through_mover: bool = True, stream=None):
-    """Adjoint of (mover ->) moments; gpos, gvel (3, np) overwritten, gE, gB (3, Nn) accumulated."""
+                     gB: torch.Tensor, through_mover: bool = True, offset_grad: bool = False, stream=None):
+    """Adjoint of (mover ->) moments; gpos, gvel (3, np) overwritten, gE, gB (3, Nn) accumulated.
+    offset_grad (FP32 particles): gpos with respect to the in-cell offsets instead of the positions."""
     esz = gpos.element_size()
     n = sp.np
     gp = (ctypes.c_void_p * 3)(*[gpos.data_ptr() + d * n * esz if n else None for d in range(3)])
     gv = (ctypes.c_void_p * 3)(*[gvel.data_ptr() + d * n * esz if n else None for d in range(3)])
-    flags = BWD_THROUGH_MOVER if through_mover else 0
+    flags = (BWD_THROUGH_MOVER if through_mover else 0) | (BWD_OFFSET_GRAD if offset_grad else 0)
     c = sp.c()
     _check(lib().ecsim_moments_backward(ctypes.byref(grid.c()), ctypes.byref(c), _ptr(E), _ptr(B), _ptr(gJ),
                                         _ptr(gM), gp, gv, _ptr(gE), _ptr(gB), flags, _stream(stream)))
@@ -359,6 +363,17 @@ def field_energy(grid: Grid, F: torch.Tensor, out: torch.Tensor, ws: Optional[to
         ws = torch.empty(ENERGY_WS_BYTES, dtype=torch.uint8, device=F.device)
     _check(lib().ecsim_field_energy(ctypes.byref(grid.c()), _ptr(F), _ptr(out), _ptr(ws), ws.numel(),
                                     _stream(stream)))
+
+
+def check_finite(stream=None):
+    """Synchronous: raises EcsimError (status ENONFINITE) if a kernel produced a NaN or an
+    infinity on this device since the last check; clears the flag."""
+    _check(lib().ecsim_check_finite(_stream(stream)))
+
+
+def nonfinite_read(flag_out: torch.Tensor, stream=None):
+    """Asynchronous: the device flag (0 or 1) into the int32 device tensor flag_out, then cleared."""
+    _check(lib().ecsim_nonfinite_read(_ptr(flag_out), _stream(stream)))
 
 
 # ----------------------------------------------------------------------------

@@ -232,8 +232,51 @@ def test_move_moments_regroup_validation(E):
     d.cell_start = ctypes.c_void_p(0x5000)                                    # aliases the source ranges
     assert call((E._Particles * 1)(d)) == E.EINVAL
     assert call((E._Particles * 1)(good()), ws=None, wsb=0) == E.EWORKSPACE
-    # species x cells above the scan's limit
-    big = E.Grid((128, 128, 65), (0.5,) * 3, 0.1).c()   # 1,064,960 cells: every call here fails before a launch
-    assert L.ecsim_move_moments_regroup(ctypes.byref(big), src, (E._Particles * 1)(good()), 1, fake, fake, fake,
+    # species x cells beyond the int32 ranges
+    big = E.Grid((1290, 1290, 1290), (0.5,) * 3, 0.1).c()   # 2,146,689,000 cells, 4 species: > 2^31 entries
+    src4 = (E._Particles * 4)(*[gp(_particles(E, prec=E.F32, cell=True, ptr=0x1000 + 0x100 * i), 0x5000 + i)
+                                for i in range(4)])
+    dst4 = (E._Particles * 4)(*[gp(_particles(E, prec=E.F32, cell=True, ptr=0x9000 + 0x100 * i), 0x6000 + i)
+                                for i in range(4)])
+    assert L.ecsim_move_moments_regroup(ctypes.byref(big), src4, dst4, 4, fake, fake, fake,
                                         fake, fake, None, fake, 1 << 40, 0, None) == E.EINVAL
     assert b"exceeds" in L.ecsim_last_error()
+
+
+def test_sorted_species_limits_are_errors(E):
+    """With ECSIM_SORTED more than 4 species is an error, not a silent switch to the any-order deposit."""
+    L = E.lib()
+    g = _grid(E)
+    fake = ctypes.c_void_p(0x1000)
+    sp = []
+    for i in range(5):
+        p = _particles(E, ptr=0x1000 + 0x100 * i)
+        p.cell_start = 0x8000 + 0x100 * i
+        sp.append(p)
+    arr = (E._Particles * 5)(*sp)
+    assert L.ecsim_moments(ctypes.byref(g), arr, 5, fake, fake, fake, fake, 1 << 40, E.SORTED, None) == E.EINVAL
+    assert b"at most 4 species" in L.ecsim_last_error()
+    assert L.ecsim_diagnostics(ctypes.byref(g), arr, 5, fake, fake, fake, fake, 1 << 40, E.SORTED, None) == E.EINVAL
+    assert b"at most 4 species" in L.ecsim_last_error()
+
+
+def test_nonfinite_api_validation(E):
+    """The non-finite status code and the checks' host-side validation."""
+    L = E.lib()
+    assert E.ENONFINITE == -4
+    txt = open(HEADER).read()
+    assert "ECSIM_ENONFINITE = -4" in txt
+    assert L.ecsim_nonfinite_read(None, None) == E.EINVAL
+    assert b"flag_out" in L.ecsim_last_error()
+
+
+def test_offset_gradient_flag_needs_fp32(E):
+    L = E.lib()
+    g = _grid(E)
+    fake = ctypes.c_void_p(0x1000)
+    gp = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
+    p = _particles(E)   # FP64
+    st = L.ecsim_moments_backward(ctypes.byref(g), ctypes.byref(p), fake, fake, fake, fake, gp, gp, fake, fake,
+                                  E.BWD_THROUGH_MOVER | E.BWD_OFFSET_GRAD, None)
+    assert st == E.EINVAL
+    assert b"OFFSET_GRAD" in L.ecsim_last_error()
