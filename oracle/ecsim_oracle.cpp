@@ -28,6 +28,10 @@
 #include <cstring>
 #include <vector>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
@@ -390,6 +394,57 @@ int gmres(FieldOp& op, const double* b, double* x, int64_t n, double tol, int m,
   return it;
 }
 
+// Eqs. 1 and 3 for one particle at position xp with velocity vp: J += its
+// current q vhat W_N / V, M27 += its 64 corner-pair blocks.
+void deposit_particle(const Grid& g, double beta, double qp, const double xp[3], const double vp[3],
+                      const double* B_node, double* J, double* M27) {
+  const int64_t nn = g.nn();
+  const double V = g.V();
+  Stencil<double> s = stencil(g, xp);
+  double Bp[3];
+  gather(g, s, B_node, Bp);
+  double a[9];
+  rotation(Bp, beta, a);
+  double vhat[3];
+  matvec(a, vp, vhat);
+  // Eq. 1: J_N += q_p vhat_p W_pN / V_N
+  for (int az = 0; az < 2; ++az)
+    for (int ay = 0; ay < 2; ++ay)
+      for (int ax = 0; ax < 2; ++ax) {
+        double w = corner_weight(s, ax, ay, az);
+        int64_t nd = corner_node(g, s, ax, ay, az);
+        for (int c = 0; c < 3; ++c) J[c * nn + nd] += qp * vhat[c] * w / V;
+      }
+  // Eq. 3: M_{N N'} += beta_p q_p alpha_p W_pN' W_pN / V_N for every ordered
+  // pair of corners (a, b); N = node(a), N' = node(b), offset o = b - a.
+  for (int az = 0; az < 2; ++az)
+    for (int ay = 0; ay < 2; ++ay)
+      for (int ax = 0; ax < 2; ++ax)
+        for (int bz = 0; bz < 2; ++bz)
+          for (int by = 0; by < 2; ++by)
+            for (int bx = 0; bx < 2; ++bx) {
+              double wa = corner_weight(s, ax, ay, az);
+              double wb = corner_weight(s, bx, by, bz);
+              int64_t nd = corner_node(g, s, ax, ay, az);
+              int k = off27(bx - ax, by - ay, bz - az);
+              for (int ij = 0; ij < 9; ++ij)
+                M27[((int64_t)k * 9 + ij) * nn + nd] += beta * qp * a[ij] * wb * wa / V;
+            }
+}
+
+// Eqs. 4, 5 and 8 for particle p of [3][np] arrays x, v, in place.
+void move_particle(const Grid& g, double beta, int64_t np, int64_t p, double* x, double* v, const double* E_node,
+                   const double* B_node) {
+  double xp[3] = {x[p], x[np + p], x[2 * np + p]};
+  double vp[3] = {v[p], v[np + p], v[2 * np + p]};
+  Stencil<double> s = stencil(g, xp);
+  double Ep[3], Bp[3];
+  gather(g, s, E_node, Ep);
+  gather(g, s, B_node, Bp);
+  move_one(g, beta, xp, vp, Ep, Bp);
+  for (int c = 0; c < 3; ++c) { x[c * np + p] = xp[c]; v[c * np + p] = vp[c]; }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -460,43 +515,12 @@ void oracle_moments(const int32_t* n, const double* h, double dt, int64_t np, co
                     const double* v, const double* q, double q_const, double qom,
                     const double* B_node, double* J, double* M27) {
   Grid g = make_grid(n, h, dt);
-  const int64_t nn = g.nn();
-  const double V = g.V();
   const double beta = qom * dt / 2.0;
   for (int64_t p = 0; p < np; ++p) {
     const double qp = q ? q[p] : q_const;
     double xp[3] = {x[p], x[np + p], x[2 * np + p]};
     double vp[3] = {v[p], v[np + p], v[2 * np + p]};
-    Stencil<double> s = stencil(g, xp);
-    double Bp[3];
-    gather(g, s, B_node, Bp);
-    double a[9];
-    rotation(Bp, beta, a);
-    double vhat[3];
-    matvec(a, vp, vhat);
-    // Eq. 1: J_N += q_p vhat_p W_pN / V_N
-    for (int az = 0; az < 2; ++az)
-      for (int ay = 0; ay < 2; ++ay)
-        for (int ax = 0; ax < 2; ++ax) {
-          double w = corner_weight(s, ax, ay, az);
-          int64_t nd = corner_node(g, s, ax, ay, az);
-          for (int c = 0; c < 3; ++c) J[c * nn + nd] += qp * vhat[c] * w / V;
-        }
-    // Eq. 3: M_{N N'} += beta_p q_p alpha_p W_pN' W_pN / V_N for every ordered
-    // pair of corners (a, b); N = node(a), N' = node(b), offset o = b - a.
-    for (int az = 0; az < 2; ++az)
-      for (int ay = 0; ay < 2; ++ay)
-        for (int ax = 0; ax < 2; ++ax)
-          for (int bz = 0; bz < 2; ++bz)
-            for (int by = 0; by < 2; ++by)
-              for (int bx = 0; bx < 2; ++bx) {
-                double wa = corner_weight(s, ax, ay, az);
-                double wb = corner_weight(s, bx, by, bz);
-                int64_t nd = corner_node(g, s, ax, ay, az);
-                int k = off27(bx - ax, by - ay, bz - az);
-                for (int ij = 0; ij < 9; ++ij)
-                  M27[((int64_t)k * 9 + ij) * nn + nd] += beta * qp * a[ij] * wb * wa / V;
-              }
+    deposit_particle(g, beta, qp, xp, vp, B_node, J, M27);
   }
 }
 
@@ -529,16 +553,60 @@ void oracle_move(const int32_t* n, const double* h, double dt, int64_t np, doubl
                  double qom, const double* E_node, const double* B_node) {
   Grid g = make_grid(n, h, dt);
   const double beta = qom * dt / 2.0;
-  for (int64_t p = 0; p < np; ++p) {
-    double xp[3] = {x[p], x[np + p], x[2 * np + p]};
-    double vp[3] = {v[p], v[np + p], v[2 * np + p]};
-    Stencil<double> s = stencil(g, xp);
-    double Ep[3], Bp[3];
-    gather(g, s, E_node, Ep);
-    gather(g, s, B_node, Bp);
-    move_one(g, beta, xp, vp, Ep, Bp);
-    for (int c = 0; c < 3; ++c) { x[c * np + p] = xp[c]; v[c * np + p] = vp[c]; }
+  for (int64_t p = 0; p < np; ++p) move_particle(g, beta, np, p, x, v, E_node, B_node);
+}
+
+// The mover and then the moments at the moved positions (the particle pass
+// of one step, as timed for the CPU baseline), over `threads` threads: each
+// thread moves a contiguous share of the particles in place and deposits them
+// into its own zeroed J and M27; the thread grids are then added into J and
+// M27 (+=) in thread order, so the result does not depend on scheduling.
+// threads = 1 runs the same code on one thread. Returns the threads used.
+int oracle_move_moments_threads(const int32_t* n, const double* h, double dt, int64_t np, double* x, double* v,
+                                const double* q, double q_const, double qom, const double* E_node,
+                                const double* B_node, const double* B_next, double* J, double* M27,
+                                int threads) {
+  Grid g = make_grid(n, h, dt);
+  const int64_t nn = g.nn();
+  const double beta = qom * dt / 2.0;
+  if (threads < 1) threads = 1;
+  std::vector<std::vector<double>> Jt(threads), Mt(threads);
+  int used = 1;
+#pragma omp parallel num_threads(threads)
+  {
+    int t = 0, nt = 1;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+    nt = omp_get_num_threads();
+#endif
+#pragma omp single
+    used = nt;
+    Jt[t].assign((size_t)3 * nn, 0.0);
+    Mt[t].assign((size_t)27 * 9 * nn, 0.0);
+    const int64_t p0 = np * t / nt, p1 = np * (t + 1) / nt;
+    for (int64_t p = p0; p < p1; ++p) {
+      move_particle(g, beta, np, p, x, v, E_node, B_node);
+      const double qp = q ? q[p] : q_const;
+      double xp[3] = {x[p], x[np + p], x[2 * np + p]};
+      double vp[3] = {v[p], v[np + p], v[2 * np + p]};
+      deposit_particle(g, beta, qp, xp, vp, B_next, Jt[t].data(), Mt[t].data());
+    }
+#pragma omp barrier
+    // fixed-order reduction: every entry sums the thread grids in order 0..nt-1
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < 27 * 9 * nn; ++i) {
+      double s = M27[i];
+      for (int u = 0; u < nt; ++u) s += Mt[u][i];
+      M27[i] = s;
+    }
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < 3 * nn; ++i) {
+      double s = J[i];
+      for (int u = 0; u < nt; ++u) s += Jt[u][i];
+      J[i] = s;
+    }
   }
+  return used;
 }
 
 void oracle_curl_C(const int32_t* n, const double* h, const double* E, double* out) {

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ecsim_oracle.cpp")
 LIB = os.path.join(HERE, "liboracle.so")
 
-CXXFLAGS = ["-O2", "-std=c++17", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared"]
+CXXFLAGS = ["-O2", "-std=c++17", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared"]
 
 
 def build(force: bool = False) -> str:
@@ -58,6 +58,8 @@ def _declare(L):
     L.oracle_canonical14.argtypes = [_p]
     L.oracle_mass_apply27.argtypes = [_p, _p, _p, _p]
     L.oracle_move.argtypes = [_p, _p, _d, _i64, _p, _p, _d, _p, _p]
+    L.oracle_move_moments_threads.argtypes = [_p, _p, _d, _i64, _p, _p, _p, _d, _d, _p, _p, _p, _p, _p, _i32]
+    L.oracle_move_moments_threads.restype = _i32
     L.oracle_curl_C.argtypes = [_p, _p, _p, _p]
     L.oracle_curl_N.argtypes = [_p, _p, _p, _p]
     L.oracle_centres_to_nodes.argtypes = [_p, _p, _p]
@@ -184,6 +186,23 @@ def move(n, h, dt, x, v, qom, E_node, B_node):
     lib().oracle_move(_ptr(ni), _ptr(hh), float(dt), x.shape[1], _ptr(x), _ptr(v), float(qom),
                       _ptr(_f64(E_node)), _ptr(_f64(B_node)))
     return x, v
+
+
+def move_moments_threads(n, h, dt, x, v, q, qom, E_node, B_node, B_next, J=None, M27=None, threads=1):
+    """The particle pass of one step on `threads` host threads: the mover (E_node, B_node), then the
+    moments at the new positions with B_next accumulated into J and M27 (thread-private grids added
+    in thread order). Returns (x', v', J, M27, threads used); x and v are not modified."""
+    ni, hh = _grid(n, h)
+    nn = int(np.prod(n))
+    J = np.zeros((3, nn)) if J is None else J
+    M27 = np.zeros((27, 9, nn)) if M27 is None else M27
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    qa, qc = _q(q)
+    used = lib().oracle_move_moments_threads(_ptr(ni), _ptr(hh), float(dt), x.shape[1], _ptr(x), _ptr(v),
+                                             _ptr(qa), qc, float(qom), _ptr(_f64(E_node)), _ptr(_f64(B_node)),
+                                             _ptr(_f64(B_next)), _ptr(J), _ptr(M27), int(threads))
+    return x, v, J, M27, int(used)
 
 
 def curl_C(n, h, E):

@@ -533,3 +533,28 @@ def test_dual_gradient_matches_central_differences(oracle, inputs):
                 else:
                     fd = (lp(s.x, s.v, E, up) - lp(s.x, s.v, E, dn)).sum() / (2 * eps)
                 assert abs(gref[c, node] - fd) <= 1e-6 * max(np.max(np.abs(gref)), 1e-30)
+
+
+def test_threaded_particle_pass_matches_serial(oracle, inputs):
+    """The host-threaded particle pass (the CPU baseline's form: mover, then the
+    moments at the moved positions, thread-private grids added in thread
+    order) is the serial mover followed by the serial moments: positions and
+    velocities bit for bit, J and M to rounding of the changed summation
+    order, and bit for bit on one thread."""
+    p = inputs.uniform_plasma(7, (6, 5, 4), 9)
+    rng = np.random.default_rng(11)
+    En = 1e-2 * rng.standard_normal((3, p.nn))
+    BN = np.array([[0.02], [0.0], [0.2]]) + 0.05 * rng.standard_normal((3, p.nn))
+    Bn = BN + 0.01 * rng.standard_normal((3, p.nn))
+    for s in p.species:
+        x1, v1 = oracle.move(p.n, p.h, p.dt, s.x, s.v, s.qom, En, BN)
+        J, M27 = oracle.moments(p.n, p.h, p.dt, x1, v1, s.q, s.qom, Bn)
+        for th in (1, 3, 4):
+            x2, v2, J2, M2, used = oracle.move_moments_threads(p.n, p.h, p.dt, s.x, s.v, s.q, s.qom, En, BN, Bn,
+                                                               threads=th)
+            assert used == th
+            assert np.array_equal(x1, x2) and np.array_equal(v1, v2)
+            if th == 1:
+                assert np.array_equal(J, J2) and np.array_equal(M27, M2)
+            assert relerr(J2, J) < 1e-14
+            assert relerr(M2, M27) < 1e-14
