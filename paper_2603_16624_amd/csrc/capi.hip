@@ -2,6 +2,7 @@
 // launchers on the caller's stream, and the host driver of the FP64 GMRES
 // field solve (Eqs. 6-7). Declarations and the contract of every entry point
 // are in include/ecsim.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -468,9 +469,12 @@ ecsim_status ecsim_solve_workspace_size(const ecsim_grid* grid, int32_t restart,
   if (restart < 1 || restart > kMaxRestart) return fail(ECSIM_EINVAL, "restart = %d not in 1..%d", restart, kMaxRestart);
   if (!bytes) return fail(ECSIM_EINVAL, "bytes is NULL");
   const size_t vec = align256(sizeof(double) * 3 * (size_t)g.nn);
-  // V (m+1 vectors), w, r/b, cc (curl scratch), partials, small device scalars
-  *bytes = vec * (size_t)(restart + 1) + 3 * vec + align256(sizeof(double) * kDotBlocks * (restart + 2)) +
-           align256(sizeof(double) * 2 * (restart + 2));
+  const size_t m = (size_t)restart;
+  // V (m+1 vectors), w, r/b, cc (curl scratch), dot partials, and the
+  // device-side GMRES state: both Gram-Schmidt passes, norms, H, the
+  // rotations, g, the residual history, -y and the iteration state
+  *bytes = vec * (m + 1) + 3 * vec + align256(sizeof(double) * kDotBlocks * (m + 2)) +
+           align256(sizeof(double) * (m * m + 8 * m + 16));
   return ECSIM_OK;
 }
 
@@ -524,7 +528,18 @@ ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const voi
   w8 += vec;
   double* partial = (double*)w8;
   w8 += align256(sizeof(double) * kDotBlocks * (m + 2));
-  double* dsc = (double*)w8;   // device scalars: h column (m+1) + spare
+  // device-side state
+  double* d = (double*)w8;
+  double* h1 = d;                 // m + 1
+  double* h2 = h1 + (m + 1);      // m + 1
+  double* nrm = h2 + (m + 1);     // 4: |b|^2, |r|^2, |w|^2
+  double* H = nrm + 4;            // (m + 1) m
+  double* cs = H + (size_t)(m + 1) * m;
+  double* sn = cs + m;
+  double* gv = sn + m;            // m + 1
+  double* hist = gv + (m + 1);    // m
+  double* ny = hist + m;          // m
+  int* state = (int*)(ny + m);    // 2 ints
 
   hipStream_t st = (hipStream_t)stream;
   Solver S{g, m_prec == ECSIM_F32, M, st, cc, (kC * kTheta * g.dt) * (kC * kTheta * g.dt), 4.0 * kPi * kTheta * g.dt};
@@ -537,87 +552,97 @@ ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const voi
   // b = E^n - 4 pi theta dt J + c theta dt curl_N B_C^n
   HIPCK(launch_rhs(g, E_n, m_prec == ECSIM_F32, J, B_C_n, -4.0 * kPi * kTheta * g.dt, kC * kTheta * g.dt, bvec, st));
   HIPCK(hipMemcpyAsync(E_theta, E_n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  HIPCK(launch_dots(bvec, ld, 1, bvec, n, partial, nrm, st));
 
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), hcol(m + 1), h2(m + 1);
-  auto dot_host = [&](const double* Vb, int nv, const double* x, double* out_host) -> hipError_t {
-    hipError_t ee = launch_dots(Vb, ld, nv, x, n, partial, dsc, st);
-    if (ee != hipSuccess) return ee;
-    ee = hipMemcpyAsync(out_host, dsc, sizeof(double) * nv, hipMemcpyDeviceToHost, st);
-    if (ee != hipSuccess) return ee;
-    return hipStreamSynchronize(st);
-  };
-  double bnorm2 = 0.0;
-  HIPCK(dot_host(bvec, 1, bvec, &bnorm2));
-  if (!std::isfinite(bnorm2))
-    return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the right-hand side is not finite (J, E^n or B^n)");
-  const double bnorm = std::sqrt(bnorm2);
+  // Restarted GMRES(m) with classical Gram-Schmidt applied twice. Every
+  // Arnoldi step runs on the device (matrix apply, both projection passes,
+  // the norm, the new basis vector and the Givens update of H and g); the
+  // host only decides how many steps to launch before it next reads the
+  // residual history: two at the start of a cycle, then as many as the
+  // observed convergence rate predicts are needed, so that a cycle takes a
+  // few host reads instead of three per step. Steps launched past
+  // convergence change nothing (the Givens kernel freezes the state).
+  std::vector<double> hh((size_t)m);
+  int st2[2] = {0, 0};
+  double bnorm = 0.0;
   int it = 0;
   double rel = 0.0;
   bool converged = false;
-  if (bnorm == 0.0) {
-    HIPCK(launch_scale_copy(n, 0.0, E_n, E_theta, st));
-    converged = true;
-  }
-  while (!converged) {
-    // r = b - A x  (into V_0)
+  bool first = true;
+  while (true) {
+    // r = b - A x  (into V_0) and its norm; the first cycle also reads |b|
     HIPCK(S.apply(E_theta, w));
     HIPCK(hipMemcpyAsync(V, bvec, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     HIPCK(launch_axpby(n, -1.0, w, 1.0, V, st));
-    double beta2 = 0.0;
-    HIPCK(dot_host(V, 1, V, &beta2));
-    if (!std::isfinite(beta2))
+    HIPCK(launch_dots(V, ld, 1, V, n, partial, nrm + 1, st));
+    double nh[2] = {0.0, 0.0};
+    HIPCK(hipMemcpyAsync(nh, nrm, sizeof nh, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (first) {
+      if (!std::isfinite(nh[0]))
+        return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the right-hand side is not finite (J, E^n or B^n)");
+      bnorm = std::sqrt(nh[0]);
+      first = false;
+      if (bnorm == 0.0) {
+        HIPCK(launch_scale_copy(n, 0.0, E_n, E_theta, st));
+        converged = true;
+        break;
+      }
+    }
+    if (!std::isfinite(nh[1]))
       return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the residual is not finite (M or the iterate)");
-    double beta = std::sqrt(beta2);
+    const double beta = std::sqrt(nh[1]);
     rel = beta / bnorm;
     if (rel <= tol) { converged = true; break; }
     if (it >= maxit) break;
     HIPCK(launch_scale_copy(n, 1.0 / beta, V, V, st));
-    std::fill(gv.begin(), gv.end(), 0.0);
-    gv[0] = beta;
-    int j = 0;
-    for (; j < m && it < maxit;) {
-      double* Vj = V + (size_t)j * ld;
-      double* Vj1 = V + (size_t)(j + 1) * ld;
-      HIPCK(S.apply(Vj, w));
-      // classical Gram-Schmidt, twice (CGS2): all j+1 projections per pass
-      HIPCK(dot_host(V, j + 1, w, hcol.data()));
-      HIPCK(launch_sub_combo(V, ld, j + 1, hcol.data(), w, n, st));
-      HIPCK(dot_host(V, j + 1, w, h2.data()));
-      HIPCK(launch_sub_combo(V, ld, j + 1, h2.data(), w, n, st));
-      for (int i = 0; i <= j; ++i) hcol[i] += h2[i];
-      double hn2 = 0.0;
-      HIPCK(dot_host(w, 1, w, &hn2));
-      if (!std::isfinite(hn2))
-        return fail(ECSIM_ENONFINITE, "ecsim_field_solve: a Krylov vector is not finite (M is not finite)");
-      double hn = std::sqrt(hn2);
-      if (hn > 0.0) HIPCK(launch_scale_copy(n, 1.0 / hn, w, Vj1, st));
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
-      H[(size_t)(j + 1) * m + j] = hn;
-      for (int i = 0; i < j; ++i) {
-        double t = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
-        H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = t;
+    HIPCK(launch_gmres_start(m, beta, gv, state, st));
+    const double thresh = 0.5 * tol * bnorm;
+    int j = 0;          // steps launched in this cycle
+    int used = 0;       // steps that count (up to convergence)
+    int batch = 2;
+    bool done = false;
+    while (!done) {
+      const int nb = std::min(std::min(batch, m - j), maxit - it - j);
+      for (int s = j; s < j + nb; ++s) {
+        double* Vs = V + (size_t)s * ld;
+        double* Vs1 = V + (size_t)(s + 1) * ld;
+        HIPCK(S.apply(Vs, w));
+        HIPCK(launch_dots(V, ld, s + 1, w, n, partial, h1, st));
+        HIPCK(launch_sub_combo_dev(V, ld, s + 1, h1, w, n, st));
+        HIPCK(launch_dots(V, ld, s + 1, w, n, partial, h2, st));
+        HIPCK(launch_sub_combo_dev(V, ld, s + 1, h2, w, n, st));
+        HIPCK(launch_dots(w, ld, 1, w, n, partial, nrm + 2, st));
+        HIPCK(launch_normalize(w, nrm + 2, Vs1, n, st));
+        HIPCK(launch_givens(s, m, H, cs, sn, gv, h1, h2, nrm + 2, thresh, state, hist, st));
       }
-      double aa = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
-      double rr = std::hypot(aa, bb);
-      cs[j] = aa / rr;
-      sn[j] = bb / rr;
-      H[(size_t)j * m + j] = rr;
-      H[(size_t)(j + 1) * m + j] = 0.0;
-      gv[j + 1] = -sn[j] * gv[j];
-      gv[j] = cs[j] * gv[j];
-      ++j;
-      ++it;
-      if (std::fabs(gv[j]) <= 0.5 * tol * bnorm || hn == 0.0) break;
+      HIPCK(hipMemcpyAsync(hh.data() + j, hist + j, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+      HIPCK(hipMemcpyAsync(st2, state, sizeof st2, hipMemcpyDeviceToHost, st));
+      HIPCK(hipStreamSynchronize(st));
+      j += nb;
+      used = st2[1];
+      for (int s = j - nb; s < j; ++s)
+        if (!std::isfinite(hh[s]))
+          return fail(ECSIM_ENONFINITE, "ecsim_field_solve: a Krylov vector is not finite (M is not finite)");
+      done = st2[0] == 0 || j >= m || it + j >= maxit;
+      if (!done) {
+        // steps still needed at the rate of the last two: |g| falls by about
+        // hist[j-1] / hist[j-2] per step
+        int next = 1;
+        if (j >= 2 && hh[j - 1] > 0.0 && hh[j - 2] > hh[j - 1]) {
+          const double rate = hh[j - 1] / hh[j - 2];
+          const double k = std::log(thresh / hh[j - 1]) / std::log(rate);
+          next = k < 1.0 ? 1 : (k > (double)m ? m : (int)std::ceil(k));
+        }
+        batch = next;
+      }
     }
-    for (int i = j - 1; i >= 0; --i) {
-      double s = gv[i];
-      for (int k = i + 1; k < j; ++k) s -= H[(size_t)i * m + k] * y[k];
-      y[i] = s / H[(size_t)i * m + i];
+    it += used;
+    // x += V y, y from the j x j triangle (on the device)
+    if (used > 0) {
+      HIPCK(launch_backsolve(H, gv, m, used, ny, st));
+      HIPCK(launch_sub_combo_dev(V, ld, used, ny, E_theta, n, st));
     }
-    // x += V y  (as w -= V (-y))
-    for (int i = 0; i < j; ++i) y[i] = -y[i];
-    HIPCK(launch_sub_combo(V, ld, j, y.data(), E_theta, n, st));
   }
   // advance the fields: B_C^{n+theta} = B_C^n - c theta dt curl_C E^{n+theta}
   HIPCK(launch_curl_C(g, E_theta, cc, st));

@@ -271,6 +271,79 @@ __global__ void __launch_bounds__(kBlock) k_sub_combo(const double* __restrict__
   w[i] = s;
 }
 
+// w -= sum_v coef[v] V_v with the coefficients in device memory
+__global__ void __launch_bounds__(kBlock) k_sub_combo_dev(const double* __restrict__ V, int64_t ld, int nv,
+                                                          const double* __restrict__ coef, double* __restrict__ w,
+                                                          int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= n) return;
+  double s = w[i];
+  for (int v = 0; v < nv; ++v) s -= coef[v] * V[v * ld + i];
+  w[i] = s;
+}
+
+// out = w / sqrt(*nrm2) (zeros when the norm is zero: a Krylov breakdown)
+__global__ void __launch_bounds__(kBlock) k_normalize(const double* __restrict__ w, const double* __restrict__ nrm2,
+                                                      double* __restrict__ out, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double s = *nrm2;
+  out[i] = s > 0.0 ? w[i] / sqrt(s) : 0.0;
+}
+
+// One Arnoldi column on the device (one thread): H[:, j] from the two
+// Gram-Schmidt passes and the new vector's norm, the earlier Givens rotations
+// applied to it, a new rotation that zeroes H[j+1][j], and the rotated
+// right-hand side g. hist[j] = |g[j+1]|, the residual norm of the least-squares
+// problem after j + 1 steps. Once that norm is below thresh (or the Krylov
+// space broke down), state[0] = 0 and later calls leave everything as is, so
+// steps launched past convergence change nothing. state[1] = columns used.
+__global__ void k_givens(int j, int m, double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
+                         double* __restrict__ gv, const double* __restrict__ h1, const double* __restrict__ h2,
+                         const double* __restrict__ hn2, double thresh, int* __restrict__ state,
+                         double* __restrict__ hist) {
+  if (state[0] == 0) {
+    hist[j] = -1.0;
+    return;
+  }
+  const double hn = sqrt(*hn2 > 0.0 ? *hn2 : 0.0);
+  for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] = h1[i] + h2[i];
+  H[(int64_t)(j + 1) * m + j] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = H[(int64_t)i * m + j], b = H[(int64_t)(i + 1) * m + j];
+    H[(int64_t)i * m + j] = cs[i] * a + sn[i] * b;
+    H[(int64_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = H[(int64_t)j * m + j], b = H[(int64_t)(j + 1) * m + j];
+  const double rr = hypot(a, b);
+  cs[j] = rr > 0.0 ? a / rr : 1.0;
+  sn[j] = rr > 0.0 ? b / rr : 0.0;
+  H[(int64_t)j * m + j] = rr;
+  H[(int64_t)(j + 1) * m + j] = 0.0;
+  gv[j + 1] = -sn[j] * gv[j];
+  gv[j] = cs[j] * gv[j];
+  hist[j] = fabs(gv[j + 1]);
+  state[1] = j + 1;
+  if (hist[j] <= thresh || hn == 0.0) state[0] = 0;
+}
+
+// start of a restart cycle: g = (beta, 0, ...), one active iteration state
+__global__ void k_gmres_start(int m, double beta, double* __restrict__ gv, int* __restrict__ state) {
+  for (int i = 0; i <= m; ++i) gv[i] = i == 0 ? beta : 0.0;
+  state[0] = 1;
+  state[1] = 0;
+}
+
+// back substitution of the j x j triangle H y = g (one thread); writes -y
+__global__ void k_backsolve(const double* __restrict__ H, const double* __restrict__ gv, int m, int j,
+                            double* __restrict__ ny) {
+  for (int i = j - 1; i >= 0; --i) {
+    double s = gv[i];
+    for (int k = i + 1; k < j; ++k) s += H[(int64_t)i * m + k] * ny[k];   // ny[k] = -y[k]
+    ny[i] = -(s / H[(int64_t)i * m + i]);
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
                                                   double* __restrict__ y) {
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
@@ -387,6 +460,35 @@ hipError_t launch_sub_combo(const double* V, int64_t ld, int nv, const double* c
   Coefs c;
   for (int v = 0; v < nv; ++v) c.c[v] = coef_host[v];
   hipLaunchKernelGGL(k_sub_combo, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, st, V, ld, nv, c, w, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_combo_dev(const double* V, int64_t ld, int nv, const double* coef_dev, double* w, int64_t n,
+                                hipStream_t st) {
+  if (nv < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_sub_combo_dev, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, st, V, ld, nv, coef_dev, w, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(const double* w, const double* nrm2, double* out, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_normalize, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, st, w, nrm2, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_givens(int j, int m, double* H, double* cs, double* sn, double* gv, const double* h1,
+                         const double* h2, const double* hn2, double thresh, int* state, double* hist,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, st, j, m, H, cs, sn, gv, h1, h2, hn2, thresh, state, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_gmres_start(int m, double beta, double* gv, int* state, hipStream_t st) {
+  hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(1), 0, st, m, beta, gv, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_backsolve(const double* H, const double* gv, int m, int j, double* ny, hipStream_t st) {
+  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, st, H, gv, m, j, ny);
   return hipGetLastError();
 }
 

@@ -84,6 +84,18 @@ hipError_t launch_dots(const double* V, int64_t ld, int nv, const double* w, int
 constexpr int kMaxRestart = 120;
 hipError_t launch_sub_combo(const double* V, int64_t ld, int nv, const double* coef_host, double* w, int64_t n,
                             hipStream_t st);
+// w -= sum_v coef[v] V_v with device coefficients
+hipError_t launch_sub_combo_dev(const double* V, int64_t ld, int nv, const double* coef_dev, double* w, int64_t n,
+                                hipStream_t st);
+// out = w / sqrt(*nrm2)
+hipError_t launch_normalize(const double* w, const double* nrm2, double* out, int64_t n, hipStream_t st);
+// the device-side GMRES bookkeeping: one Arnoldi column with its Givens
+// rotation, the start of a restart cycle, the final back substitution
+hipError_t launch_givens(int j, int m, double* H, double* cs, double* sn, double* gv, const double* h1,
+                         const double* h2, const double* hn2, double thresh, int* state, double* hist,
+                         hipStream_t st);
+hipError_t launch_gmres_start(int m, double beta, double* gv, int* state, hipStream_t st);
+hipError_t launch_backsolve(const double* H, const double* gv, int m, int j, double* ny, hipStream_t st);
 // y = a x + b y
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
 hipError_t launch_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t st);
