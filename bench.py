@@ -208,32 +208,55 @@ def run_form(prec, args, plasma):
     return out
 
 
-def fixed_error(plasma, steps=5):
-    """FP32-form error against the FP64 path on the full workload, step by step.
+def fixed_error(plasma, steps=5, record=None):
+    """FP32-form error on the full workload, step by step, beside the FP64 path.
 
     Both forms start from the same state (the FP32 form is the FP64 state
     encoded as cell + offset) and run `steps` steps of the loop side by side
     (field solve, fused pass with the regrouping every 4 steps). After each
     step the relative max-norm differences of J-hat and M (the next step's
-    moments) and of E^{n+1} are recorded; the FP64 path itself agrees with the
-    FP64 oracle to 1e-12 (the oracle is too slow for 33.5M particles a step).
+    moments) and of E^{n+1} between the two runs are recorded: the free-running
+    divergence of the FP32 form from the FP64 one. With `record` (a list), the
+    FP32 run's inputs and outputs of every step are also kept on the host, for
+    the comparison with the FP64 oracle that the CPU-baseline leg makes.
     """
+    import numpy as np
     import torch
     from paper_2603_16624_amd import ecsim as E
     sims = {P: E.Simulation(plasma, prec=P, tol=1e-10, fused=True, regroup=True) for P in (E.F64, E.F32)}
     rel = lambda a, b: float((a.double() - b.double()).abs().max() / b.double().abs().max())
+    cpu = lambda t: t.detach().cpu().numpy()
     per_step = []
     for _ in range(steps):
+        s32 = sims[E.F32]
+        if record is not None and s32.primed:
+            pre = dict(species=[dict(cell=cpu(sp.cell), off=cpu(sp.pos), v=cpu(sp.vel),
+                                     q=None if sp.q is None else cpu(sp.q), q_const=sp.q_const, qom=sp.qom)
+                                for sp in s32.species],
+                       J=cpu(s32.J), M=cpu(s32.M), E=cpu(s32.E), BC=cpu(s32.BC))
         for sim in sims.values():
+            if record is not None and sim is s32 and not sim.primed:
+                sim.prime()
+                pre = dict(species=[dict(cell=cpu(sp.cell), off=cpu(sp.pos), v=cpu(sp.vel),
+                                         q=None if sp.q is None else cpu(sp.q), q_const=sp.q_const, qom=sp.qom)
+                                    for sp in sim.species],
+                           J=cpu(sim.J), M=cpu(sim.M), E=cpu(sim.E), BC=cpu(sim.BC))
             sim.step()
         torch.cuda.synchronize()
-        s64, s32 = sims[E.F64], sims[E.F32]
+        s64 = sims[E.F64]
         per_step.append({"J": rel(s32.J, s64.J), "M": rel(s32.M, s64.M), "E": rel(s32.E, s64.E)})
+        if record is not None:
+            # the pass's fields as the kernels saw them (FP32 copies) and its results
+            # after the step the node-field buffers have swapped: BN_next_p holds
+            # the mover's B^n, BN_p the deposit's B^{n+1}
+            pre.update(Et=cpu(s32.Et_p), Bmove=cpu(s32.BN_next_p), Bdep=cpu(s32.BN_p),
+                       J1=cpu(s32.J), M1=cpu(s32.M), E1=cpu(s32.E))
+            record.append(pre)
     del sims
     torch.cuda.empty_cache()
     worst = {k: max(d[k] for d in per_step) for k in ("J", "M", "E")}
     return {**worst, "per_step": per_step, "bound": 1e-5,
-            "against": f"FP64 path from the same initial state, after each of {steps} steps"}
+            "against": f"FP64 GPU path from the same initial state, free-running, after each of {steps} steps"}
 
 
 def calibrate_copy():
@@ -249,29 +272,164 @@ def calibrate_copy():
     torch.cuda.empty_cache()
 
 
-def cpu_baseline(plasma, sample):
-    """The FP64 oracle's mover + moments on 1/sample of the particles, on the host."""
+def host_cpu():
+    """CPU model and core counts of the host (lscpu), and the threads this process may use."""
+    import subprocess
+    info = {"model": None, "physical_cores": None, "logical_cpus": None}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        kv = {}
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        info["model"] = kv.get("Model name")
+        sockets = int(kv.get("Socket(s)", "1") or 1)
+        cores = int(kv.get("Core(s) per socket", "0") or 0)
+        info["physical_cores"] = sockets * cores if cores else None
+        info["logical_cpus"] = int(kv.get("CPU(s)", "0") or 0) or None
+    except Exception:
+        pass
+    affinity = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = affinity
+    if omp and omp.isdigit() and int(omp) > 0:
+        threads = min(threads, int(omp))
+    if info["physical_cores"]:
+        threads = min(threads, info["physical_cores"])
+    info["cpus_allowed"] = affinity
+    info["threads"] = max(1, threads)
+    return info
+
+
+def _m27_from_m14(O, n, M14):
+    """The 27 blocks of every node from the 14 stored ones (M_{g,g-o} = block k of node g - o)."""
+    import numpy as np
+    nx, ny, nz = n
+    off = O.canonical14()
+    M27 = np.zeros((27, 9, nx * ny * nz))
+    for k in range(14):
+        ox, oy, oz = (int(a) for a in off[k])
+        M27[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)] = M14[k]
+        if k:
+            src = M14[k].reshape(9, nz, ny, nx)
+            M27[(-ox + 1) + 3 * (-oy + 1) + 9 * (-oz + 1)] = np.roll(src, (oz, oy, ox), axis=(1, 2, 3)).reshape(9, -1)
+    return M27
+
+
+def oracle_error(O, plasma, rec, threads, nnodes=8):
+    """The FP32 form against the FP64 oracle, step by step, from the FP32 run's own state.
+
+    For every recorded step: J-hat and the 14 mass-matrix blocks after the
+    fused pass at sampled nodes, against the oracle's mover (with the pass's
+    E^{n+theta} and B^n) and moments (with B^{n+1}) of every particle that
+    starts within two cells of those nodes, fed the FP32 state widened exactly
+    to FP64; and E^{n+1} over the whole grid, against the oracle's GMRES field
+    solve (tolerance 1e-10) and field advance from the same moments and fields.
+    """
+    import numpy as np
+    from paper_2603_16624_amd import inputs as I
+    p = plasma
+    nx, ny, nz = p.n
+    rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    rng = np.random.default_rng(4711)
+    out = []
+    t0 = time.perf_counter()
+    for r in rec:
+        nodes = rng.choice(p.nn, size=nnodes, replace=False)
+        near = np.zeros(p.nn, dtype=bool)
+        for gnode in nodes:
+            gx, gy, gz = gnode % nx, (gnode // nx) % ny, gnode // (nx * ny)
+            for dz in range(-3, 3):
+                for dy in range(-3, 3):
+                    for dx in range(-3, 3):
+                        near[(gx + dx) % nx + nx * (((gy + dy) % ny) + ny * ((gz + dz) % nz))] = True
+        Et, Bm, Bd = (np.asarray(r[k], dtype=np.float64) for k in ("Et", "Bmove", "Bdep"))
+        Jo = np.zeros((3, p.nn))
+        M27 = np.zeros((27, 9, p.nn))
+        for s in r["species"]:
+            idx = np.nonzero(near[s["cell"]])[0]
+            x = I.decode_f32(s["cell"][idx], s["off"][:, idx], p.n, p.h)
+            v = s["v"][:, idx].astype(np.float64)
+            q = s["q"][idx].astype(np.float64) if s["q"] is not None else float(np.float32(s["q_const"]))
+            _, _, Jo, M27, _ = O.move_moments_threads(p.n, p.h, p.dt, x, v, q, s["qom"], Et, Bm, Bd, Jo, M27,
+                                                       threads)
+        Mo = O.m14(p.n, M27)
+        del M27
+        eJ = rel(r["J1"][:, nodes].astype(np.float64), Jo[:, nodes])
+        eM = rel(r["M1"][:, :, nodes].astype(np.float64), Mo[:, :, nodes])
+        del Mo
+        M27 = _m27_from_m14(O, p.n, r["M"].astype(np.float64))
+        sol = O.field_solve(p.n, p.h, p.dt, M27, r["J"].astype(np.float64), r["E"], r["BC"], 1e-10)
+        del M27
+        eE = rel(r["E1"], sol["E_next"])
+        out.append({"J": eJ, "M": eM, "E": eE, "oracle_gmres_iters": sol["iters"]})
+    worst = {k: max(d[k] for d in out) for k in ("J", "M", "E")} if out else {}
+    return {**worst, "per_step": out, "bound": 1e-5, "nodes_per_step": nnodes, "wall_s": time.perf_counter() - t0,
+            "against": "FP64 oracle, one step from the FP32 run's own state (J, M at sampled nodes; "
+                       "E^{n+1} over the grid from the same moments)"}
+
+
+def cpu_baseline(plasma, sample, rec=None):
+    """The CPU leg: the FP64 oracle timed on the host, and (with `rec`) the FP32
+    form's per-step error against it.
+
+    Timings (std clock around the oracle calls): the oracle's particle pass --
+    mover, then the moments at the moved positions -- on all the threads this
+    process may use (thread-private grids added in a fixed order) over
+    1/`sample` of each species of the 64^3 workload, and on one thread over
+    1/(16 `sample`); and the whole scheme on the 8^3 workload (moments, GMRES
+    field solve, mover; 10 steps), on all threads and on one.
+    """
     import numpy as np
     from oracle import oracle as O
+    from paper_2603_16624_amd import inputs as I
+    cpu = host_cpu()
+    nt = cpu["threads"]
     rng = np.random.default_rng(12345)
     BN = O.centres_to_nodes(plasma.n, plasma.B_C)
     En = 1e-4 * rng.standard_normal((3, plasma.nn))
-    nn = plasma.nn
-    J = np.zeros((3, nn))
-    M27 = np.zeros((27, 9, nn))
-    count = 0
+
+    def pass_rate(frac, threads):
+        J = np.zeros((3, plasma.nn))
+        M27 = np.zeros((27, 9, plasma.nn))
+        count, dt = 0, 0.0
+        for s in plasma.species:
+            k = max(1, s.np // frac)
+            x = np.ascontiguousarray(s.x[:, :k])
+            v = np.ascontiguousarray(s.v[:, :k])
+            q = s.q[:k] if np.ndim(s.q) else s.q
+            t0 = time.perf_counter()
+            _, _, J, M27, used = O.move_moments_threads(plasma.n, plasma.h, plasma.dt, x, v, q, s.qom, En, BN, BN,
+                                                         J, M27, threads)
+            dt += time.perf_counter() - t0
+            count += k
+        return count, dt, used
+
+    c_all, t_all, used = pass_rate(sample, nt)
+    c_one, t_one, _ = pass_rate(16 * sample, 1)
+    p0 = I.config0()
+    steps0 = 10
     t0 = time.perf_counter()
-    for s in plasma.species:
-        k = max(1, s.np // sample)
-        x = np.ascontiguousarray(s.x[:, :k])
-        v = np.ascontiguousarray(s.v[:, :k])
-        x1, v1 = O.move(plasma.n, plasma.h, plasma.dt, x, v, s.qom, En, BN)
-        O.moments(plasma.n, plasma.h, plasma.dt, x1, v1, s.q[:k], s.qom, BN, J, M27)
-        count += k
-    dt = time.perf_counter() - t0
-    return dict(value=count / dt, unit="particles/s", cores=1, kind="oracle",
-                sample=f"FP64 oracle mover+moments on {count} particles (1/{sample} of each species) "
-                       f"of the 64^3 workload, single thread, {dt:.1f} s")
+    O.run_steps_threads(p0, steps0, threads=nt)
+    t0_all = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.run_steps_threads(p0, steps0, threads=1)
+    t0_one = time.perf_counter() - t0
+    base = dict(value=c_all / t_all, unit="particles/s", cores=used, kind="oracle",
+                sample=f"FP64 oracle particle pass (mover, then moments at the moved positions) on {c_all} "
+                       f"particles (1/{sample} of each species) of the 64^3 x 64 ppc x 2 species workload, "
+                       f"{used} threads, {t_all:.1f} s",
+                cpu_model=cpu["model"], physical_cores=cpu["physical_cores"], cpus_allowed=cpu["cpus_allowed"],
+                one_core={"value": c_one / t_one, "unit": "particles/s", "cores": 1,
+                          "sample": f"{c_one} particles (1/{16 * sample} of each species), {t_one:.1f} s"},
+                small_workload_10_steps={
+                    "workload": "8^3 cells x 27 ppc x 2 species (27,648 particles), 10 steps of moments, "
+                                "GMRES field solve (tol 1e-10) and mover",
+                    "all_cores": {"cores": used, "s": t0_all, "particles_steps_per_s": p0.n_particles * steps0 / t0_all},
+                    "one_core": {"cores": 1, "s": t0_one, "particles_steps_per_s": p0.n_particles * steps0 / t0_one}})
+    err = oracle_error(O, plasma, rec, nt) if rec else None
+    return base, err
 
 
 def _time_events(fn, reps, warmup=2):
@@ -506,14 +664,20 @@ def main():
         torch.cuda.empty_cache()
         r64 = run_form("f64", args, plasma)
         print(f"[bench] f64: {json.dumps(r64)}", file=sys.stderr, flush=True)
+    err = None
+    rec = None
+    if not args.no_error:
+        rec = [] if not args.no_cpu_baseline else None
+        err = fixed_error(plasma, record=rec)
+        print(f"[bench] fixed error (FP32 vs FP64 path): {json.dumps(err)}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(plasma, args.cpu_sample)
+        cpu, oerr = cpu_baseline(plasma, args.cpu_sample, rec)
+        rec = None
         print(f"[bench] cpu: {json.dumps(cpu)}", file=sys.stderr, flush=True)
-    err = None
-    if not args.no_error:
-        err = fixed_error(plasma)
-        print(f"[bench] fixed error: {json.dumps(err)}", file=sys.stderr, flush=True)
+        if oerr is not None:
+            print(f"[bench] fixed error (FP32 vs oracle): {json.dumps(oerr)}", file=sys.stderr, flush=True)
+            err = {**oerr, "fp64_path_divergence": err}
     apply = adjoint = diag = two_d = harris = four_2d = None
     if not args.no_extras:
         apply = mass_apply_rate(args.n)

@@ -349,3 +349,33 @@ def run_steps(plasma, nsteps, tol=1e-10, restart=30, maxit=1000, record=None):
         hist.append(dict(step=step, K=K, WE=WE, WB=WB, total=K + WE + WB, iters=sol["iters"],
                          rel_resid=sol["rel_resid"]))
     return dict(x=x, v=v, E=E, BC=BC), hist
+
+
+def run_steps_threads(plasma, nsteps, threads=1, tol=1e-10, restart=30, maxit=1000):
+    """The scheme's step loop with the particle pass on host threads: the moments of the initial
+    state, then per step the field solve, and the mover followed by the next step's moments
+    (move_moments_threads, with B^n for the mover and B^{n+1} for the moments). The same scheme as
+    run_steps (Sec. II), with the mover and the next moments in one pass. Returns the final state,
+    the per-step history and the threads used."""
+    x = [s.x.copy() for s in plasma.species]
+    v = [s.v.copy() for s in plasma.species]
+    E = plasma.E.copy()
+    BC = plasma.B_C.copy()
+    BN = centres_to_nodes(plasma.n, BC)
+    J, M27 = species_moments(plasma, x, v, BN)
+    hist = []
+    used = 1
+    for step in range(1, nsteps + 1):
+        sol = field_solve(plasma.n, plasma.h, plasma.dt, M27, J, E, BC, tol, restart, maxit)
+        BN_next = centres_to_nodes(plasma.n, sol["BC_next"])
+        Jn = np.zeros_like(J)
+        Mn = np.zeros_like(M27)
+        for i, s in enumerate(plasma.species):
+            x[i], v[i], Jn, Mn, used = move_moments_threads(plasma.n, plasma.h, plasma.dt, x[i], v[i], s.q, s.qom,
+                                                            sol["E_theta"], BN, BN_next, Jn, Mn, threads)
+        J, M27, BN = Jn, Mn, BN_next
+        E, BC = sol["E_next"], sol["BC_next"]
+        K, WE, WB = total_energy(plasma, v, E, BC)
+        hist.append(dict(step=step, total=K + WE + WB, iters=sol["iters"], rel_resid=sol["rel_resid"]))
+    return dict(x=x, v=v, E=E, BC=BC), hist, used
+

@@ -558,3 +558,18 @@ def test_threaded_particle_pass_matches_serial(oracle, inputs):
                 assert np.array_equal(J, J2) and np.array_equal(M27, M2)
             assert relerr(J2, J) < 1e-14
             assert relerr(M2, M27) < 1e-14
+
+
+def test_threaded_step_loop_matches_step_loop(oracle, inputs):
+    """The step loop with the threaded particle pass reaches the same state as
+    the plain step loop (moments -> solve -> mover), to rounding, and also
+    conserves the energy."""
+    p = inputs.config0()
+    ref, hist = oracle.run_steps(p, 3)
+    out, hist_t, used = oracle.run_steps_threads(p, 3, threads=4)
+    assert used == 4
+    for a, b in zip(ref["v"], out["v"]):
+        assert relerr(b, a) < 1e-12
+    assert relerr(out["E"], ref["E"]) < 1e-9
+    e0 = hist[0]["total"]
+    assert max(abs(h["total"] - e0) for h in hist_t) / e0 < 1e-10
