@@ -131,6 +131,20 @@ ecsim_status ecsim_workspace_size(const ecsim_grid *grid, int64_t np, int32_t pr
                                   uint32_t flags, size_t *bytes /* host out */);
 
 /*
+ * The charge-to-mass ratio with which the kernels of precision `prec` move a
+ * species of ratio `qom` (host, synchronous): they carry beta = qom dt / 2 as
+ * a constant of that precision (the beta_p of Eqs. 2 and 4-5), so
+ * *out = 2 beta / dt, which in ECSIM_F32 differs from qom by the FP32
+ * rounding of beta (1.5e-8 relative for qom = -1, dt = 0.1). The scheme
+ * conserves the total energy of the particles it moves (Secs. I-II, theta =
+ * 1/2): every kinetic energy this library returns (ke_out) uses the masses
+ * m_p = q_p / *out, and a caller that sums the kinetic energy itself should
+ * too; with q_p / qom the FP32 total drifts one way by that rounding times the
+ * work the field does on the species.
+ */
+ecsim_status ecsim_species_qom(int32_t prec, double qom, double dt, double *out /* host */);
+
+/*
  * Particle mover, Eqs. 4, 5 and 8 of the paper:
  *   E_p, B_p = trilinear gathers of E_node = E^{n+theta} and B_node = B^n at
  *              x^{n-1/2};
@@ -145,7 +159,8 @@ ecsim_status ecsim_workspace_size(const ecsim_grid *grid, int64_t np, int32_t pr
  * Updates pos/cell/vel of `sp` in place, preserving particle order.
  * E_node, B_node: [3][Nn] in the particles' precision.
  * ke_out: optional device double; receives (+=) sum_p 1/2 m_p |v^{n+1}|^2 with
- * m_p = q_p/(q/m). Per-particle charges are read only for ke_out.
+ * m_p = q_p / (q/m)_int, (q/m)_int from ecsim_species_qom for the particles'
+ * precision. Per-particle charges are read only for ke_out.
  */
 ecsim_status ecsim_move(const ecsim_grid *grid, const ecsim_particles *sp,
                         const void *E_node, const void *B_node, double *ke_out,

@@ -145,6 +145,15 @@ ecsim_status ecsim_workspace_size(const ecsim_grid* grid, int64_t np, int32_t pr
   return ECSIM_OK;
 }
 
+ecsim_status ecsim_species_qom(int32_t prec, double qom, double dt, double* out) {
+  if (check_prec(prec) != ECSIM_OK) return ECSIM_EINVAL;
+  if (!out) return fail(ECSIM_EINVAL, "ecsim_species_qom: out is NULL");
+  if (!std::isfinite(qom) || qom == 0.0) return fail(ECSIM_EINVAL, "ecsim_species_qom: qom must be finite and non-zero");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ECSIM_EINVAL, "ecsim_species_qom: dt must be > 0");
+  *out = integrated_qom(qom, dt, prec == ECSIM_F32);
+  return ECSIM_OK;
+}
+
 ecsim_status ecsim_move(const ecsim_grid* grid, const ecsim_particles* sp, const void* E_node, const void* B_node,
                         double* ke_out, void* stream) {
   Grid g;

@@ -1604,7 +1604,7 @@ TArgs<T> make_args(const Grid& g, const SpeciesArgs* sp, int ns) {
     a.s[s].beta = (T)(sp[s].qom * g.dt / 2.0);
     a.s[s].beta_V = (T)(sp[s].qom * g.dt / 2.0 / g.V);
     a.s[s].inv_V = (T)(1.0 / g.V);
-    a.s[s].inv_qom = 1.0 / sp[s].qom;
+    a.s[s].inv_qom = 1.0 / integrated_qom(sp[s].qom, g.dt, sizeof(T) == 4);
     a.s[s].cell_start = sp[s].cell_start;
   }
   a.dth[0] = (T)(g.pdt[0] / g.hx);

@@ -23,6 +23,17 @@ struct SpeciesArgs {
 
 constexpr int kMaxSpecies = 8;
 
+// The kernels carry beta = (q/m) dt / 2 of a species as a constant in the
+// particles' precision, so they move particles whose charge-to-mass ratio is
+// 2 beta / dt (in FP32 that differs from q/m by the rounding of beta, 1.5e-8
+// relative for q/m = -1, dt = 0.1). The scheme exchanges energy exactly
+// between the fields and those particles (Secs. I-II), so the kinetic energy
+// takes their masses, q_p dt / (2 beta).
+inline double integrated_qom(double qom, double dt, bool f32) {
+  const double beta = qom * dt / 2.0;
+  return 2.0 * (f32 ? (double)(float)beta : beta) / dt;
+}
+
 hipError_t launch_move(const Grid& g, bool f32, const SpeciesArgs& sp, const void* E, const void* B,
                        double* ke, hipStream_t st);
 

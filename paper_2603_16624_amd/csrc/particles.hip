@@ -320,7 +320,7 @@ hipError_t launch_move(const Grid& g, bool f32, const SpeciesArgs& sp, const voi
                        hipStream_t st) {
   if (sp.np == 0) return hipSuccess;
   const double beta = sp.qom * g.dt / 2.0;
-  const double inv_qom = 1.0 / sp.qom;
+  const double inv_qom = 1.0 / integrated_qom(sp.qom, g.dt, f32);
   if (f32) {
     hipLaunchKernelGGL((k_move<float, true>), dim3(nblocks_capped(sp.np, kBlock)), dim3(kBlock), 0, st, g, sp.np,
                        (float*)sp.pos[0], (float*)sp.pos[1], (float*)sp.pos[2], sp.cell, (float*)sp.vel[0],

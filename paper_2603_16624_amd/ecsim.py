@@ -57,6 +57,7 @@ def lib():
         L.ecsim_version.restype = ctypes.c_char_p
         sig = {
             "ecsim_workspace_size": [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, P],
+            "ecsim_species_qom": [ctypes.c_int32, ctypes.c_double, ctypes.c_double, P],
             "ecsim_move": [P, P, P, P, P, P],
             "ecsim_moments": [P, P, ctypes.c_int32, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32, P],
             "ecsim_move_moments": [P, P, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32,
@@ -85,7 +86,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ["ecsim_last_error", "ecsim_version", "ecsim_workspace_size", "ecsim_move", "ecsim_moments",
+EXPORTED = ["ecsim_last_error", "ecsim_version", "ecsim_workspace_size", "ecsim_species_qom", "ecsim_move", "ecsim_moments",
             "ecsim_move_moments", "ecsim_move_moments_regroup", "ecsim_diagnostics",
             "ecsim_diagnostics_workspace_size",
             "ecsim_mass_apply", "ecsim_moments_backward", "ecsim_sort", "ecsim_centres_to_nodes", "ecsim_to_f32",
@@ -219,6 +220,14 @@ def workspace_size(grid: Grid, np_: int, prec: int, flags: int = 0) -> int:
     out = ctypes.c_size_t(0)
     _check(lib().ecsim_workspace_size(ctypes.byref(grid.c()), int(np_), int(prec), int(flags), ctypes.byref(out)))
     return int(out.value)
+
+
+def species_qom(prec: int, qom: float, dt: float) -> float:
+    """The charge-to-mass ratio the kernels of precision prec move a species of ratio qom with
+    (the masses of every kinetic energy the library returns are q_p / this)."""
+    out = ctypes.c_double(0.0)
+    _check(lib().ecsim_species_qom(int(prec), float(qom), float(dt), ctypes.byref(out)))
+    return out.value
 
 
 def move(grid: Grid, sp: Species, E: torch.Tensor, B: torch.Tensor, ke: Optional[torch.Tensor] = None,

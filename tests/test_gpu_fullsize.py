@@ -22,7 +22,7 @@ in both forms against the GMRES tolerance (1e-10 relative).
 import numpy as np
 import pytest
 
-from tests.gpu_common import dev, host, need_gpu, periodic_rel, rel, round32, say, torch
+from tests.gpu_common import dev, host, kinetic0, need_gpu, periodic_rel, rel, round32, say, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -163,7 +163,7 @@ def test_energy_conservation_full_size(E, O, plasma, prec):
     if prec == "f32":
         for s, f in zip(p.species, I.to_f32_state(p)):
             s.x, s.v, s.q = f["x64"], f["v64"], f["q64"]
-    K0 = sum(O.kinetic(s.v, s.q, s.qom) for s in p.species)
+    K0 = kinetic0(E, O, p, prec)
     WE0, WB0 = sim.energy()
     e0 = K0 + WE0 + WB0
     drift = 0.0

@@ -74,7 +74,8 @@ def test_harris_twenty_steps_with_adjoint(E, O):
     assert all(s.q is not None for s in sim.species)
     K0 = 0.0
     for ps, s in zip(p.species, sim.species):
-        K0 += O.kinetic(host(s.vel).astype(np.float64), host(s.q).astype(np.float64), ps.qom)
+        K0 += O.kinetic(host(s.vel).astype(np.float64), host(s.q).astype(np.float64),
+                        E.species_qom(E.F32, ps.qom, p.dt))
     WE0, WB0 = sim.energy()
     e0 = K0 + WE0 + WB0
     drift = 0.0
