@@ -231,6 +231,28 @@ ecsim_status ecsim_move_moments(const ecsim_grid *grid, const ecsim_particles *s
                                 void *ws, size_t ws_bytes, uint32_t flags, void *stream);
 
 /*
+ * ecsim_move_moments without a workspace argument and without any device
+ * allocation, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc. The
+ * scratch (stray list, stray state, per-cell counts and their scan) is a
+ * static device array of ECSIM_NOALLOC_SCRATCH_BYTES that the library holds
+ * on every device it runs on until the process ends; every call clears what
+ * must start at zero. Calls on one device share that array, so two calls
+ * that overlap on one GPU (different streams, or threads) race and give
+ * wrong results; serialise them. Moves, J, M, ke_out, flags and errors as
+ * for ecsim_move_moments; ECSIM_EWORKSPACE (nothing launched) when the
+ * particles and grid need more scratch than the array holds: the bytes
+ * ecsim_workspace_size reports for the total particle count must not exceed
+ * ECSIM_NOALLOC_SCRATCH_BYTES (about 800,000 FP32 or 480,000 FP64 particles
+ * on small grids). Allocates nothing, calls no allocating routine.
+ */
+#define ECSIM_NOALLOC_SCRATCH_BYTES (64u << 20)
+ecsim_status ecsim_move_moments_noalloc(const ecsim_grid *grid, const ecsim_particles *species,
+                                        int32_t nspecies, const void *E_node, const void *B_node,
+                                        const void *B_next, void *J, void *M, double *ke_out,
+                                        uint32_t flags, void *stream);
+
+/*
  * The fused particle pass of ecsim_move_moments (same moves, same J and M),
  * which also regroups the particles by cell for the next pass: the deposit
  * takes every particle cell by cell (a cell's own range particles still in

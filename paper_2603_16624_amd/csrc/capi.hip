@@ -58,6 +58,29 @@ int* device_flag() {
   return g_flag_ptr[dev];
 }
 
+// Scratch of ecsim_move_moments_noalloc, in place of a caller's workspace: a
+// file-scope device array, which every device that runs the library holds
+// (its own copy, at its own address) until the process ends. Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol): the device address of the current device's copy is looked up
+// once per device and kept.
+__device__ __attribute__((aligned(256))) unsigned char scratch[ECSIM_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* device_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 // Attaches the current device's non-finite flag to a validated grid, right
 // before the first launch of an entry point.
 ecsim_status bind_flag(Grid& g, const char* who) {
@@ -301,6 +324,45 @@ ecsim_status ecsim_move_moments(const ecsim_grid* grid, const ecsim_particles* s
   }
   e = launch_move_deposit(g, f32, a, nspecies, E_node, B_node, B_next, J, M, ke_out, ws, st);
   if (e != hipSuccess) return hip_fail(e, "ecsim_move_moments");
+  return ECSIM_OK;
+}
+
+ecsim_status ecsim_move_moments_noalloc(const ecsim_grid* grid, const ecsim_particles* species, int32_t nspecies,
+                                        const void* E_node, const void* B_node, const void* B_next, void* J,
+                                        void* M, double* ke_out, uint32_t flags, void* stream) {
+  const char* who = "ecsim_move_moments_noalloc";
+  Grid g;
+  SpeciesArgs a[kMaxSpecies];
+  if (flags & ~(uint32_t)(ECSIM_ACCUMULATE | ECSIM_SORTED)) return fail(ECSIM_EINVAL, "%s: unknown flags 0x%x", who, flags);
+  if (species_list(grid, species, nspecies, g, a, who, flags, true) != ECSIM_OK) return ECSIM_EINVAL;
+  if (!E_node || !B_node || !B_next || !J || !M)
+    return fail(ECSIM_EINVAL, "%s: E_node, B_node, B_next, J and M are required", who);
+  if (!tiled_species_ok(a, nspecies))
+    return fail(ECSIM_EINVAL, "%s: at most 4 species of fewer than 2^28 particles each", who);
+  int64_t np_total = 0;
+  for (int s = 0; s < nspecies; ++s) np_total += a[s].np;
+  const bool f32 = species[0].prec == ECSIM_F32;
+  const size_t need = tiled_workspace_bytes(g, np_total, f32);
+  if (need > (size_t)ECSIM_NOALLOC_SCRATCH_BYTES)
+    return fail(ECSIM_EWORKSPACE,
+                "%s: %lld particles on %lld cells need %zu bytes of scratch; the static scratch holds %zu "
+                "(use ecsim_move_moments with a workspace)",
+                who, (long long)np_total, (long long)g.nn, need, (size_t)ECSIM_NOALLOC_SCRATCH_BYTES);
+  void* ws = device_scratch();
+  if (!ws) return fail(ECSIM_EHIP, "%s: the device's static scratch is not accessible", who);
+  if (bind_flag(g, who) != ECSIM_OK) return ECSIM_EHIP;
+  const size_t esz = f32 ? 4 : 8;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  // the same launches as ecsim_move_moments; every word of the scratch that
+  // must start at zero (the stray counter, the zero block, the per-cell
+  // counts) is cleared by those launches' own fill kernels
+  if (!(flags & ECSIM_ACCUMULATE)) {
+    if ((e = launch_zero(J, esz * 3 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_move_moments_noalloc zero J");
+    if ((e = launch_zero(M, esz * 126 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_move_moments_noalloc zero M");
+  }
+  e = launch_move_deposit(g, f32, a, nspecies, E_node, B_node, B_next, J, M, ke_out, ws, st);
+  if (e != hipSuccess) return hip_fail(e, who);
   return ECSIM_OK;
 }
 

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libecsim.so")
 
 OK, EINVAL, EHIP, EWORKSPACE, ENONFINITE, ENOCONV = 0, -1, -2, -3, -4, -5
 F64, F32 = 0, 1
+NOALLOC_SCRATCH_BYTES = 64 << 20   # ECSIM_NOALLOC_SCRATCH_BYTES of include/ecsim.h
 ACCUMULATE, SORTED, BWD_THROUGH_MOVER, BWD_OFFSET_GRAD = 1, 2, 8, 16
 ENERGY_WS_BYTES = 2048
 
@@ -62,6 +63,7 @@ def lib():
             "ecsim_moments": [P, P, ctypes.c_int32, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32, P],
             "ecsim_move_moments": [P, P, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32,
                                    P],
+            "ecsim_move_moments_noalloc": [P, P, ctypes.c_int32, P, P, P, P, P, P, ctypes.c_uint32, P],
             "ecsim_move_moments_regroup": [P, P, P, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_size_t,
                                            ctypes.c_uint32, P],
             "ecsim_diagnostics": [P, P, ctypes.c_int32, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32, P],
@@ -87,7 +89,7 @@ def lib():
 
 
 EXPORTED = ["ecsim_last_error", "ecsim_version", "ecsim_workspace_size", "ecsim_species_qom", "ecsim_move", "ecsim_moments",
-            "ecsim_move_moments", "ecsim_move_moments_regroup", "ecsim_diagnostics",
+            "ecsim_move_moments", "ecsim_move_moments_noalloc", "ecsim_move_moments_regroup", "ecsim_diagnostics",
             "ecsim_diagnostics_workspace_size",
             "ecsim_mass_apply", "ecsim_moments_backward", "ecsim_sort", "ecsim_centres_to_nodes", "ecsim_to_f32",
             "ecsim_solve_workspace_size", "ecsim_field_solve", "ecsim_field_energy", "ecsim_check_finite",
@@ -282,6 +284,15 @@ def move_moments(grid: Grid, species: Sequence[Species], E: torch.Tensor, B: tor
                          device=J.device)
     _check(lib().ecsim_move_moments(ctypes.byref(grid.c()), arr, len(species), _ptr(E), _ptr(B), _ptr(B_next),
                                     _ptr(J), _ptr(M), _ptr(ke), _ptr(ws), ws.numel(), int(flags), _stream(stream)))
+
+
+def move_moments_noalloc(grid: Grid, species: Sequence[Species], E: torch.Tensor, B: torch.Tensor,
+                         B_next: torch.Tensor, J: torch.Tensor, M: torch.Tensor, ke: Optional[torch.Tensor] = None,
+                         flags: int = 0, stream=None):
+    """move_moments on the library's static device scratch: no workspace, no allocation."""
+    arr = (_Particles * len(species))(*[s.c() for s in species])
+    _check(lib().ecsim_move_moments_noalloc(ctypes.byref(grid.c()), arr, len(species), _ptr(E), _ptr(B),
+                                            _ptr(B_next), _ptr(J), _ptr(M), _ptr(ke), int(flags), _stream(stream)))
 
 
 def move_moments_regroup(grid: Grid, species: Sequence[Species], dst: Sequence[Species], E: torch.Tensor,

@@ -243,6 +243,30 @@ def test_move_moments_regroup_validation(E):
     assert b"exceeds" in L.ecsim_last_error()
 
 
+def test_move_moments_noalloc_validation(E):
+    """The static-scratch pass rejects bad arguments and inputs beyond its scratch before any launch."""
+    L = E.lib()
+    g = _grid(E)
+    fake = ctypes.c_void_p(0x1000)
+    gp = lambda p, cs: (setattr(p, "cell_start", cs), p)[1]
+
+    def call(parts, ns=1, flags=0, J=fake):
+        return L.ecsim_move_moments_noalloc(ctypes.byref(g), parts, ns, fake, fake, fake, J, fake, None, flags,
+                                            None)
+
+    small = (E._Particles * 1)(gp(_particles(E, prec=E.F32, cell=True), 0x5000))
+    assert call(small, flags=0x100) == E.EINVAL
+    assert call(small, J=None) == E.EINVAL
+    assert call((E._Particles * 1)(gp(_particles(E, prec=E.F32, cell=True), None))) == E.EINVAL   # no ranges
+    need = ctypes.c_size_t(0)
+    for prec, np_ in ((E.F32, 2_000_000), (E.F64, 600_000)):
+        assert L.ecsim_workspace_size(ctypes.byref(g), np_, prec, 0, ctypes.byref(need)) == E.OK
+        assert need.value > E.NOALLOC_SCRATCH_BYTES
+        big = (E._Particles * 1)(gp(_particles(E, prec=prec, np_=np_, cell=prec == E.F32), 0x5000))
+        assert call(big) == E.EWORKSPACE
+        assert b"scratch" in L.ecsim_last_error()
+
+
 def test_sorted_species_limits_are_errors(E):
     """With ECSIM_SORTED more than 4 species is an error, not a silent switch to the any-order deposit."""
     L = E.lib()
