@@ -84,7 +84,10 @@ __global__ void __launch_bounds__(kBlock) k_backward(
     Vec3<T> Ep = gather(E, nn, W0, nd0);
     Bp = gather(B, nn, W0, nd0);
     rotation(Bp, beta, a0);
-    vn = velocity_update(a0, v, Ep, beta, u);
+    // alpha and u for the chain rule; the new velocity as the forward mover
+    // computes it (so the recomputed push lands where the forward's did)
+    velocity_update(a0, v, Ep, beta, u);
+    vn = advance_velocity(Bp, beta, v, Ep);
     if constexpr (CELL) {
       int ix = s0.i[0], iy = s0.i[1], iz = s0.i[2];
       float ox = push_offset(s0.w1[0], vn.x, dth0, ix, g.nx);

@@ -234,14 +234,17 @@ ecsim_status ecsim_moments(const ecsim_grid* grid, const ecsim_particles* specie
   if (bind_flag(g, "ecsim_moments") != ECSIM_OK) return ECSIM_EHIP;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
-  if (!(flags & ECSIM_ACCUMULATE)) {
-    if ((e = launch_zero(J, esz * 3 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_moments zero J");
-    if ((e = launch_zero(M, esz * 126 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_moments zero M");
-  }
-  if (tiled)
-    e = launch_deposit_tiled(g, f32, a, nspecies, B_node, J, M, ws, st);
-  else
+  const bool acc = (flags & ECSIM_ACCUMULATE) != 0;
+  if (tiled) {
+    // the tiled deposit's node flush writes (or adds to) every entry of J and M
+    e = launch_deposit_tiled(g, f32, a, nspecies, B_node, J, M, acc, ws, st);
+  } else {
+    if (!acc) {
+      if ((e = launch_zero(J, esz * 3 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_moments zero J");
+      if ((e = launch_zero(M, esz * 126 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_moments zero M");
+    }
     e = launch_deposit_atomic(g, f32, a, nspecies, B_node, J, M, st);
+  }
   if (e != hipSuccess) return hip_fail(e, "ecsim_moments");
   return ECSIM_OK;
 }
@@ -315,14 +318,9 @@ ecsim_status ecsim_move_moments(const ecsim_grid* grid, const ecsim_particles* s
   if (!ws || ws_bytes < need)
     return fail(ECSIM_EWORKSPACE, "ecsim_move_moments: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
   if (bind_flag(g, "ecsim_move_moments") != ECSIM_OK) return ECSIM_EHIP;
-  const size_t esz = f32 ? 4 : 8;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e;
-  if (!(flags & ECSIM_ACCUMULATE)) {
-    if ((e = launch_zero(J, esz * 3 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_move_moments zero J");
-    if ((e = launch_zero(M, esz * 126 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_move_moments zero M");
-  }
-  e = launch_move_deposit(g, f32, a, nspecies, E_node, B_node, B_next, J, M, ke_out, ws, st);
+  const hipError_t e = launch_move_deposit(g, f32, a, nspecies, E_node, B_node, B_next, J, M, ke_out,
+                                           (flags & ECSIM_ACCUMULATE) != 0, ws, st);
   if (e != hipSuccess) return hip_fail(e, "ecsim_move_moments");
   return ECSIM_OK;
 }
@@ -351,17 +349,13 @@ ecsim_status ecsim_move_moments_noalloc(const ecsim_grid* grid, const ecsim_part
   void* ws = device_scratch();
   if (!ws) return fail(ECSIM_EHIP, "%s: the device's static scratch is not accessible", who);
   if (bind_flag(g, who) != ECSIM_OK) return ECSIM_EHIP;
-  const size_t esz = f32 ? 4 : 8;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e;
   // the same launches as ecsim_move_moments; every word of the scratch that
   // must start at zero (the stray counter, the zero block, the per-cell
-  // counts) is cleared by those launches' own fill kernels
-  if (!(flags & ECSIM_ACCUMULATE)) {
-    if ((e = launch_zero(J, esz * 3 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_move_moments_noalloc zero J");
-    if ((e = launch_zero(M, esz * 126 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_move_moments_noalloc zero M");
-  }
-  e = launch_move_deposit(g, f32, a, nspecies, E_node, B_node, B_next, J, M, ke_out, ws, st);
+  // counts) is cleared by those launches' own fill kernels, and the per-cell
+  // sums are written before they are read
+  const hipError_t e = launch_move_deposit(g, f32, a, nspecies, E_node, B_node, B_next, J, M, ke_out,
+                                           (flags & ECSIM_ACCUMULATE) != 0, ws, st);
   if (e != hipSuccess) return hip_fail(e, who);
   return ECSIM_OK;
 }
@@ -408,14 +402,9 @@ ecsim_status ecsim_move_moments_regroup(const ecsim_grid* grid, const ecsim_part
   if (!ws || ws_bytes < need)
     return fail(ECSIM_EWORKSPACE, "%s: workspace of %zu bytes needed, %zu given", who, need, ws ? ws_bytes : 0);
   if (bind_flag(g, who) != ECSIM_OK) return ECSIM_EHIP;
-  const size_t esz = f32 ? 4 : 8;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e;
-  if (!(flags & ECSIM_ACCUMULATE)) {
-    if ((e = launch_zero(J, esz * 3 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_move_moments_regroup zero J");
-    if ((e = launch_zero(M, esz * 126 * (size_t)g.nn, st)) != hipSuccess) return hip_fail(e, "ecsim_move_moments_regroup zero M");
-  }
-  e = launch_move_deposit_regroup(g, f32, a, d, nspecies, E_node, B_node, B_next, J, M, ke_out, ws, st);
+  const hipError_t e = launch_move_deposit_regroup(g, f32, a, d, nspecies, E_node, B_node, B_next, J, M, ke_out,
+                                                   (flags & ECSIM_ACCUMULATE) != 0, ws, st);
   if (e != hipSuccess) return hip_fail(e, who);
   return ECSIM_OK;
 }

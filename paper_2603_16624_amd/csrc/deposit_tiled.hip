@@ -79,6 +79,7 @@ struct TSpecies {
   T inv_V;       // 1 / V
   double inv_qom;
   const int32_t* cell_start;
+  int np;
 };
 
 // The strays' state copied out of the species arrays in cell order (the
@@ -126,6 +127,7 @@ struct TArgs {
   int* stay;
   int* scount;
   RegroupDst<T> dst[kMaxTiledSpecies];
+  T* csum;   // per-cell sums [cells][SCS], written by the deposit, read by the node flush
 };
 
 // Kahan compensated summation: the true running sum is s - c.
@@ -546,75 +548,15 @@ __device__ __forceinline__ void particle_record(const Stencil<T>& ps, const Vec3
   for (int c = 0; c < 27; ++c) r[12 + c] = (f[0][c % 3] * f[1][(c / 3) % 3]) * f[2][c / 9];
 }
 
-// Every (entry, node) of the brick at (x0, y0, z0) gathers its <= 8 cell
-// contributions from the per-cell sums and is added to the global J and M
-// once (entries that are exactly zero are skipped).
-template <typename T, int TX, int TY, int TZ>
-__device__ __forceinline__ void flush_brick(const Grid& g, const T* scell, int x0, int y0, int z0, T* __restrict__ J,
-                                            T* __restrict__ M, int tid, int nthr) {
-  constexpr int NX = TX + 1, NY = TY + 1, NZ = TZ + 1, NN = NX * NY * NZ;
-  // items: (ij, node) for the mass matrix, then (component, node) for J
-  constexpr int NITEM = 9 * NN + 3 * NN;
-  bool bad = false;
-  for (int it = tid; it < NITEM; it += nthr) {
-    const bool is_m = it < 9 * NN;
-    const int ln = is_m ? it % NN : (it - 9 * NN) % NN;
-    const int sub = is_m ? it / NN : (it - 9 * NN) / NN;   // ij, or the current component
-    const int nx_ = ln % NX, ny_ = (ln / NX) % NY, nz_ = ln / (NX * NY);
-    // the cells n - a of this brick, as offsets into the per-cell sums; a
-    // cell beyond the brick reads cell 0 and is masked to zero (adding +0
-    // leaves every sum as it would be without the term), so the gather runs
-    // without divergent branches
-    int coff[8];
-    bool cin[8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int lcx = nx_ - (a & 1), lcy = ny_ - ((a >> 1) & 1), lcz = nz_ - ((a >> 2) & 1);
-      cin[a] = lcx >= 0 && lcx < TX && lcy >= 0 && lcy < TY && lcz >= 0 && lcz < TZ;
-      coff[a] = cin[a] ? (lcx + TX * (lcy + TY * lcz)) * SCS : 0;
-    }
-    const int gx = wrap_once(x0 + nx_, g.nx), gy = wrap_once(y0 + ny_, g.ny), gz = wrap_once(z0 + nz_, g.nz);
-    const int64_t gn = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
-    const T* const sb = scell + sub;
-    if (is_m) {
-#pragma unroll
-      for (int k = 0; k < 14; ++k) {
-        T v = T(0);
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          const int cls = pair_class(k, a);
-          if (cls < 0) continue;
-          const T x = sb[coff[a] + cls * 9];
-          v += cin[a] ? x : T(0);
-        }
-        bad = bad || !finite(v);
-        if (v != T(0)) unsafeAtomicAdd(M + (int64_t)(k * 9 + sub) * g.nn + gn, v);
-      }
-    } else {
-      T v = T(0);
-#pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const T x = sb[coff[a] + 243 + 3 * a];
-        v += cin[a] ? x : T(0);
-      }
-      bad = bad || !finite(v);
-      if (v != T(0)) unsafeAtomicAdd(J + (int64_t)sub * g.nn + gn, v);
-    }
-  }
-  note_nonfinite(g, bad);
-}
-
 // Records in LDS are stored transposed, rec[row][slot] with a row stride of
-// 66 slots (64 particles + 2): the MFMA operand reads of 16 lanes with
+// 66 slots (64 particles + 2): the matrix-core operand reads of 16 lanes with
 // consecutive rows and 2 lane groups then hit 32 different banks. Rows 39-41
-// are not read as used operands; they stage the cells' corner fields
-// (during phase 1) and the current class sums (during phase 3). With 42 rows
-// a 4-wavefront workgroup on a 4x4x2 brick needs 79 KB of LDS (FP32), so two
-// workgroups share a CU.
+// are not read as used operands; they hold the cell's current class sums at
+// the end of a cell. A 4-wavefront workgroup needs 44 KB of LDS (FP32), so
+// three workgroups share a CU.
 constexpr int kSlots = 66;
 constexpr int kRows = 42;
-constexpr int kStage = 39 * kSlots;        // [2 cells][24]: deposit B at the corners
-constexpr int kTcur = 39 * kSlots;         // [2 cells][84]: current class sums (phase 3 only)
+constexpr int kTcur = 39 * kSlots;         // [27][3]: current class sums (end of a cell)
 
 
 // ---------------------------------------------------------------------------
@@ -914,133 +856,492 @@ k_group(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   ws.copy_out(args, wbuf, lane, wst[wave]);
 }
 // ---------------------------------------------------------------------------
+// grouped mover
+// ---------------------------------------------------------------------------
+// A workgroup owns a brick of TX x TY x TZ cells. It stages the mover fields
+// E^{n+theta}, B^n on the brick's nodes plus a one-cell halo in LDS, one
+// record of (E, B) per node so that a corner is two 16-byte reads, then its
+// wavefronts run through the brick's particles species by species: the
+// species' cell ranges of the brick, taken as one list padded to whole blocks
+// of 64, so that every block belongs to one species and reads and writes its
+// arrays through buffer resources in scalar registers with one 32-bit offset
+// per lane (a lane past the list has an offset beyond the buffer: its loads
+// read zero, its stores are dropped). The next block's loads are in flight
+// while a block is moved. A particle whose cell lies in the halo'd box is
+// moved with the staged fields (the same gathers, rotation and push as every
+// other mover) and written back, and listed if it is now outside its range's
+// cell; a particle beyond the box is listed unmoved (with its range's cell)
+// for the stray mover.
+template <typename T>
+struct MoverRsrc {
+  __amdgpu_buffer_rsrc_t pos[3], vel[3], q, cell;
+};
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, int64_t bytes) {
+  // raw buffer: stride 0, range checked against the byte count
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
+                                           (int)(bytes < 0x7fffffff ? bytes : 0x7fffffff), 0x00020000);
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+}
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, T v) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+  }
+}
+
+// one particle's inputs of the grouped mover, loaded ahead of use
+template <typename T>
+struct MData {
+  T x0, x1, x2, v0, v1, v2, q;
+  int c;      // stored cell (FP32 form)
+  int lc;     // local cell of its range
+  int p;      // index in the species arrays
+  bool ok;
+};
+
+template <typename T, int TX, int TY, int TZ, int NW>
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+k_mover(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
+  constexpr int NCELL = TX * TY * TZ;
+  constexpr int HX = TX + 3, HY = TY + 3, HZ = TZ + 3, HN = HX * HY * HZ;   // halo'd node box
+  constexpr int NT = NW * 64;
+  constexpr int NS = kMaxTiledSpecies;
+  static_assert(NS * NCELL <= NT, "one range per thread");
+  // per node: Ex Ey Ez Bx By Bz and two pad values (16-byte aligned halves)
+  __shared__ __attribute__((aligned(16))) T fld[HN * 8];
+  __shared__ int rbeg[NS * NCELL];        // range (species s, cell lc) at s * NCELL + lc
+  __shared__ int roff[NS * (NCELL + 1)];  // species s: list offsets of its cells, [s][lc]
+  __shared__ int rleft[NS * NCELL];       // regrouping: particles of each range listed as strays
+  __shared__ int sblk[NS + 1];            // first block of each species in the workgroup's block order
+  __shared__ double red[NW];
+  __shared__ int wst[NW];
+  __shared__ WaveBuf<T> slist[NW];
+  __shared__ uint8_t rmap[kMapCap];       // list position -> local cell, per species (when it fits)
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int x0, y0, z0;
+  brick_origin<TX, TY, TZ>(ntx, nty, ntz, x0, y0, z0);
+  const int ns = args.ns;
+
+  // ranges: thread t = s * NCELL + lc
+  int n = 0;
+  if (tid < NS * NCELL) {
+    const int s = tid / NCELL, lc = tid % NCELL;
+    const BrickCell c = brick_cell<TX, TY, TZ>(g, x0, y0, z0, lc);
+    int b0 = 0;
+    if (c.valid && s < ns) {
+      const int32_t* cs = args.s[s].cell_start;
+      b0 = cs[c.cell];
+      n = cs[c.cell + 1] - b0;
+    }
+    rbeg[tid] = b0;
+    rleft[tid] = 0;
+  }
+  // per-species exclusive scan over the NCELL cells (NCELL = 32: within half
+  // a wavefront)
+  static_assert(NCELL <= 64 && 64 % NCELL == 0, "a species' cells within one wavefront");
+  int incl = n;
+#pragma unroll
+  for (int o = 1; o < NCELL; o <<= 1) {
+    const int y = __shfl_up(incl, o);
+    if ((lane % NCELL) >= o) incl += y;
+  }
+  if (tid < NS * NCELL) {
+    const int s = tid / NCELL, lc = tid % NCELL;
+    roff[s * (NCELL + 1) + lc] = incl - n;
+    if (lc == NCELL - 1) roff[s * (NCELL + 1) + NCELL] = incl;
+  }
+  for (int nl = tid; nl < HN; nl += NT) {
+    // any number of periods: a dimension may hold fewer cells than the box
+    const int gx = ((x0 - 1 + nl % HX) % g.nx + g.nx) % g.nx;
+    const int gy = ((y0 - 1 + (nl / HX) % HY) % g.ny + g.ny) % g.ny;
+    const int gz = ((z0 - 1 + nl / (HX * HY)) % g.nz + g.nz) % g.nz;
+    const int64_t gn = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      fld[8 * nl + f] = args.Emove[f * g.nn + gn];
+      fld[8 * nl + 3 + f] = args.Bmove[f * g.nn + gn];
+    }
+    fld[8 * nl + 6] = T(0);
+    fld[8 * nl + 7] = T(0);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int b = 0;
+    for (int s = 0; s < NS; ++s) {
+      sblk[s] = b;
+      b += (roff[s * (NCELL + 1) + NCELL] + 63) >> 6;
+    }
+    sblk[NS] = b;
+  }
+  // the list position -> cell map of each species, if every species' list fits
+  int tmax = 0;
+  for (int s = 0; s < NS; ++s) {
+    const int t = roff[s * (NCELL + 1) + NCELL];
+    tmax = t > tmax ? t : tmax;
+  }
+  const bool mapped = tmax * NS <= kMapCap;   // workgroup-uniform
+  const int mstride = mapped ? tmax : 0;
+  if (mapped && tid < NS * NCELL) {
+    const int s = tid / NCELL, lc = tid % NCELL;
+    const int a = roff[s * (NCELL + 1) + lc];
+    for (int i = 0; i < n; ++i) rmap[s * mstride + a + i] = (uint8_t)lc;
+  }
+  __syncthreads();
+  const int nblk = sblk[NS];
+
+  // the species' arrays as buffers (scalar registers)
+  auto rsrc_of = [&](int s) {
+    MoverRsrc<T> R;
+    const TSpecies<T>& sp = args.s[s];
+    const int64_t np = sp.np;
+    for (int d = 0; d < 3; ++d) {
+      R.pos[d] = buffer_of<T>(sp.pos[d], np * (int64_t)sizeof(T));
+      R.vel[d] = buffer_of<T>(sp.vel[d], np * (int64_t)sizeof(T));
+    }
+    R.q = buffer_of<T>(sp.q ? (const void*)sp.q : args.zero, sp.q ? np * (int64_t)sizeof(T) : 0);
+    R.cell = buffer_of<T>(sp.cell ? (const void*)sp.cell : args.zero, sp.cell ? np * 4 : 0);
+    return R;
+  };
+
+  // block b of the workgroup's order: species s, lane position i in its list
+  auto load = [&](int b, int& s_out) -> MData<T> {
+    int s = 0;
+#pragma unroll
+    for (int k = 1; k < NS; ++k) s += b >= sblk[k] ? 1 : 0;
+    s = __builtin_amdgcn_readfirstlane(s);
+    s_out = s;
+    const int i = (b - sblk[s]) * 64 + lane;
+    const int* ro = roff + s * (NCELL + 1);
+    const int tot = ro[NCELL];
+    MData<T> d;
+    d.ok = i < tot;
+    const int ic = d.ok ? i : tot - 1;
+    int lc;
+    if (mapped) {   // workgroup-uniform
+      lc = rmap[s * mstride + ic];
+    } else {
+      lc = 0;
+#pragma unroll
+      for (int step = NCELL / 2; step > 0; step >>= 1) lc += ro[lc + step] <= ic ? step : 0;
+    }
+    d.lc = lc;
+    d.p = rbeg[s * NCELL + lc] + (ic - ro[lc]);
+    const uint32_t off = d.ok ? (uint32_t)d.p * (uint32_t)sizeof(T) : 0xffffffffu;
+    const MoverRsrc<T> R = rsrc_of(s);
+    d.x0 = bload<T>(R.pos[0], off);
+    d.x1 = bload<T>(R.pos[1], off);
+    d.x2 = bload<T>(R.pos[2], off);
+    d.v0 = bload<T>(R.vel[0], off);
+    d.v1 = bload<T>(R.vel[1], off);
+    d.v2 = bload<T>(R.vel[2], off);
+    d.q = bload<T>(R.q, off);   // 0 for a constant-charge species (empty buffer)
+    d.c = sizeof(T) == 4 ? (int)__builtin_amdgcn_raw_buffer_load_b32(R.cell, d.ok ? (uint32_t)d.p * 4u : 0xffffffffu, 0, 0) : 0;
+    return d;
+  };
+
+  double kel = 0.0;
+  WaveStrays<T> ws;
+  WaveBuf<T>& wbuf = slist[wave];
+
+  auto process = [&](const MData<T>& pd, int s) {
+    const TSpecies<T>& sp = args.s[s];
+    const T q = pd.q + (sp.q ? T(0) : sp.q_const);
+    const BrickCell gc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, pd.lc);
+    const Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
+    int item = (s << kItemShift) | pd.p;
+    SRec<T> rec{pd.x0, pd.x1, pd.x2, pd.v0, pd.v1, pd.v2, q, pd.c};
+    // local cell in the halo'd box (periodic)
+    const int dx = wrap_once(ps.i[0] - x0 + 1, g.nx);
+    const int dy = wrap_once(ps.i[1] - y0 + 1, g.ny);
+    const int dz = wrap_once(ps.i[2] - z0 + 1, g.nz);
+    const bool inbox = pd.ok && dx <= TX + 1 && dy <= TY + 1 && dz <= TZ + 1;
+    const int lx = inbox ? dx : 0, ly = inbox ? dy : 0, lz = inbox ? dz : 0;
+    const T* const fb = fld + 8 * (lx + HX * (ly + HY * lz));
+    Vec3<T> Ep{T(0), T(0), T(0)}, Bp{T(0), T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const T w = corner_weight(ps, a);
+      const T* const f = fb + 8 * ((a & 1) + HX * (((a >> 1) & 1) + HY * ((a >> 2) & 1)));
+      Ep.x = fma(w, f[0], Ep.x);
+      Ep.y = fma(w, f[1], Ep.y);
+      Ep.z = fma(w, f[2], Ep.z);
+      Bp.x = fma(w, f[3], Bp.x);
+      Bp.y = fma(w, f[4], Bp.y);
+      Bp.z = fma(w, f[5], Bp.z);
+    }
+    const Vec3<T> v = advance_velocity(Bp, sp.beta, Vec3<T>{pd.v0, pd.v1, pd.v2}, Ep);
+    note_nonfinite(g, inbox && !(finite(v.x) && finite(v.y) && finite(v.z)));
+    T n0, n1, n2;
+    int pcell;
+    if constexpr (sizeof(T) == 4) {
+      int ix = ps.i[0], iy = ps.i[1], iz = ps.i[2];
+      n0 = push_offset(ps.w1[0], v.x, args.dth[0], ix, g.nx);
+      n1 = push_offset(ps.w1[1], v.y, args.dth[1], iy, g.ny);
+      n2 = push_offset(ps.w1[2], v.z, args.dth[2], iz, g.nz);
+      pcell = ix + g.nx * (iy + g.ny * iz);
+    } else {
+      n0 = push_abs(pd.x0, g.pdt[0], v.x, g.nx * g.hx);
+      n1 = push_abs(pd.x1, g.pdt[1], v.y, g.ny * g.hy);
+      n2 = push_abs(pd.x2, g.pdt[2], v.z, g.nz * g.hz);
+      const Stencil<double> nps = stencil_abs(g, n0, n1, n2);
+      pcell = nps.i[0] + g.nx * (nps.i[1] + g.ny * nps.i[2]);
+    }
+    // moved state in the box; unchanged beyond it (the stray mover moves it)
+    if (inbox) {
+      rec.x0 = n0;
+      rec.x1 = n1;
+      rec.x2 = n2;
+      rec.v0 = v.x;
+      rec.v1 = v.y;
+      rec.v2 = v.z;
+      rec.c = pcell;
+    }
+    // write back: lanes without a particle have an offset past the buffer
+    const uint32_t off = pd.ok ? (uint32_t)pd.p * (uint32_t)sizeof(T) : 0xffffffffu;
+    const MoverRsrc<T> R = rsrc_of(s);
+    bstore<T>(R.pos[0], off, rec.x0);
+    bstore<T>(R.pos[1], off, rec.x1);
+    bstore<T>(R.pos[2], off, rec.x2);
+    bstore<T>(R.vel[0], off, rec.v0);
+    bstore<T>(R.vel[1], off, rec.v1);
+    bstore<T>(R.vel[2], off, rec.v2);
+    if constexpr (sizeof(T) == 4)
+      __builtin_amdgcn_raw_buffer_store_b32((uint32_t)rec.c, R.cell, pd.ok ? (uint32_t)pd.p * 4u : 0xffffffffu, 0, 0);
+    if (args.ke) {
+      const double vx = v.x, vy = v.y, vz = v.z;
+      kel += inbox ? 0.5 * ((double)q * sp.inv_qom) * ((vx * vx + vy * vy) + vz * vz) : 0.0;
+    }
+    // listed: moved out of the range's cell, or beyond the box (unmoved)
+    const bool stray = pd.ok && (inbox ? pcell != gc.cell : true);
+    if (pd.ok && !inbox) item |= kUnmoved;
+    const int lcell = inbox ? pcell : gc.cell;
+    if (args.stay && stray) atomicAdd(&rleft[s * NCELL + pd.lc], 1);
+    ws.put(args, wbuf, lane, stray, item, lcell, rec);
+  };
+
+  // blocks wave, wave + NW, ...: the next block's loads in flight while one
+  // is moved; unrolled once so that the two register sets swap roles (a copy
+  // of a loaded register would wait for its load)
+  if (wave < nblk) {
+    int sa, sb;
+    MData<T> pa = load(wave, sa), pb;
+    for (int b = wave; b < nblk;) {
+      const bool nb1 = b + NW < nblk;
+      if (nb1) pb = load(b + NW, sb);
+      process(pa, sa);
+      b += NW;
+      if (!nb1) break;
+      const bool nb2 = b + NW < nblk;
+      if (nb2) pa = load(b + NW, sa);
+      process(pb, sb);
+      b += NW;
+      if (!nb2) break;
+    }
+  }
+  if (args.ke) {
+    for (int off = 32; off > 0; off >>= 1) kel += __shfl_down(kel, off);
+    if (lane == 0) red[wave] = kel;
+  }
+  // the strays still held take one reservation of the workgroup in the list
+  if (lane == 0) wst[wave] = ws.fill;
+  __syncthreads();
+  if (tid == 0) {
+    int tot = 0;
+    for (int w = 0; w < NW; ++w) tot += wst[w];
+    int b = tot ? atomicAdd(args.stray_count, tot) : 0;
+    for (int w = 0; w < NW; ++w) {
+      const int c = wst[w];
+      wst[w] = b;
+      b += c;
+    }
+    if (args.ke) {
+      double sum = 0.0;
+      for (int w = 0; w < NW; ++w) sum += red[w];
+      if (sum != 0.0) unsafeAtomicAdd(args.ke, sum);
+    }
+  }
+  __syncthreads();
+  if (args.stay && tid < NS * NCELL) {
+    const int s = tid / NCELL, lc = tid % NCELL;
+    const BrickCell c = brick_cell<TX, TY, TZ>(g, x0, y0, z0, lc);
+    if (c.valid && s < ns)
+      args.stay[(int64_t)s * g.nn + c.cell] =
+          roff[s * (NCELL + 1) + lc + 1] - roff[s * (NCELL + 1) + lc] - rleft[tid];
+  }
+  ws.copy_out(args, wbuf, lane, wst[wave]);
+}
+
+// ---------------------------------------------------------------------------
 // tiled deposit
 // ---------------------------------------------------------------------------
+// A workgroup owns a brick of cells; each wavefront takes the brick's cells
+// one at a time. Per cell the wavefront-uniform quantities (the cell's
+// particle ranges, its corner B, the regrouping starts) are loaded one cell
+// ahead, one value per lane, and moved to scalar registers; each block of 64
+// list positions is one particle per lane:
+//   1. the lane's record (12 values, 27 class weights) goes to LDS;
+//   2. the next block's loads are issued (this cell's, else the next cell's);
+//   3. 16 matrix-core steps of K = 4 particles reduce the block, from zero,
+//      and the block sum is added to the cell's running sums (FP32: Kahan).
+// At the end of a cell its class sums and corner currents are written to the
+// per-cell sums in global memory; the node flush then forms J and M.
 // With REGROUP the deposit also writes every particle it takes (the cell's own
 // range particles still in the cell, then its strays) to the targets, species
 // by species in cell order: the next pass's grouping, without a separate sort.
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int l) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+  } else {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
+
 template <typename T, int TX, int TY, int TZ, int NW, bool REGROUP>
-__global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz,
-                                                     T* __restrict__ J, T* __restrict__ M) {
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
+k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   using MF = Mfma<T>;
   using acc_t = typename MF::acc;
   constexpr int NCELL = TX * TY * TZ;
-  constexpr int NPAIR = (NCELL + 1) / 2;
   constexpr int WREC = kRows * kSlots;
-  // one LDS block: the wavefront records first (so that their offsets fit the
-  // 16-bit immediate of ds_read), then the per-cell sums
-  __shared__ __attribute__((aligned(16))) T smem[NW * WREC + NCELL * SCS];
+  // the wavefront records, and two rows more: the matrix-core operand reads
+  // of the unused classes 27-31 reach two rows past a wavefront's records
+  __shared__ __attribute__((aligned(16))) T smem[NW * WREC + 2 * kSlots];
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
   __shared__ PtrSet<T> lptr_tab[kZeroSlot + 1];
+  // regrouping targets, read from LDS where used (kept in scalar registers
+  // they would crowd out the cell's uniform values)
+  __shared__ RegroupDst<T> ldst[REGROUP ? kMaxTiledSpecies : 1];
   LdsPtrSet<T>* const lptr = (LdsPtrSet<T>*)lptr_tab;
-  T* const scell = smem + NW * WREC;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int half = lane >> 5;
-  const int hl = lane & 31;
-  const int col = lane & 15;                    // MFMA column (class) of this lane
-  const int grp = lane >> 4;                    // MFMA k-group of this lane
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int col = lane & 15;   // MFMA column (class) of this lane
+  const int grp = lane >> 4;   // MFMA k-group of this lane
   int x0, y0, z0;
   brick_origin<TX, TY, TZ>(ntx, nty, ntz, x0, y0, z0);
 
-  for (int i = tid; i < NCELL * SCS; i += NW * 64) scell[i] = T(0);
-  for (int i = tid; i < NW * WREC; i += NW * 64) smem[i] = T(0);
+  for (int i = tid; i < NW * WREC + 2 * kSlots; i += NW * 64) smem[i] = T(0);
   fill_tables(args, lsp, lptr_tab, tid);
+  if constexpr (REGROUP) {
+#pragma unroll
+    for (int k = 0; k < kMaxTiledSpecies; ++k)
+      if (tid == 8 + k) ldst[k] = args.dst[k < args.ns ? k : 0];
+  }
   __syncthreads();
 
   T* const wrec = smem + wave * WREC;
-  // this lane's MFMA operand base: row col, slot grp (cell A) / 32 + grp (cell B)
-  const T* const opnd = wrec + col * kSlots + grp;
-  T* const stage = wrec + kStage + 24 * half;
-  // lanes 0..23 of each half stage component hl / 8 of B at corner hl % 8
-  auto load_stage = [&](const BrickCell& c) -> T {
-    T r = T(0);
-    if (hl < 24) {
+  const T* const opnd = wrec + col * kSlots + grp;   // row col, slot grp
+  T* const tcur = wrec + kTcur;                       // current class sums [27][3]
+
+  // One-cell-ahead loads, one value per lane: lanes 0..23 the cell's corner
+  // B (component l / 8, corner l % 8), lanes 0..9 its range bounds (lo, hi
+  // of slot l / 2), lanes 0..3 the regrouping starts.
+  auto load_cell = [&](const BrickCell& c, T& bv, int& rv, int& dv) {
+    bv = T(0);
+    rv = 0;
+    dv = 0;
+    const int cl = c.valid ? c.cell : 0;
+    if (lane < 24) {
       const Stencil<T> st = cell_stencil<T>(g, c);
-      r = args.Bdep[(hl >> 3) * g.nn + corner_node(g, st, hl & 7)];
+      bv = args.Bdep[(lane >> 3) * g.nn + corner_node(g, st, lane & 7)];
     }
-    return r;
+    if (lane < 2 * kSlots5) {
+      const int s = lane >> 1;
+      const int32_t* cs = s == kStraySlot ? args.ind_start : lsp[s < kMaxTiledSpecies ? s : 0].cell_start;
+      rv = gld(cs + cl + (lane & 1));
+    }
+    if constexpr (REGROUP) {
+      if (lane < kMaxTiledSpecies) dv = gld(ldst[lane].start + cl);
+    }
+  };
+  // the cell's ranges from the loaded bounds (wavefront-uniform)
+  auto cell_ranges = [&](const BrickCell& c, int rv) -> Ranges {
+    RangeLd r;
+#pragma unroll
+    for (int s = 0; s < kSlots5; ++s) {
+      r.lo[s] = __builtin_amdgcn_readlane(rv, 2 * s);
+      r.hi[s] = __builtin_amdgcn_readlane(rv, 2 * s + 1);
+    }
+    return make_ranges<T, kSlots5>(args, r, c);
   };
 
-  // Pair pipeline: while a pair of cells is processed, the next pair's cell
-  // ranges and corner fields, and then its first particle block, are loaded.
-  BrickCell pc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, 2 * wave + half);
-  T sv = load_stage(pc);
-  Ranges rg = make_ranges<T, kSlots5>(args, load_ranges<T, kSlots5>(args, lsp, pc), pc);
-  PData<T> pd = load_dep<T>(lptr, rg, hl);
-  DStart dsn{};
-  if constexpr (REGROUP) dsn = load_dstart(args, pc);
+  BrickCell cc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, wave);
+  T bv;
+  int rv, dv;
+  load_cell(cc, bv, rv, dv);
+  Ranges cr = cell_ranges(cc, rv);
+  PData<T> pd = load_dep<T>(lptr, cr, lane);
 
-  for (int pair = wave; pair < NPAIR; pair += NW) {
-    const bool has_next = pair + NW < NPAIR;   // wave-uniform
-    const BrickCell nc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, 2 * (has_next ? pair + NW : pair) + half);
-    RangeLd nrl{};
-    T nsv = T(0);
-    const DStart dsc = dsn;
-    if (has_next) {
-      nrl = load_ranges<T, kSlots5>(args, lsp, nc);
-      nsv = load_stage(nc);
-      if constexpr (REGROUP) dsn = load_dstart(args, nc);
-    }
-    const Ranges cr = rg;
-    const int lc = pc.lc;
-    const int cell = pc.cell;
-    const int cntA = __builtin_amdgcn_readfirstlane(__shfl(cr.total, 0));
-    const int cntB = __builtin_amdgcn_readfirstlane(__shfl(cr.total, 32));
-    const int cmax = cntA > cntB ? cntA : cntB;
-    if (cmax == 0) {   // wave-uniform: both cells empty
+  for (int lc = wave; lc < NCELL; lc += NW) {
+    const bool has_next = lc + NW < NCELL;   // wave-uniform
+    const BrickCell nc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, has_next ? lc + NW : lc);
+    // this cell's corner B and regrouping starts, in scalar registers
+    T Bc[24];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) Bc[i] = lane_value(bv, i);
+    int dst0[kMaxTiledSpecies];
+#pragma unroll
+    for (int s = 0; s < kMaxTiledSpecies; ++s) dst0[s] = REGROUP ? __builtin_amdgcn_readlane(dv, s) : 0;
+    // the next cell's, in flight while this cell is processed
+    T nbv = T(0);
+    int nrv = 0, ndv = 0;
+    if (has_next) load_cell(nc, nbv, nrv, ndv);
+
+    const int cell = cc.cell;   // -1: not a cell of the grid (a clipped brick)
+    const int cnt = cr.total;   // wave-uniform
+    if (cnt == 0) {
+      if (cell >= 0)
+        for (int i = lane; i < SCS; i += 64) gst(args.csum + (int64_t)cell * SCS + i, T(0));
       if (has_next) {
-        rg = make_ranges<T, kSlots5>(args, nrl, nc);
-        pd = load_dep<T>(lptr, rg, hl);
+        cr = cell_ranges(nc, nrv);
+        pd = load_dep<T>(lptr, cr, lane);
       }
-      pc = nc;
-      sv = nsv;
+      cc = nc;
+      bv = nbv;
+      rv = nrv;
+      dv = ndv;
       continue;
     }
-    // corner B of the cell, staged for the lanes of this half
-    if (hl < 24) stage[hl] = sv;
-    wave_sync();
-    // the cell's corner B in registers, read once per pair (the same values
-    // for every particle of the half's cell); the regrouping deposit, whose
-    // registers would then exceed two waves per SIMD, reads them per block
-    T Bc[24];
-    if constexpr (!REGROUP) {
+    int run[kMaxTiledSpecies] = {0, 0, 0, 0};   // regrouping: particles written per species
+    T S[2][4], C[2][4];                         // running sums [tile][reg]
 #pragma unroll
-      for (int i = 0; i < 24; ++i) Bc[i] = stage[i];
-    }
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { S[t][r] = T(0); C[t][r] = T(0); }
 
-    // regrouping: the cell's particles written so far, per species
-    int run[kMaxTiledSpecies] = {0, 0, 0, 0};
-    (void)dsc;
-    // running sums of the two cells: [cell][tile][reg]
-    T S[2][2][4], C[2][2][4];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) { S[h][t][r] = T(0); C[h][t][r] = T(0); }
-
-    // One block of 32 particles per cell: records to LDS, the next block's
-    // loads issued, then 8 matrix-core steps over the records.
-    auto block = [&](int cb, bool fresh, acc_t& dA0, acc_t& dA1, acc_t& dB0, acc_t& dB1) {
-      // ---- 1. particle lanes: one record column per lane ----
-      // Every lane runs the same arithmetic; lanes whose particle is not in
-      // the cell (or that hold none) carry zero charge, so zero values.
+    for (int cb = 0; cb < cnt; cb += 64) {
+      // ---- 1. this lane's record; lanes without a particle of the cell
+      // (past the count, or no longer in the cell) carry zero charge ----
       bool keep;
       {
         const TSpecies<T>& sp = lsp[dep_species(pd)];
         const Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
-        // in the cell: FP32 compares the stored cell index (the weights need
-        // only the offsets), FP64 the cell of the stencil
         if constexpr (sizeof(T) == 4) keep = pd.ok && pd.c == cell;
         else keep = pd.ok && ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]) == cell;
         T W[8];
 #pragma unroll
         for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
-        const Vec3<T> B1 = REGROUP ? gather_staged(W, stage) : gather_staged(W, Bc);
+        const Vec3<T> B1 = gather_staged(W, Bc);
         T r[39];
         particle_record(ps, B1, Vec3<T>{pd.v0, pd.v1, pd.v2}, keep ? dep_charge(pd, lptr) : T(0), sp, r);
 #pragma unroll
@@ -1049,20 +1350,19 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
       if constexpr (REGROUP) {
         // species by species (a block mostly holds one): the target index is
         // the cell's start for the species, the particles of the species
-        // written so far in this cell, and the lanes before this one in its
-        // half (one cell per half) taking the same species
+        // written so far in this cell, and the lanes before this one taking
+        // the same species
         const int sl = dep_species(pd);
-        const uint32_t below = (1u << hl) - 1u;
+        const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll
         for (int s = 0; s < kMaxTiledSpecies; ++s) {
           if (s < args.ns) {   // wave-uniform
             const bool mine = keep && sl == s;
             const uint64_t m = __ballot(mine);
-            const uint32_t hm = half ? (uint32_t)(m >> 32) : (uint32_t)m;
-            const int my = dsc.v[s] + run[s] + __popc(hm & below);
-            run[s] += __popc(hm);
+            const int my = dst0[s] + run[s] + __popcll(m & below);
+            run[s] += __popcll(m);
             if (m) {   // wave-uniform
-              const RegroupDst<T>& D = args.dst[s];
+              const RegroupDst<T>& D = ldst[s];
               if (mine && my >= 0 && my < D.np) {
                 gst(D.pos[0] + my, pd.x0);
                 gst(D.pos[1] + my, pd.x1);
@@ -1078,102 +1378,170 @@ __global__ void __launch_bounds__(NW * 64) k_deposit(Grid g, TArgs<T> args, int 
         }
       }
       wave_sync();
-      // prefetch the next block (of this pair, else of the next pair) while
-      // this block is reduced: one load site, so that the loads stay in
-      // flight until the next block uses them
-      const bool same = cb + 32 < cmax;   // wave-uniform
-      if (!same && has_next) rg = make_ranges<T, kSlots5>(args, nrl, nc);
-      pd = load_dep<T>(lptr, select_ranges(same, cr, rg), same ? cb + 32 + hl : hl);
-      // ---- 2. matrix cores: S[value][class] += sum over 4 particles per step ----
-      // records past a cell's count are zero; the steps past both cells'
-      // counts are skipped
-      const int nk = cmax - cb;   // wave-uniform, >= 1
+      // ---- 2. the next block's loads (this cell's, else the next cell's
+      // first), in flight while this block is reduced ----
+      const bool same = cb + 64 < cnt;   // wave-uniform
+      if (!same && has_next) cr = cell_ranges(nc, nrv);
+      pd = load_dep<T>(lptr, cr, same ? cb + 64 + lane : lane);
+      // ---- 3. matrix cores: block sums [value][class] from zero; the steps
+      // past the cell's count are skipped (their records are zero) ----
+      const int nk = cnt - cb;   // wave-uniform, >= 1
+      acc_t d0 = {0, 0, 0, 0}, d1 = {0, 0, 0, 0};
 #pragma unroll
-      for (int k4 = 0; k4 < 32; k4 += 4) {
+      for (int k4 = 0; k4 < 64; k4 += 4) {
         if (k4 > 0 && k4 >= nk) break;
-        const T aA = opnd[k4];
-        const T aB = opnd[32 + k4];
-        const T bA0 = opnd[12 * kSlots + k4];
-        const T bB0 = opnd[12 * kSlots + 32 + k4];
-        const T bA1 = opnd[28 * kSlots + k4];
-        const T bB1 = opnd[28 * kSlots + 32 + k4];
-        const acc_t z = {0, 0, 0, 0};
-        const bool f0 = fresh && k4 == 0;
-        dA0 = MF::run(aA, bA0, f0 ? z : dA0);
-        dB0 = MF::run(aB, bB0, f0 ? z : dB0);
-        dA1 = MF::run(aA, bA1, f0 ? z : dA1);
-        dB1 = MF::run(aB, bB1, f0 ? z : dB1);
-      }
-    };
-
-    // Superblocks of 64 particles per cell: the matrix cores start from zero
-    // and take up to two blocks, then the running sums take the superblock
-    // sums (FP32 with Kahan compensation).
-    for (int ch = 0; ch < cmax; ch += 64) {
-      acc_t dA0, dA1, dB0, dB1;
-      block(ch, true, dA0, dA1, dB0, dB1);
-      if (ch + 32 < cmax) {   // wave-uniform
-        wave_sync();
-        block(ch + 32, false, dA0, dA1, dB0, dB1);
+        const T a = opnd[k4];
+        const T b0 = opnd[12 * kSlots + k4];
+        const T b1 = opnd[28 * kSlots + k4];
+        d0 = MF::run(a, b0, d0);
+        d1 = MF::run(a, b1, d1);
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if constexpr (sizeof(T) == 4) {
-          kahan(S[0][0][q], C[0][0][q], dA0[q]);
-          kahan(S[0][1][q], C[0][1][q], dA1[q]);
-          kahan(S[1][0][q], C[1][0][q], dB0[q]);
-          kahan(S[1][1][q], C[1][1][q], dB1[q]);
+          kahan(S[0][q], C[0][q], d0[q]);
+          kahan(S[1][q], C[1][q], d1[q]);
         } else {
-          S[0][0][q] += dA0[q];
-          S[0][1][q] += dA1[q];
-          S[1][0][q] += dB0[q];
-          S[1][1][q] += dB1[q];
+          S[0][q] += d0[q];
+          S[1][q] += d1[q];
         }
       }
       wave_sync();
     }
 
-    // ---- 3. per-cell sums to LDS: mass-matrix classes, current classes ----
-    T* const tcur = wrec + kTcur;
+    // ---- per-cell sums to global memory: the mass-matrix classes; the
+    // current classes to LDS, from which the corner currents follow ----
+    T* const sc = args.csum + (int64_t)(cell >= 0 ? cell : 0) * SCS;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int lch = 2 * pair + h;
-      if (lch >= NCELL) continue;
-      T* sc = scell + lch * SCS;
+    for (int t = 0; t < 2; ++t) {
+      const int cls = t * 16 + col;
+      if (cls >= 27) continue;
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int cls = t * 16 + col;
-        if (cls >= 27) continue;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int row = MF::row(lane, q);
-          T v = S[h][t][q];
-          if constexpr (sizeof(T) == 4) v -= C[h][t][q];
-          if (row < 9) sc[cls * 9 + row] = v;
-          else if (row < 12) tcur[h * 84 + cls * 3 + (row - 9)] = v;
+      for (int q = 0; q < 4; ++q) {
+        const int row = MF::row(lane, q);
+        T v = S[t][q];
+        if constexpr (sizeof(T) == 4) v -= C[t][q];
+        if (row < 9) {
+          if (cell >= 0) gst(sc + cls * 9 + row, v);
+        } else if (row < 12) {
+          tcur[cls * 3 + (row - 9)] = v;
         }
       }
     }
     wave_sync();
-    // corner currents J_a = sum_b T_{a+b}: lanes 0..23 of each half
-    if (hl < 24 && lc < NCELL) {
-      const int a = hl / 3, comp = hl % 3;
+    // corner currents J_a = sum_b T_{a+b}: lanes 0..23
+    if (lane < 24 && cell >= 0) {
+      const int a = lane / 3, comp = lane % 3;
       const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
-      const T* tc = tcur + half * 84;
       T s = T(0);
 #pragma unroll
       for (int bb = 0; bb < 8; ++bb) {
         const int cls = (ax + (bb & 1)) + 3 * (ay + ((bb >> 1) & 1)) + 9 * (az + ((bb >> 2) & 1));
-        s += tc[cls * 3 + comp];
+        s += tcur[cls * 3 + comp];
       }
-      scell[lc * SCS + 243 + 3 * a + comp] = s;
+      gst(sc + 243 + 3 * a + comp, s);
     }
     wave_sync();
-    pc = nc;
-    sv = nsv;
+    cc = nc;
+    bv = nbv;
+    rv = nrv;
+    dv = ndv;
   }
-  __syncthreads();   // the per-cell sums are complete
-  flush_brick<T, TX, TY, TZ>(g, scell, x0, y0, z0, J, M, tid, NW * 64);
+}
+
+// ---------------------------------------------------------------------------
+// node flush: every node's J and 14 mass-matrix blocks from the per-cell sums
+// ---------------------------------------------------------------------------
+// Node g is corner a of the 8 cells g - a. Block k of g holds every stored
+// pair (a, a + o_k) of those cells, whose weight class 2a + o_k picks the
+// cell's class sum; the current at g is the sum of the cells' corner-a
+// currents. A workgroup owns a brick of FX x FY x FZ nodes: it stages the
+// per-cell sums of the (FX+1)(FY+1)(FZ+1) cells around them in LDS (each
+// cell's sums are contiguous, so the loads coalesce), then every (entry,
+// node) adds its at most 8 terms in FP64 and stores the rounded result once
+// (with accumulate: added to J and M). Every node has one owner: no atomics,
+// and J and M need no clearing.
+template <typename T, int FX, int FY, int FZ>
+__global__ void __launch_bounds__(256) k_flush_nodes(Grid g, const T* __restrict__ csum, T* __restrict__ J,
+                                                     T* __restrict__ M, int accumulate, int nbx, int nby, int nbz) {
+  constexpr int CX = FX + 1, CY = FY + 1, CZ = FZ + 1, NC = CX * CY * CZ;
+  constexpr int NN = FX * FY * FZ;
+  __shared__ T rec[NC * SCS];
+  __shared__ int64_t cbase[NC];
+  int x0, y0, z0;
+  brick_origin<FX, FY, FZ>(nbx, nby, nbz, x0, y0, z0);
+  const int tid = threadIdx.x;
+  // cell c = (x0 - 1 + cx, y0 - 1 + cy, z0 - 1 + cz), periodic (any number
+  // of periods: a dimension may hold fewer cells than the brick)
+  if (tid < NC) {
+    const int cx = ((x0 - 1 + tid % CX) % g.nx + g.nx) % g.nx;
+    const int cy = ((y0 - 1 + (tid / CX) % CY) % g.ny + g.ny) % g.ny;
+    const int cz = ((z0 - 1 + tid / (CX * CY)) % g.nz + g.nz) % g.nz;
+    cbase[tid] = (cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz)) * SCS;
+  }
+  __syncthreads();
+  // staged 16 values per thread at a time, all loads in flight together
+  constexpr int TOT = NC * SCS, CH = 16;
+  for (int i0 = 0; i0 < TOT; i0 += 256 * CH) {
+    T v[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int i = i0 + j * 256 + tid;
+      const int ic = i < TOT ? i : TOT - 1;
+      const int c = ic / SCS, e = ic - c * SCS;
+      v[j] = csum[cbase[c] + e];
+    }
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int i = i0 + j * 256 + tid;
+      if (i < TOT) rec[i] = v[j];
+    }
+  }
+  __syncthreads();
+  bool bad = false;
+  auto put = [&](T* o, double v) {
+    const T out = accumulate ? (T)((double)*o + v) : (T)v;
+    bad = bad || !finite(out);
+    *o = out;
+  };
+  // items (group, node): groups 0..8 the mass-matrix entry ij of all 14
+  // blocks, group 9 the three current components
+  for (int it = tid; it < 10 * NN; it += 256) {
+    const int grp = it / NN, ln = it - grp * NN;
+    const int lx = ln % FX, ly = (ln / FX) % FY, lz = ln / (FX * FY);
+    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+    if (gx >= g.nx || gy >= g.ny || gz >= g.nz) continue;   // a clipped brick
+    const int64_t gn = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
+    // the staged cell g - a is (lx + 1 - ax, ly + 1 - ay, lz + 1 - az)
+    const T* const cb = rec + ((lx + 1) + CX * ((ly + 1) + CY * (lz + 1))) * SCS;
+    if (grp < 9) {
+      const int ij = grp;
+#pragma unroll
+      for (int k = 0; k < 14; ++k) {
+        double v = 0.0;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const int cls = pair_class(k, a);
+          if (cls < 0) continue;
+          const int off = (a & 1) + CX * (((a >> 1) & 1) + CY * ((a >> 2) & 1));
+          v += (double)cb[-off * SCS + cls * 9 + ij];
+        }
+        put(M + (int64_t)(k * 9 + ij) * g.nn + gn, v);
+      }
+    } else {
+#pragma unroll
+      for (int comp = 0; comp < 3; ++comp) {
+        double v = 0.0;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const int off = (a & 1) + CX * (((a >> 1) & 1) + CY * ((a >> 2) & 1));
+          v += (double)cb[-off * SCS + 243 + 3 * a + comp];
+        }
+        put(J + (int64_t)comp * g.nn + gn, v);
+      }
+    }
+  }
+  note_nonfinite(g, bad);
 }
 
 // ---------------------------------------------------------------------------
@@ -1540,10 +1908,15 @@ struct StrayWs {
   int* scount;
   int* rscan;
   int* rsums;
+  void* csum;      // per-cell sums of the deposit, [cells][SCS]
 };
 
 
 StrayWs carve(const Grid& g, int64_t cap, size_t esz, void* ws) {
+  // the per-cell sums first: [cells][SCS] values
+  char* w0 = (char*)ws;
+  void* csum = w0;
+  ws = w0 + align256(esz * SCS * (size_t)g.nn);
   char* w = (char*)ws;
   StrayWs s;
   // the counter (hit by atomics), the zero block (read by every idle or
@@ -1586,6 +1959,7 @@ StrayWs carve(const Grid& g, int64_t cap, size_t esz, void* ws) {
   s.rscan = (int*)w;
   w += align256(sizeof(int) * (kMaxTiledSpecies * (size_t)g.nn + 1));
   s.rsums = (int*)w;
+  s.csum = csum;
   return s;
 }
 
@@ -1606,6 +1980,7 @@ TArgs<T> make_args(const Grid& g, const SpeciesArgs* sp, int ns) {
     a.s[s].inv_V = (T)(1.0 / g.V);
     a.s[s].inv_qom = 1.0 / integrated_qom(sp[s].qom, g.dt, sizeof(T) == 4);
     a.s[s].cell_start = sp[s].cell_start;
+    a.s[s].np = sp[s].np;
   }
   a.dth[0] = (T)(g.pdt[0] / g.hx);
   a.dth[1] = (T)(g.pdt[1] / g.hy);
@@ -1616,8 +1991,8 @@ TArgs<T> make_args(const Grid& g, const SpeciesArgs* sp, int ns) {
 // grouped pass (move or check) -> [stray mover] -> stray counting sort -> deposit
 template <typename T, int TX, int TY, int TZ, int NW>
 hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove, const void* Bmove,
-                 const void* Bdep, void* J, void* M, double* ke, bool move, void* ws, hipStream_t st,
-                 const SpeciesArgs* dst = nullptr) {
+                 const void* Bdep, void* J, void* M, double* ke, bool move, bool accumulate, void* ws,
+                 hipStream_t st, const SpeciesArgs* dst = nullptr) {
   const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
   const int ntiles = ntx * nty * ntz;
   int64_t cap = 0;
@@ -1633,6 +2008,7 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
   a.stray_item = w.item;
   a.stray_cell = w.cell;
   a.ke = ke;
+  a.csum = (T*)w.csum;
   a.zero = w.zero;
   a.sink = w.sink;
   a.ind_start = w.start;
@@ -1667,8 +2043,8 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
   }
   constexpr int kGroupWaves = 4;   // 4-wave workgroups: three fit a CU at the mover's register count
   if (move) {
-    hipLaunchKernelGGL((k_group<T, TX, TY, TZ, kGroupWaves, true>), dim3(ntiles), dim3(kGroupWaves * 64), 0, st, g,
-                       a, ntx, nty, ntz);
+    hipLaunchKernelGGL((k_mover<T, TX, TY, TZ, kGroupWaves>), dim3(ntiles), dim3(kGroupWaves * 64), 0, st, g, a, ntx,
+                       nty, ntz);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_move_strays<T>, dim3(1024), dim3(256), 0, st, g, a);
   } else {
@@ -1694,11 +2070,18 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
     hipLaunchKernelGGL(k_regroup_starts<T>, dim3(1024), dim3(256), 0, st, a, (const int*)w.rscan, g.nn);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((k_deposit<T, TX, TY, TZ, NW, true>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty,
-                       ntz, (T*)J, (T*)M);
+                       ntz);
   } else {
     hipLaunchKernelGGL((k_deposit<T, TX, TY, TZ, NW, false>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty,
-                       ntz, (T*)J, (T*)M);
+                       ntz);
   }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // node bricks of the flush: FP32 4 x 4 x 2 (75 staged cells, 80 KB of
+  // LDS, two workgroups per CU); FP64 4 x 2 x 2 (45 cells, 94 KB)
+  constexpr int FX = 4, FY = sizeof(T) == 4 ? 4 : 2, FZ = 2;
+  const int nbx = (g.nx + FX - 1) / FX, nby = (g.ny + FY - 1) / FY, nbz = (g.nz + FZ - 1) / FZ;
+  hipLaunchKernelGGL((k_flush_nodes<T, FX, FY, FZ>), dim3((unsigned)(nbx * nby * nbz)), dim3(256), 0, st, g,
+                     (const T*)w.csum, (T*)J, (T*)M, accumulate ? 1 : 0, nbx, nby, nbz);
   return hipGetLastError();
 }
 
@@ -1731,7 +2114,7 @@ hipError_t launch_diagnostics_tiled(const Grid& g, bool f32, const SpeciesArgs* 
 
 size_t tiled_workspace_bytes(const Grid& g, int64_t np_total, bool f32) {
   const size_t esz = f32 ? 4 : 8;
-  return 768 + 6 * align256(sizeof(int) * (size_t)np_total) + 14 * align256(esz * (size_t)np_total) +
+  return align256(esz * SCS * (size_t)g.nn) + 768 + 6 * align256(sizeof(int) * (size_t)np_total) + 14 * align256(esz * (size_t)np_total) +
          align256(sizeof(int) * (size_t)g.nn) + align256(sizeof(int) * (size_t)(g.nn + 1)) +
          align256(sizeof(int) * (size_t)scan_sums_ints(g.nn)) +
          2 * align256(sizeof(int) * kMaxTiledSpecies * (size_t)g.nn) +
@@ -1747,35 +2130,36 @@ bool tiled_species_ok(const SpeciesArgs* sp, int ns) {
 }
 
 hipError_t launch_deposit_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* B, void* J,
-                                void* M, void* ws, hipStream_t st) {
+                                void* M, bool accumulate, void* ws, hipStream_t st) {
   // single-layer (2D) grids take 8x4x1 bricks, so that no brick cell is empty
   if (g.nz == 1) {
-    if (f32) return run_T<float, 8, 4, 1, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
-    return run_T<double, 8, 4, 1, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
+    if (f32) return run_T<float, 8, 4, 1, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, accumulate, ws, st);
+    return run_T<double, 8, 4, 1, 2>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, accumulate, ws, st);
   }
-  if (f32) return run_T<float, 4, 4, 2, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
-  return run_T<double, 4, 4, 2, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, ws, st);
+  if (f32) return run_T<float, 4, 4, 2, 4>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, accumulate, ws, st);
+  return run_T<double, 4, 4, 2, 2>(g, sp, ns, nullptr, nullptr, B, J, M, nullptr, false, accumulate, ws, st);
 }
 
 hipError_t launch_move_deposit_regroup(const Grid& g, bool f32, const SpeciesArgs* sp, const SpeciesArgs* dst, int ns,
                                        const void* E, const void* B, const void* Bnext, void* J, void* M, double* ke,
-                                       void* ws, hipStream_t st) {
+                                       bool accumulate, void* ws, hipStream_t st) {
   if (g.nz == 1) {
-    if (f32) return run_T<float, 8, 4, 1, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st, dst);
-    return run_T<double, 8, 4, 1, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st, dst);
+    if (f32) return run_T<float, 8, 4, 1, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, accumulate, ws, st, dst);
+    return run_T<double, 8, 4, 1, 2>(g, sp, ns, E, B, Bnext, J, M, ke, true, accumulate, ws, st, dst);
   }
-  if (f32) return run_T<float, 4, 4, 2, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st, dst);
-  return run_T<double, 4, 4, 2, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st, dst);
+  if (f32) return run_T<float, 4, 4, 2, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, accumulate, ws, st, dst);
+  return run_T<double, 4, 4, 2, 2>(g, sp, ns, E, B, Bnext, J, M, ke, true, accumulate, ws, st, dst);
 }
 
 hipError_t launch_move_deposit(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* E, const void* B,
-                               const void* Bnext, void* J, void* M, double* ke, void* ws, hipStream_t st) {
+                               const void* Bnext, void* J, void* M, double* ke, bool accumulate, void* ws,
+                               hipStream_t st) {
   if (g.nz == 1) {
-    if (f32) return run_T<float, 8, 4, 1, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st);
-    return run_T<double, 8, 4, 1, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st);
+    if (f32) return run_T<float, 8, 4, 1, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, accumulate, ws, st);
+    return run_T<double, 8, 4, 1, 2>(g, sp, ns, E, B, Bnext, J, M, ke, true, accumulate, ws, st);
   }
-  if (f32) return run_T<float, 4, 4, 2, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st);
-  return run_T<double, 4, 4, 2, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, ws, st);
+  if (f32) return run_T<float, 4, 4, 2, 4>(g, sp, ns, E, B, Bnext, J, M, ke, true, accumulate, ws, st);
+  return run_T<double, 4, 4, 2, 2>(g, sp, ns, E, B, Bnext, J, M, ke, true, accumulate, ws, st);
 }
 
 }  // namespace ecsim

@@ -210,20 +210,33 @@ __device__ __forceinline__ Vec3<T> velocity_update(const T a[9], Vec3<T> v, Vec3
 }
 
 // The mover's step of Eqs. 3-5 from the gathered fields. In the FP32 form
-// alpha and the update are evaluated in FP64 and v^{n+1} is rounded once: the
-// map v -> (2 alpha - I) v is a rotation, but with alpha rounded to FP32 it
+// the update is evaluated in FP64 and v^{n+1} is rounded once: the map
+// v -> (2 alpha - I) v is a rotation, but with alpha rounded to FP32 it
 // scales |v| by 1 + O(1e-7), and where B is nearly uniform all particles share
 // that rounding, so the kinetic energy would drift one way every step. A single
 // rounding of the result is unbiased and averages out over the particles.
+// The FP64 evaluation writes alpha u out directly, with b = beta B:
+//   vbar = (u + u x b + b (b . u)) / (1 + |b|^2),  u = v + beta E_p,
+// and 1/(1 + |b|^2) from the hardware reciprocal refined by two Newton steps
+// (each squares the relative error, from 2^-26 to below the FP64 rounding).
+// Every FP32 mover (grouped, stray, any order) and the adjoint's recompute of
+// the push call this routine, so they move a particle identically.
 template <typename T>
 __device__ __forceinline__ Vec3<T> advance_velocity(Vec3<T> Bp, T beta, Vec3<T> v, Vec3<T> Ep) {
   if constexpr (sizeof(T) == 4) {
-    double a[9];
-    rotation(Vec3<double>{Bp.x, Bp.y, Bp.z}, (double)beta, a);
-    Vec3<double> u;
-    const Vec3<double> r =
-        velocity_update(a, Vec3<double>{v.x, v.y, v.z}, Vec3<double>{Ep.x, Ep.y, Ep.z}, (double)beta, u);
-    return Vec3<T>{(T)r.x, (T)r.y, (T)r.z};
+    const double bt = beta;
+    const double bx = bt * (double)Bp.x, by = bt * (double)Bp.y, bz = bt * (double)Bp.z;
+    const double den = fma(bx, bx, fma(by, by, fma(bz, bz, 1.0)));
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    r = fma(r, fma(-den, r, 1.0), r);
+    const double vx = v.x, vy = v.y, vz = v.z;
+    const double ux = fma(bt, (double)Ep.x, vx), uy = fma(bt, (double)Ep.y, vy), uz = fma(bt, (double)Ep.z, vz);
+    const double bu = fma(bx, ux, fma(by, uy, bz * uz));
+    const double wx = fma(bx, bu, ux + fma(uy, bz, -uz * by));
+    const double wy = fma(by, bu, uy + fma(uz, bx, -ux * bz));
+    const double wz = fma(bz, bu, uz + fma(ux, by, -uy * bx));
+    return Vec3<T>{(T)fma(2.0 * r, wx, -vx), (T)fma(2.0 * r, wy, -vy), (T)fma(2.0 * r, wz, -vz)};
   } else {
     T a[9];
     rotation(Bp, beta, a);

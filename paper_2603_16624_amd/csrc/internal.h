@@ -48,19 +48,21 @@ hipError_t launch_deposit_atomic(const Grid& g, bool f32, const SpeciesArgs* sp,
 // outside their range's cell are handled through a stray list in `ws`.
 size_t tiled_workspace_bytes(const Grid& g, int64_t np_total, bool f32);
 bool tiled_species_ok(const SpeciesArgs* sp, int ns);
+// J and M are written (accumulate: added to) by the node flush; they need
+// no clearing.
 hipError_t launch_deposit_tiled(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* B,
-                                void* J, void* M, void* ws, hipStream_t st);
+                                void* J, void* M, bool accumulate, void* ws, hipStream_t st);
 // Fused mover + deposit: moves every species with (E, B) and deposits the
 // moments at the new positions with Bnext.
 hipError_t launch_move_deposit(const Grid& g, bool f32, const SpeciesArgs* sp, int ns, const void* E,
-                               const void* B, const void* Bnext, void* J, void* M, double* ke, void* ws,
-                               hipStream_t st);
+                               const void* B, const void* Bnext, void* J, void* M, double* ke, bool accumulate,
+                               void* ws, hipStream_t st);
 // Fused mover + deposit that also regroups: each species' particles are
 // written to dst[s] in cell order (the deposit's order) and dst[s].cell_start
 // receives the ranges.
 hipError_t launch_move_deposit_regroup(const Grid& g, bool f32, const SpeciesArgs* sp, const SpeciesArgs* dst, int ns,
                                        const void* E, const void* B, const void* Bnext, void* J, void* M, double* ke,
-                                       void* ws, hipStream_t st);
+                                       bool accumulate, void* ws, hipStream_t st);
 // exclusive scan of n < 2^31 ints into out[0..n], out[n] = total; sums:
 // scratch of scan_sums_ints(n) ints
 int64_t scan_sums_ints(int64_t n);
