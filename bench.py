@@ -600,10 +600,21 @@ def four_species_2d_rate(steps=5):
     return out
 
 
+def adjoint_bytes(p, prec):
+    """Algorithmic bytes of one backward through the mover over all species: the particle state read
+    (position, velocity; FP32 also the cell) and its gradients written, the node fields E, B, gJ and
+    the 14 stored blocks of gM read, and gE, gB read and written (accumulated)."""
+    esz = 8 if prec == "f64" else 4
+    per_particle = 6 * esz + (4 if prec == "f32" else 0) + 6 * esz
+    per_node = (3 + 3 + 3 + 126) * esz + 2 * 6 * esz
+    return p.n_particles * per_particle + p.nn * per_node
+
+
 def adjoint_time():
     """Adjoint of mover -> moments (ecsim_moments_backward through the mover) on the
     32^3 x 27 ppc x 2 species workload (1,769,472 particles), FP64 and FP32: time
-    of one backward over both species."""
+    of one backward over both species, with the particles grouped by cell (the
+    brick-tiled kernel) and in any order (one thread per particle)."""
     import numpy as np
     import torch
     from paper_2603_16624_amd import ecsim as E
@@ -628,12 +639,24 @@ def adjoint_time():
         gB = torch.zeros((3, p.nn), dtype=dt, device="cuda")
         gx = [torch.empty_like(s.pos) for s in sp]
         gv = [torch.empty_like(s.vel) for s in sp]
+        grouped = []
+        for s in sp:
+            d = s.empty_like()
+            E.sort(grid, s, d, torch.empty(grid.nn + 1, dtype=torch.int32, device="cuda"))
+            grouped.append(d)
+        ws = [torch.empty(E.backward_workspace_size(grid, s.np, s.prec), dtype=torch.uint8, device="cuda") for s in sp]
 
-        def bwd():
-            for s, a, b in zip(sp, gx, gv):
-                E.moments_backward(grid, s, Ed, Bd, gJd, gMd, a, b, gE, gB, through_mover=True)
-        ms = _time_events(bwd, 5)
-        out[prec] = {"ms": ms, "particles_per_s": p.n_particles / (ms * 1e-3)}
+        def bwd(species, wss):
+            def run():
+                for s, a, b, w in zip(species, gx, gv, wss):
+                    E.moments_backward(grid, s, Ed, Bd, gJd, gMd, a, b, gE, gB, through_mover=True, ws=w)
+            return run
+        ms = _time_events(bwd(grouped, ws), 5)
+        ms_any = _time_events(bwd(sp, [None] * len(sp)), 5)
+        nbytes = adjoint_bytes(p, prec)
+        out[prec] = {"ms": ms, "particles_per_s": p.n_particles / (ms * 1e-3), "algorithmic_bytes": nbytes,
+                     "GB_per_s": nbytes / (ms * 1e-3) / 1e9, "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "any_order": {"ms": ms_any, "particles_per_s": p.n_particles / (ms_any * 1e-3)}}
     out["workload"] = f"{p.n[0]}x{p.n[1]}x{p.n[2]} cells x 27 ppc x 2 species ({p.n_particles} particles)"
     return out
 

@@ -307,12 +307,29 @@ ecsim_status ecsim_mass_apply(const ecsim_grid *grid, int32_t m_prec, const void
  * (+=) always; gE untouched without ECSIM_BWD_THROUGH_MOVER. gJ: [3][Nn],
  * gM: [14][9][Nn], in the particles' precision. Alpha and the weights are
  * recomputed, not stored.
+ * If sp->cell_start is set (particles grouped by cell ranges), a brick-tiled
+ * kernel forms each cell's table of gradient blocks once (the 36 stored corner
+ * pairs of gM summed by weight class, and gJ at the 8 corners) and handles the
+ * particles that stay in their range's cell; the others (stale grouping, or
+ * leaving the cell in the move) are listed in ws and handled one thread each,
+ * with their post-move cell's table read from ws. ws is then required: device
+ * workspace of ecsim_backward_workspace_size() bytes (else ECSIM_EWORKSPACE);
+ * without cell_start ws is unused (may be NULL). Calls that share a workspace
+ * must not overlap.
  */
 ecsim_status ecsim_moments_backward(const ecsim_grid *grid, const ecsim_particles *sp,
                                     const void *E_node, const void *B_node,
                                     const void *gJ, const void *gM, void *gpos[3],
                                     void *gvel[3], void *gE, void *gB,
-                                    uint32_t flags, void *stream);
+                                    void *ws, size_t ws_bytes, uint32_t flags, void *stream);
+
+/*
+ * Workspace of ecsim_moments_backward for np particles of precision prec
+ * grouped by cell: the list count, a list of np indices and a table of 268
+ * values per cell, in bytes. ECSIM_EINVAL for a bad grid, np < 0, an unknown
+ * precision or a NULL bytes.
+ */
+ecsim_status ecsim_backward_workspace_size(const ecsim_grid *grid, int64_t np, int32_t prec, size_t *bytes);
 
 /*
  * Counting sort of one species by cell, out of place. The paper's moment

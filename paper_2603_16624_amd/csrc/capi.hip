@@ -421,9 +421,20 @@ ecsim_status ecsim_mass_apply(const ecsim_grid* grid, int32_t m_prec, const void
   return ECSIM_OK;
 }
 
+ecsim_status ecsim_backward_workspace_size(const ecsim_grid* grid, int64_t np, int32_t prec, size_t* bytes) {
+  Grid g;
+  if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
+  if (np < 0) return fail(ECSIM_EINVAL, "ecsim_backward_workspace_size: np < 0");
+  if (prec != ECSIM_F32 && prec != ECSIM_F64) return fail(ECSIM_EINVAL, "ecsim_backward_workspace_size: bad precision %d", prec);
+  if (!bytes) return fail(ECSIM_EINVAL, "ecsim_backward_workspace_size: bytes is NULL");
+  *bytes = backward_workspace_bytes(g, np, prec == ECSIM_F32);
+  return ECSIM_OK;
+}
+
 ecsim_status ecsim_moments_backward(const ecsim_grid* grid, const ecsim_particles* sp, const void* E_node,
                                     const void* B_node, const void* gJ, const void* gM, void* gpos[3],
-                                    void* gvel[3], void* gE, void* gB, uint32_t flags, void* stream) {
+                                    void* gvel[3], void* gE, void* gB, void* ws, size_t ws_bytes, uint32_t flags,
+                                    void* stream) {
   Grid g;
   SpeciesArgs a;
   if (make_grid(grid, g) != ECSIM_OK) return ECSIM_EINVAL;
@@ -440,9 +451,15 @@ ecsim_status ecsim_moments_backward(const ecsim_grid* grid, const ecsim_particle
   if (sp->np > 0)
     for (int d = 0; d < 3; ++d)
       if (!gpos[d] || !gvel[d]) return fail(ECSIM_EINVAL, "ecsim_moments_backward: gpos/gvel[%d] is NULL", d);
+  if (a.cell_start && sp->np > 0) {
+    const size_t need = backward_workspace_bytes(g, sp->np, sp->prec == ECSIM_F32);
+    if (!ws || ws_bytes < need)
+      return fail(ECSIM_EWORKSPACE, "ecsim_moments_backward: grouped particles need a workspace of %zu bytes, %zu given",
+                  need, ws ? ws_bytes : (size_t)0);
+  }
   if (bind_flag(g, "ecsim_moments_backward") != ECSIM_OK) return ECSIM_EHIP;
   hipError_t e = launch_backward(g, sp->prec == ECSIM_F32, a, E_node, B_node, gJ, gM, gpos, gvel, gE, gB, through,
-                                 offset_grad, (hipStream_t)stream);
+                                 offset_grad, ws, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "ecsim_moments_backward");
   return ECSIM_OK;
 }

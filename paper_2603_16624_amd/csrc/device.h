@@ -2,8 +2,14 @@
 //
 // One inline routine computes each quantity -- interpolation stencil, field
 // gather, rotation matrix -- so that the mover, the moment deposit and the
-// adjoint obtain bit-identical alpha_p and W_pN for a particle (the scheme
-// conserves energy only if the mover and the moments use the same ones).
+// adjoint share them (the scheme conserves energy only if the mover and the
+// moments use the same alpha_p and W_pN). In FP64 the mover and the deposit
+// obtain bit-identical alpha_p. In FP32 they agree to rounding only: the mover
+// evaluates the velocity update in FP64 and rounds v^{n+1} once (see
+// advance_velocity), while the deposit forms alpha_p in FP32 with the charge
+// factors folded into 1/(1 + |beta B|^2). Both differences are unbiased
+// roundings of the same exact alpha_p, so the energy error they add is a
+// random walk of FP32 rounding size per particle, not a drift.
 // The library is compiled with -ffp-contract=off; fused multiply-adds appear
 // only where written explicitly.
 #pragma once
@@ -333,6 +339,20 @@ __device__ __forceinline__ int pair_block(int a, int b, bool& at_a) {
   if (oz == 0 && oy == 0) return ox == 0 ? 0 : 1;
   if (oz == 0) return 3 + ox;
   return 5 + (ox + 1) + 3 * (oy + 1);
+}
+
+// Brick origin of workgroup blockIdx.x; blocks are spread so that each XCD
+// gets contiguous bricks.
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ void brick_origin(int ntx, int nty, int ntz, int& x0, int& y0, int& z0) {
+  const int ntiles = ntx * nty * ntz;
+  int b = blockIdx.x;
+  constexpr int nxcd = 8;
+  const int per = ntiles / nxcd;
+  if (per * nxcd == ntiles) b = (b % nxcd) * per + b / nxcd;
+  x0 = (b % ntx) * TX;
+  y0 = ((b / ntx) % nty) * TY;
+  z0 = (b / (ntx * nty)) * TZ;
 }
 
 }  // namespace ecsim

@@ -115,8 +115,13 @@ hipError_t launch_scale_copy(int64_t n, double a, const double* x, double* y, hi
 hipError_t launch_sumsq(const double* x, int64_t n, double scale, double* partial, double* out, bool accumulate,
                         hipStream_t st);
 
+// Adjoint of (mover ->) moments of one species. With sp.cell_start the
+// brick-tiled kernel runs, and ws (backward_workspace_bytes) holds the list of
+// particles it leaves to the list kernel and every cell's table; without it
+// one thread per particle reads every grid value from memory.
+size_t backward_workspace_bytes(const Grid& g, int64_t np, bool f32);
 hipError_t launch_backward(const Grid& g, bool f32, const SpeciesArgs& sp, const void* E, const void* B,
                            const void* gJ, const void* gM, void* const gpos[3], void* const gvel[3], void* gE,
-                           void* gB, bool through_mover, bool offset_grad, hipStream_t st);
+                           void* gB, bool through_mover, bool offset_grad, void* ws, hipStream_t st);
 
 }  // namespace ecsim

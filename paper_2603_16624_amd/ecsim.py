@@ -69,7 +69,8 @@ def lib():
             "ecsim_diagnostics": [P, P, ctypes.c_int32, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32, P],
             "ecsim_diagnostics_workspace_size": [P, ctypes.c_int32, ctypes.c_uint32, P],
             "ecsim_mass_apply": [P, ctypes.c_int32, P, P, ctypes.c_double, ctypes.c_double, P, P],
-            "ecsim_moments_backward": [P, P, P, P, P, P, P, P, P, P, ctypes.c_uint32, P],
+            "ecsim_moments_backward": [P, P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, ctypes.c_uint32, P],
+            "ecsim_backward_workspace_size": [P, ctypes.c_int64, ctypes.c_int32, P],
             "ecsim_sort": [P, P, P, P, P, P, ctypes.c_size_t, P],
             "ecsim_centres_to_nodes": [P, P, P, P, P],
             "ecsim_to_f32": [ctypes.c_int64, P, P, P],
@@ -91,7 +92,7 @@ def lib():
 EXPORTED = ["ecsim_last_error", "ecsim_version", "ecsim_workspace_size", "ecsim_species_qom", "ecsim_move", "ecsim_moments",
             "ecsim_move_moments", "ecsim_move_moments_noalloc", "ecsim_move_moments_regroup", "ecsim_diagnostics",
             "ecsim_diagnostics_workspace_size",
-            "ecsim_mass_apply", "ecsim_moments_backward", "ecsim_sort", "ecsim_centres_to_nodes", "ecsim_to_f32",
+            "ecsim_mass_apply", "ecsim_moments_backward", "ecsim_backward_workspace_size", "ecsim_sort", "ecsim_centres_to_nodes", "ecsim_to_f32",
             "ecsim_solve_workspace_size", "ecsim_field_solve", "ecsim_field_energy", "ecsim_check_finite",
             "ecsim_nonfinite_read"]
 
@@ -322,19 +323,32 @@ def mass_apply(grid: Grid, M: torch.Tensor, x: torch.Tensor, y: torch.Tensor, a:
                                   _stream(stream)))
 
 
+def backward_workspace_size(grid: Grid, np_: int, prec: int) -> int:
+    """Workspace bytes of moments_backward for np_ grouped particles (ecsim_backward_workspace_size)."""
+    out = ctypes.c_size_t()
+    _check(lib().ecsim_backward_workspace_size(ctypes.byref(grid.c()), int(np_), int(prec), ctypes.byref(out)))
+    return out.value
+
+
 def moments_backward(grid: Grid, sp: Species, E: Optional[torch.Tensor], B: torch.Tensor, gJ: torch.Tensor,
                      gM: torch.Tensor, gpos: torch.Tensor, gvel: torch.Tensor, gE: Optional[torch.Tensor],
-                     gB: torch.Tensor, through_mover: bool = True, offset_grad: bool = False, stream=None):
+                     gB: torch.Tensor, through_mover: bool = True, offset_grad: bool = False,
+                     ws: Optional[torch.Tensor] = None, stream=None):
     """Adjoint of (mover ->) moments; gpos, gvel (3, np) overwritten, gE, gB (3, Nn) accumulated.
-    offset_grad (FP32 particles): gpos with respect to the in-cell offsets instead of the positions."""
+    offset_grad (FP32 particles): gpos with respect to the in-cell offsets instead of the positions.
+    A species with cell_start takes the brick-tiled kernel (its workspace is allocated if not given)."""
     esz = gpos.element_size()
     n = sp.np
     gp = (ctypes.c_void_p * 3)(*[gpos.data_ptr() + d * n * esz if n else None for d in range(3)])
     gv = (ctypes.c_void_p * 3)(*[gvel.data_ptr() + d * n * esz if n else None for d in range(3)])
     flags = (BWD_THROUGH_MOVER if through_mover else 0) | (BWD_OFFSET_GRAD if offset_grad else 0)
+    if ws is None and sp.cell_start is not None:
+        ws = torch.empty(backward_workspace_size(grid, n, sp.prec), dtype=torch.uint8, device=gpos.device)
+    nbytes = 0 if ws is None else ws.numel() * ws.element_size()
     c = sp.c()
     _check(lib().ecsim_moments_backward(ctypes.byref(grid.c()), ctypes.byref(c), _ptr(E), _ptr(B), _ptr(gJ),
-                                        _ptr(gM), gp, gv, _ptr(gE), _ptr(gB), flags, _stream(stream)))
+                                        _ptr(gM), gp, gv, _ptr(gE), _ptr(gB), _ptr(ws), nbytes, flags,
+                                        _stream(stream)))
 
 
 def sort(grid: Grid, src: Species, dst: Species, cell_start: torch.Tensor, perm: Optional[torch.Tensor] = None,

@@ -159,11 +159,31 @@ def test_sort_and_backward_validation(E):
     gp = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
     # through the mover without E
     st = L.ecsim_moments_backward(ctypes.byref(g), ctypes.byref(p), None, fake, fake, fake, gp, gp, fake, fake,
-                                  E.BWD_THROUGH_MOVER, None)
+                                  None, 0, E.BWD_THROUGH_MOVER, None)
     assert st == E.EINVAL
     st = L.ecsim_moments_backward(ctypes.byref(g), ctypes.byref(p), fake, fake, fake, fake, gp, gp, fake, fake,
-                                  0x40, None)
+                                  None, 0, 0x40, None)
     assert st == E.EINVAL
+    # grouped particles (cell_start) need the workspace of the tiled kernel:
+    # the list count, a list entry per particle and a 268-value table per cell
+    need = ctypes.c_size_t(0)
+    assert L.ecsim_backward_workspace_size(ctypes.byref(g), p.np, p.prec, ctypes.byref(need)) == E.OK
+    assert need.value >= 256 + 4 * p.np + 268 * 8 * 64
+    need32 = ctypes.c_size_t(0)
+    assert L.ecsim_backward_workspace_size(ctypes.byref(g), p.np, E.F32, ctypes.byref(need32)) == E.OK
+    assert 268 * 4 * 64 <= need32.value < need.value
+    assert L.ecsim_backward_workspace_size(ctypes.byref(g), -1, p.prec, ctypes.byref(need)) == E.EINVAL
+    assert L.ecsim_backward_workspace_size(ctypes.byref(g), p.np, 7, ctypes.byref(need)) == E.EINVAL
+    assert L.ecsim_backward_workspace_size(ctypes.byref(g), p.np, p.prec, None) == E.EINVAL
+    assert L.ecsim_backward_workspace_size(None, p.np, p.prec, ctypes.byref(need)) == E.EINVAL
+    L.ecsim_backward_workspace_size(ctypes.byref(g), p.np, p.prec, ctypes.byref(need))
+    p.cell_start = ctypes.c_void_p(0x5000)
+    st = L.ecsim_moments_backward(ctypes.byref(g), ctypes.byref(p), fake, fake, fake, fake, gp, gp, fake, fake,
+                                  fake, need.value - 1, E.BWD_THROUGH_MOVER, None)
+    assert st == E.EWORKSPACE
+    st = L.ecsim_moments_backward(ctypes.byref(g), ctypes.byref(p), fake, fake, fake, fake, gp, gp, fake, fake,
+                                  None, need.value, E.BWD_THROUGH_MOVER, None)
+    assert st == E.EWORKSPACE
 
 
 def test_diagnostics_argument_validation(E):
@@ -301,6 +321,6 @@ def test_offset_gradient_flag_needs_fp32(E):
     gp = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
     p = _particles(E)   # FP64
     st = L.ecsim_moments_backward(ctypes.byref(g), ctypes.byref(p), fake, fake, fake, fake, gp, gp, fake, fake,
-                                  E.BWD_THROUGH_MOVER | E.BWD_OFFSET_GRAD, None)
+                                  None, 0, E.BWD_THROUGH_MOVER | E.BWD_OFFSET_GRAD, None)
     assert st == E.EINVAL
     assert b"OFFSET_GRAD" in L.ecsim_last_error()

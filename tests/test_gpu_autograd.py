@@ -81,3 +81,48 @@ def test_autograd_move_moments(A, O, prec, n, ppc):
     assert rel(host(gvel), gvo) < tol
     assert rel(host(gE), gEo) < tol
     assert rel(host(gB), gBo) < tol
+
+
+def test_gradcheck_small_grid(A):
+    """torch.autograd.gradcheck of the FP64 mover -> moments (3^3 grid, 20
+    particles, perturbed fields): the hand-written adjoint's vector-Jacobian
+    products against torch's central differences of the library's forward,
+    for the positions, the velocities and the grid fields E and B. Particles
+    within 1e-4 of a cell face before or after the move are redrawn (the
+    weights have kinks there)."""
+    from paper_2603_16624_amd import ecsim as E
+    say("gradcheck 3^3 x 20 particles")
+    n, h, dt = (3, 3, 3), (0.5, 0.5, 0.5), 0.1
+    L = np.array([n[d] * h[d] for d in range(3)])
+    rng = np.random.default_rng(4800)
+    nn = 27
+    En = 1e-2 * rng.standard_normal((3, nn))
+    BN = np.array([[0.02], [0.05], [0.2]]) + 0.05 * rng.standard_normal((3, nn))
+    grid = E.Grid(n, h, dt)
+    qom, q = -1.0, 3.7e-4
+
+    def clear_of_faces(x, v):
+        from oracle import oracle as O
+        x1, _ = O.move(n, h, dt, x, v, qom, En, BN)
+        ok = np.ones(x.shape[1], dtype=bool)
+        for pos in (x, x1):
+            xi = pos / np.asarray(h)[:, None]
+            frac = xi - np.floor(xi)
+            ok &= np.all((frac > 1e-4) & (frac < 1 - 1e-4), axis=0)
+        return ok
+
+    x = np.zeros((3, 0))
+    v = np.zeros((3, 0))
+    while x.shape[1] < 20:
+        xc = rng.random((3, 64)) * L[:, None]
+        vc = 0.3 * rng.standard_normal((3, 64))
+        keep = clear_of_faces(xc, vc)
+        x = np.concatenate([x, xc[:, keep]], axis=1)
+        v = np.concatenate([v, vc[:, keep]], axis=1)
+    x, v = x[:, :20], v[:, :20]
+    pos = dev(x).requires_grad_()
+    vel = dev(v).requires_grad_()
+    Et = dev(En).requires_grad_()
+    Bt = dev(BN).requires_grad_()
+    fn = lambda p_, v_, e_, b_: A.move_moments(grid, qom, q, p_, v_, e_, b_)
+    assert torch.autograd.gradcheck(fn, (pos, vel, Et, Bt), eps=1e-6, atol=1e-8, rtol=1e-5)

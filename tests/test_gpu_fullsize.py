@@ -147,6 +147,60 @@ def test_fused_pass_full_size_sampled(E, O, plasma, prec):
     assert rel(Mg[:, :, nodes], Mo[:, :, nodes]) < tol
 
 
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fused_pass_full_size_every_node(E, O, plasma, prec):
+    """One fused pass (ecsim_move_moments on a fresh cell grouping, as the
+    benchmark's pass after a regrouping) at the benchmark size: J-hat and the
+    14 stored blocks at every one of the 262,144 nodes against the oracle's
+    particle pass over all 33,554,432 particles (mover, then the moments at
+    the moved positions with B_next; the oracle on host threads with
+    thread-private grids)."""
+    import os
+    from paper_2603_16624_amd import inputs as I
+    p = plasma
+    say("full-size pass, every node", prec, p.name)
+    En, BN, Bnext = node_fields(p)
+    grid = E.Grid(p.n, p.h, p.dt)
+    if prec == "f64":
+        sp = [E.Species.from_f64(s.qom, s.x, s.v, s.q) for s in p.species]
+        xs, vs, qs = [s.x for s in p.species], [s.v for s in p.species], [s.q for s in p.species]
+        Ec, Bc, Bnc = En, BN, Bnext
+        tdt = torch.float64
+    else:
+        st = I.to_f32_state(p)
+        sp = [E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"]) for s, f in zip(p.species, st)]
+        xs, vs, qs = [f["x64"] for f in st], [f["v64"] for f in st], [f["q64"] for f in st]
+        Ec, Bc, Bnc = round32(En), round32(BN), round32(Bnext)
+        tdt = torch.float32
+        del st
+    grouped = []
+    for s in sp:
+        d = s.empty_like()
+        E.sort(grid, s, d, torch.empty(grid.nn + 1, dtype=torch.int32, device="cuda"))
+        grouped.append(d)
+    del sp
+    J = torch.empty((3, p.nn), dtype=tdt, device="cuda")
+    M = torch.empty((14, 9, p.nn), dtype=tdt, device="cuda")
+    E.move_moments(grid, grouped, dev(Ec, tdt), dev(Bc, tdt), dev(Bnc, tdt), J, M)
+    Jg, Mg = host(J), host(M)
+    del grouped, J, M
+    torch.cuda.empty_cache()
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    Jo = np.zeros((3, p.nn))
+    M27 = np.zeros((27, 9, p.nn))
+    for s, x, v, q in zip(p.species, xs, vs, qs):
+        _, _, Jo, M27, used = O.move_moments_threads(p.n, p.h, p.dt, x, v, q, s.qom, Ec, Bc, Bnc, Jo, M27,
+                                                     threads)
+    say("oracle threads", used)
+    Mo = O.m14(p.n, M27)
+    del M27
+    ej, em = rel(Jg, Jo), rel(Mg, Mo)
+    say("every node: J", ej, "M", em)
+    assert ej < TOL[prec]
+    assert em < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_energy_conservation_full_size(E, O, plasma, prec):
     """Ten steps (the regrouping fused pass) at 64^3 x 64 ppc x 2 species: the

@@ -6,6 +6,8 @@ results non-deterministic at the rounding level, so bit-exactness is not
 asked for; FP32 inputs are compared against the oracle fed the same FP32
 values widened exactly to FP64.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -201,6 +203,55 @@ def test_moments_sorted_tiled(E, O, I, n, ppc, prec):
     Jo, Mo = oracle_moments(O, p, xs, vs, qs, B)
     assert rel(host(J), Jo) < tol
     assert rel(host(M), Mo) < tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,shift", [((9, 7, 6), (1, 2, 1)), ((8, 8, 4), (3, 1, 1)), ((10, 6, 1), (5, 3, 0))])
+def test_deposit_invariant_under_brick_placement(E, O, I, prec, n, shift):
+    """The tiled deposit does not depend on where the bricks of its
+    workgroups, the cells of its wavefronts or their list packing fall: the
+    plasma and the deposit field translated by whole cells (periodic; grids
+    that are not multiples of the brick, so the bricks are clipped
+    differently) give J and M translated by the same cells, within the parity
+    tolerance (only the order of summation differs). In the FP32 form each
+    particle keeps its in-cell offsets, so its record is bit for bit the same."""
+    say("translation invariance", prec, n, shift)
+    p, _, BN = make_case(I, n, 20, 41)
+    grid = E.Grid(p.n, p.h, p.dt)
+    nx, ny, nz = p.n
+
+    def roll_nodes(F):
+        a = np.asarray(F).reshape(F.shape[:-1] + (nz, ny, nx))
+        a = np.roll(a, (shift[2], shift[1], shift[0]), axis=(-3, -2, -1))
+        return a.reshape(F.shape)
+
+    def deposit(xs_abs, B):
+        if prec == "f64":
+            sp = [E.Species.from_f64(s.qom, x, s.v, s.q) for s, x in zip(p.species, xs_abs)]
+            tdt = torch.float64
+        else:
+            sp = []
+            for s, x in zip(p.species, xs_abs):
+                cell, off = I.encode_f32(x, p.n, p.h)
+                sp.append(E.Species.from_f32(s.qom, cell, off, np.asarray(s.v, np.float32).astype(np.float64),
+                                             np.asarray(s.q, np.float32).astype(np.float64) if np.ndim(s.q)
+                                             else float(np.float32(s.q))))
+            tdt = torch.float32
+        sp = sorted_species(E, grid, sp)
+        J = torch.empty((3, p.nn), dtype=tdt, device="cuda")
+        M = torch.empty((14, 9, p.nn), dtype=tdt, device="cuda")
+        E.moments(grid, sp, dev(B, tdt), J, M, flags=E.SORTED)
+        return host(J), host(M)
+
+    B = BN if prec == "f64" else round32(BN)
+    xs = [s.x for s in p.species]
+    J0, M0 = deposit(xs, B)
+    L = np.asarray(p.L)[:, None]
+    xs1 = [np.mod(x + np.asarray(shift)[:, None] * np.asarray(p.h)[:, None], L) for x in xs]
+    J1, M1 = deposit(xs1, roll_nodes(B))
+    tol = TOL64 if prec == "f64" else TOL32
+    assert rel(J1, roll_nodes(J0)) < tol
+    assert rel(M1, roll_nodes(M0)) < tol
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -809,6 +860,59 @@ def test_backward_particle_order(E, O, I, prec, order):
     assert rel(host(gB), gBo) < tol
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,ppc,vscale,stale,through", [
+    ((6, 5, 4), 9, 1.0, False, True), ((6, 5, 4), 9, 30.0, False, True), ((6, 5, 4), 9, 3.0, True, True),
+    ((9, 5, 1), 12, 5.0, False, True), ((3, 1, 2), 5, 5.0, False, True), ((8, 8, 4), 27, 1.0, False, True)])
+def test_backward_grouped_matches_dual_oracle(E, O, I, prec, n, ppc, vscale, stale, through):
+    """The brick-tiled adjoint (particles grouped by cell: every cell's
+    gradient blocks formed once in LDS) against the oracle's dual-number
+    gradient. Scaled velocities send particles out of their cell in the move,
+    and a stale grouping (the particles moved once after the grouping) leaves
+    particles outside their range's cell: both go through the listed general
+    path. (Without the mover: test_backward_moments_only_matches_fd.)"""
+    say("backward grouped", prec, n, ppc, vscale, stale, through)
+    p, En, BN, gJ, gM = grad_case(I, n, ppc, 31)
+    for sp_ in p.species:
+        sp_.v = sp_.v * vscale
+    grid = E.Grid(p.n, p.h, p.dt)
+    tdt, tol = (torch.float64, TOL64) if prec == "f64" else (torch.float32, TOL32)
+    Ec, Bc, gJc, gMc = (En, BN, gJ, gM) if prec == "f64" else (round32(En), round32(BN), round32(gJ), round32(gM))
+    gE = torch.zeros((3, p.nn), dtype=tdt, device="cuda")
+    gB = torch.zeros((3, p.nn), dtype=tdt, device="cuda")
+    gEo = np.zeros((3, p.nn))
+    gBo = np.zeros((3, p.nn))
+    states = I.to_f32_state(p) if prec == "f32" else [None] * len(p.species)
+    for s, f in zip(p.species, states):
+        if f is None:
+            sp = E.Species.from_f64(s.qom, s.x, s.v, s.q)
+        else:
+            sp = E.Species.from_f32(s.qom, f["cell"], f["off"], f["v"], f["q"])
+        d = sp.empty_like()
+        cs = torch.empty(grid.nn + 1, dtype=torch.int32, device="cuda")
+        perm = torch.empty(sp.np, dtype=torch.int32, device="cuda")
+        E.sort(grid, sp, d, cs, perm)
+        d.cell_start = cs
+        if stale:   # the grouping goes stale: one move with small fields
+            E.move(grid, d, dev(0.1 * Ec, tdt), dev(Bc, tdt))
+        if f is None:
+            xs, vs = host(d.pos), host(d.vel)
+            qs = s.q[host(perm).astype(np.int64)]
+        else:
+            xs = I.decode_f32(host(d.cell), host(d.pos), p.n, p.h)
+            vs = host(d.vel).astype(np.float64)
+            qs = f["q64"][host(perm).astype(np.int64)]
+        gx = torch.empty_like(d.pos)
+        gv = torch.empty_like(d.vel)
+        E.moments_backward(grid, d, dev(Ec, tdt), dev(Bc, tdt), dev(gJc, tdt), dev(gMc, tdt), gx, gv, gE, gB,
+                           through_mover=True)
+        gxo, gvo, _, _ = O.grad(p.n, p.h, p.dt, xs, vs, qs, s.qom, Ec, Bc, gJc, gMc, gEo, gBo)
+        assert rel(host(gx), gxo) < tol
+        assert rel(host(gv), gvo) < tol
+    assert rel(host(gE), gEo) < tol
+    assert rel(host(gB), gBo) < tol
+
+
 def test_backward_f32_matches_dual_oracle(E, O, I):
     say("backward f32")
     p, En, BN, gJ, gM = grad_case(I, (5, 4, 4), 4, 14)
@@ -831,13 +935,25 @@ def test_backward_f32_matches_dual_oracle(E, O, I):
     assert rel(host(gB), gBo) < TOL32
 
 
-def test_backward_moments_only_matches_fd(E, O, I):
-    """Without the mover: dL/dx, dL/dv of <gJ,J> + <gM,M> by central differences of the oracle's moments."""
-    say("backward moments-only")
+@pytest.mark.parametrize("grouped", [False, True])
+def test_backward_moments_only_matches_fd(E, O, I, grouped):
+    """Without the mover: dL/dx, dL/dv of <gJ,J> + <gM,M> by central differences of the oracle's moments,
+    for particles in any order and grouped by cell (the brick-tiled kernel); dL/dB at sampled nodes by
+    central differences of the whole loss."""
+    say("backward moments-only", "grouped" if grouped else "any order")
     p, En, BN, gJ, gM = grad_case(I, (4, 4, 3), 2, 15)
     grid = E.Grid(p.n, p.h, p.dt)
     s = p.species[0]
     sp = E.Species.from_f64(s.qom, s.x, s.v, s.q)
+    if grouped:
+        d = sp.empty_like()
+        cs = torch.empty(grid.nn + 1, dtype=torch.int32, device="cuda")
+        perm = torch.empty(sp.np, dtype=torch.int32, device="cuda")
+        E.sort(grid, sp, d, cs, perm)
+        d.cell_start = cs
+        sp = d
+        k = host(perm).astype(np.int64)
+        s = dataclasses.replace(s, x=s.x[:, k], v=s.v[:, k], q=s.q[k])
     gx = torch.empty_like(sp.pos)
     gv = torch.empty_like(sp.vel)
     gB = torch.zeros((3, p.nn), dtype=torch.float64, device="cuda")
@@ -847,6 +963,18 @@ def test_backward_moments_only_matches_fd(E, O, I):
     def loss_one(x, v, i):
         J, M27 = O.moments(p.n, p.h, p.dt, x[:, i:i + 1], v[:, i:i + 1], s.q[i:i + 1], s.qom, BN)
         return np.sum(gJ * J) + np.sum(gM * O.m14(p.n, M27))
+
+    def loss_all(B):
+        J, M27 = O.moments(p.n, p.h, p.dt, s.x, s.v, s.q, s.qom, B)
+        return np.sum(gJ * J) + np.sum(gM * O.m14(p.n, M27))
+
+    gBh = host(gB)
+    for node in range(0, p.nn, max(1, p.nn // 6)):
+        for c in range(3):
+            up = BN.copy(); up[c, node] += 1e-6
+            dn = BN.copy(); dn[c, node] -= 1e-6
+            fd = (loss_all(up) - loss_all(dn)) / 2e-6
+            assert abs(gBh[c, node] - fd) <= 1e-6 * max(np.max(np.abs(gBh)), 1e-30)
 
     eps = 1e-6
     for i in range(0, s.np, max(1, s.np // 12)):
