@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--no-error", action="store_true", help="skip the FP32-vs-FP64 error measurement")
     ap.add_argument("--calib-copy", action="store_true", help="end with a 1 GiB device copy (byte-counter reference)")
     ap.add_argument("--no-extras", action="store_true", help="skip the apply and adjoint timings")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the adjoint timing (32^3 x 27 ppc x 2 species), printed as one JSON line")
     ap.add_argument("--path", choices=("fused", "split"), default="fused",
                     help="fused: one mover+moments kernel; split: mover, then the tiled deposit")
     return ap.parse_args()
@@ -676,6 +678,9 @@ def main():
     if not os.path.exists(E.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_time()}), flush=True)
+        return
     t0 = time.perf_counter()
     plasma = I.config1(ppc=args.ppc, n=(args.n, args.n, args.n))
     print(f"[bench] workload generated in {time.perf_counter() - t0:.1f} s: {plasma.name}", file=sys.stderr,

@@ -19,6 +19,10 @@ namespace ecsim {
 namespace {
 
 constexpr int kBlock = 256;
+// The list kernel's few wavefronts are latency-bound (dependent gathers, then
+// 72 scattered atomics per particle): one wavefront per workgroup spreads them
+// over all compute units.
+constexpr int kListBlock = 64;
 
 // Adds v[0..NC) of every lane to dst[c][key] (key < 0: nothing). Lanes with
 // equal keys in a contiguous run of the wavefront (cell-sorted particles
@@ -58,6 +62,8 @@ struct BwdArgs {
   const T *v0, *v1, *v2;
   const T* q;
   T q_const, beta, dth0, dth1, dth2;
+  T inv_V, beta_V;             // 1 / V and beta / V (cell volume V)
+  T inv_h[3];                  // 1 / h per dimension
   const T *E, *B, *gJ, *gM;
   T *gx0, *gx1, *gx2, *gv0, *gv1, *gv2;
   T *gE, *gB;
@@ -145,7 +151,11 @@ __device__ __forceinline__ void backward_particle(const BwdArgs<T>& A, int p, bo
   T ga1[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) ga1[i] = T(0);
+  // one corner a per step: its pairs' loads in flight together, without the
+  // register pressure of all 36 pairs at once
+#pragma unroll 1
   for (int ca = 0; ca < 8; ++ca) {
+#pragma unroll
     for (int cb = ca; cb < 8; ++cb) {
       bool at_a;
       int k = pair_block(ca, cb, at_a);
@@ -271,6 +281,9 @@ __global__ void __launch_bounds__(kBlock) k_backward(BwdArgs<T> A) {
 // with G_c the sum of gM over the cell's pairs of class c (27 blocks of 9).
 // The table of cell c holds G_c and gJ at its corners: kGS values, G first.
 constexpr int kGS = 268;   // 27 x 9 + 8 x 3 + 1 pad (16-byte rows in FP32 and FP64)
+// In LDS the tables sit kGL apart: an odd stride puts the same value of the
+// wavefront's 8 cells (local cells 4 apart) in distinct banks.
+constexpr int kGL = 269;
 
 // The grid-gradient sources of one particle: pre-move corners a take
 // W0_a gE_p and W0_a gB_p, post-move corners W1_a gB'_p (W1 from the
@@ -284,15 +297,15 @@ struct GridSrc {
 // The adjoint of one particle from its pre-move stencil s0, velocity v and
 // charge qp. pre(a, k): value k (E x, y, z, then B x, y, z) at pre-move
 // corner a. post_of(s1, c1): the post-move cell's accessor, with B(a, k) at
-// its corner a (k = 0..2) and G, its table. Returns the particle's gradients
+// its corner a (k = 0..2) and G, its table (FROM_MEMORY: in global memory,
+// else in LDS). Returns the particle's gradients
 // (position gradient per unit length) and its grid-gradient sources; c1 is
 // the post-move cell.
-template <typename T, bool CELL, bool THROUGH, class Pre, class PostOf>
+template <typename T, bool CELL, bool THROUGH, bool FROM_MEMORY, class Pre, class PostOf>
 __device__ __forceinline__ void adjoint_core(const BwdArgs<T>& A, const Stencil<T>& s0, T xa, T xb, T xc, Vec3<T> v,
                                              T qp, Pre pre, PostOf post_of, Vec3<T>& gx, Vec3<T>& gv,
                                              GridSrc<T>& src, int& c1) {
   const Grid& g = A.g;
-  const T h[3] = {T(g.hx), T(g.hy), T(g.hz)};
   // ---- forward recompute ----
   T W0[8];
 #pragma unroll
@@ -330,9 +343,8 @@ __device__ __forceinline__ void adjoint_core(const BwdArgs<T>& A, const Stencil<
   src.s1 = s1;
   const auto post = post_of(s1, c1);
   // ---- moments at the post-move state ----
-  const T V = T(g.V);
-  const T cj = qp / V;
-  const T cm = (qp * A.beta) / V;
+  const T cj = qp * A.inv_V;
+  const T cm = qp * A.beta_V;
   T W1[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) W1[a] = corner_weight(s1, a);
@@ -346,8 +358,9 @@ __device__ __forceinline__ void adjoint_core(const BwdArgs<T>& A, const Stencil<
   T a1[9];
   rotation(B1, A.beta, a1);
   const Vec3<T> vh = matvec(a1, vn);
-  // the corner fields are read again below rather than held in registers
-  asm volatile("" ::: "memory");
+  // from LDS the corner fields are read again below rather than held in
+  // registers
+  if constexpr (!FROM_MEMORY) asm volatile("" ::: "memory");
   const T* const G = post.G;
   // J part: dL/dvhat and dL/dW'_a
   T gW1[8];
@@ -378,9 +391,8 @@ __device__ __forceinline__ void adjoint_core(const BwdArgs<T>& A, const Stencil<
 #pragma unroll
   for (int ij = 0; ij < 9; ++ij) H[ij] = T(0);
   T gxi1[3] = {T(0), T(0), T(0)};
-  // one row (cy, cz) of three classes per iteration
-#pragma unroll 1
-  for (int row = 0; row < 9; ++row) {
+  // one row (cy, cz) of three classes per step
+  auto class_row = [&](int row) {
     const int cy = row % 3, cz = row / 3;
     const T fy = cy == 0 ? f[1][0] : (cy == 1 ? f[1][1] : f[1][2]);
     const T dy = cy == 0 ? df[1][0] : (cy == 1 ? df[1][1] : df[1][2]);
@@ -402,6 +414,15 @@ __device__ __forceinline__ void adjoint_core(const BwdArgs<T>& A, const Stencil<
       gxi1[1] = fma(D, (f[0][cx] * dy) * fz, gxi1[1]);
       gxi1[2] = fma(D, mxy * dz, gxi1[2]);
     }
+  };
+  if constexpr (FROM_MEMORY) {
+    // the table in global memory: every load issued up front
+#pragma unroll
+    for (int row = 0; row < 9; ++row) class_row(row);
+  } else {
+    // the table in LDS: a rolled loop keeps the registers for occupancy
+#pragma unroll 1
+    for (int row = 0; row < 9; ++row) class_row(row);
   }
   T ga1[9];
   const T vv[3] = {vn.x, vn.y, vn.z};
@@ -418,15 +439,17 @@ __device__ __forceinline__ void adjoint_core(const BwdArgs<T>& A, const Stencil<
   for (int a = 0; a < 8; ++a) gW1[a] += (post.B(a, 0) * src.gB1.x + post.B(a, 1) * src.gB1.y) + post.B(a, 2) * src.gB1.z;
   T gxiw[3];
   weight_grad(s1, gW1, gxiw);
-  gx = Vec3<T>{(cm * gxi1[0] + gxiw[0]) / h[0], (cm * gxi1[1] + gxiw[1]) / h[1], (cm * gxi1[2] + gxiw[2]) / h[2]};
+  // gradients with respect to the offsets xi (d/dx = (1/h) d/dxi)
+  T go[3] = {fma(cm, gxi1[0], gxiw[0]), fma(cm, gxi1[1], gxiw[1]), fma(cm, gxi1[2], gxiw[2])};
   gv = gvn;
   src.gEp = Vec3<T>{T(0), T(0), T(0)};
   src.gBp = Vec3<T>{T(0), T(0), T(0)};
   if constexpr (THROUGH) {
-    // x' = x + dt v' (no push along a dimension of one cell)
-    gvn.x += T(g.pdt[0]) * gx.x;
-    gvn.y += T(g.pdt[1]) * gx.y;
-    gvn.z += T(g.pdt[2]) * gx.z;
+    // x' = x + dt v', i.e. xi' = xi + (dt / h) v' (no push along a dimension
+    // of one cell)
+    gvn.x = fma(A.dth0, go[0], gvn.x);
+    gvn.y = fma(A.dth1, go[1], gvn.y);
+    gvn.z = fma(A.dth2, go[2], gvn.z);
     // v' = 2 vbar - v, vbar = alpha u, u = v + beta E_p
     const Vec3<T> gvb{T(2) * gvn.x, T(2) * gvn.y, T(2) * gvn.z};
     gv = Vec3<T>{-gvn.x, -gvn.y, -gvn.z};
@@ -451,15 +474,12 @@ __device__ __forceinline__ void adjoint_core(const BwdArgs<T>& A, const Stencil<
                ((pre(a, 3) * src.gBp.x + pre(a, 4) * src.gBp.y) + pre(a, 5) * src.gBp.z);
     T gxi0[3];
     weight_grad(s0, gW0, gxi0);
-    gx.x += gxi0[0] / h[0];
-    gx.y += gxi0[1] / h[1];
-    gx.z += gxi0[2] / h[2];
+    go[0] += gxi0[0];
+    go[1] += gxi0[1];
+    go[2] += gxi0[2];
   }
-  if (A.offset_grad) {   // FP32 form: d/d(offset) = h d/dx
-    gx.x *= h[0];
-    gx.y *= h[1];
-    gx.z *= h[2];
-  }
+  if (A.offset_grad) gx = Vec3<T>{go[0], go[1], go[2]};   // FP32 form: d/d(offset)
+  else gx = Vec3<T>{go[0] * A.inv_h[0], go[1] * A.inv_h[1], go[2] * A.inv_h[2]};
 }
 
 // Per-cell tables of one brick: item (value ij, cell) sums gM over the cell's
@@ -471,7 +491,7 @@ __device__ __forceinline__ void form_tables(const BwdArgs<T>& A, NodeOf node_of,
   for (int it = tid; it < NCELL * 10; it += nthreads) {
     const int ij = it / NCELL, lc = it % NCELL;
     const int lx = lc % TX, ly = (lc / TX) % TY, lz = lc / (TX * TY);
-    T* const G = cg + lc * kGS;
+    T* const G = cg + lc * kGL;
     if (ij < 9) {
       T Gc[27];
 #pragma unroll
@@ -509,11 +529,11 @@ __device__ __forceinline__ void form_tables(const BwdArgs<T>& A, NodeOf node_of,
 // cell's table, plain atomics for the grid gradients (the listed particles
 // are scattered).
 template <typename T, bool CELL, bool THROUGH>
-__global__ void __launch_bounds__(kBlock) k_backward_list(BwdArgs<T> A) {
+__global__ void __launch_bounds__(kListBlock) k_backward_list(BwdArgs<T> A) {
   const Grid& g = A.g;
   const int64_t nn = g.nn;
   const int n = *A.nlist;
-  for (int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+  for (int base = blockIdx.x * kListBlock; base < n; base += gridDim.x * kListBlock) {
     const int i = base + (int)threadIdx.x;
     if (i >= n) break;
     const int p = A.list[i];
@@ -542,7 +562,7 @@ __global__ void __launch_bounds__(kBlock) k_backward_list(BwdArgs<T> A) {
     Vec3<T> gx, gv;
     GridSrc<T> src;
     int c1;
-    adjoint_core<T, CELL, THROUGH>(A, s0, A.p0[p], A.p1[p], A.p2[p], v, qp, pre, post_of, gx, gv, src, c1);
+    adjoint_core<T, CELL, THROUGH, true>(A, s0, A.p0[p], A.p1[p], A.p2[p], v, qp, pre, post_of, gx, gv, src, c1);
     note_nonfinite(g, !(finite(gx.x) && finite(gx.y) && finite(gx.z) && finite(gv.x) && finite(gv.y) &&
                         finite(gv.z)));
     A.gx0[p] = gx.x;
@@ -574,10 +594,13 @@ __global__ void __launch_bounds__(kBlock) k_backward_list(BwdArgs<T> A) {
 // which the listed particles read). Each wavefront takes cells wave + NW j of
 // the brick and gives each of them ceil(n_j / C) lanes, with C the least
 // count per lane for which they fit the wavefront; the lanes of a cell take
-// its particles in turn (consecutive lanes, consecutive particles). Each
-// particle adds its grid-gradient sources at its cell's 8 corners to per-node
-// sums in LDS, which go to gE and gB with one atomic per node value at the
-// end. A
+// its particles in turn (consecutive lanes, consecutive particles), so each
+// lane meets one cell only and sums its grid-gradient sources at that cell's
+// 8 corners in registers. After the wavefront's last step the lanes of each
+// cell are summed (a tree within the cell's lanes) and added to per-node sums
+// in LDS, which go to gE and gB with one atomic per node value at the end
+// (adding every particle's sources to LDS directly, 48 atomics per particle
+// on the few addresses of a cell, measured twice as slow). A
 // particle that is not in its range's cell before the move, or leaves it in
 // the move, is listed for k_backward_list and contributes nothing here.
 template <typename T, int TX, int TY, int TZ, int NW, bool THROUGH>
@@ -587,7 +610,7 @@ __global__ void __launch_bounds__(NW * 64) k_backward_tiled(BwdArgs<T> A, int nt
   constexpr int CPW = NCELL / NW;   // cells per wavefront
   static_assert(NCELL % NW == 0 && CPW <= 32 && (CPW & (CPW - 1)) == 0, "a power-of-two cell count per wavefront");
   constexpr int NX = TX + 1, NY = TY + 1, NZ = TZ + 1, NBN = NX * NY * NZ;
-  __shared__ __attribute__((aligned(16))) T cg[NCELL * kGS];
+  __shared__ __attribute__((aligned(16))) T cg[NCELL * kGL];
   __shared__ __attribute__((aligned(16))) T nf[NBN * 8];   // per node: E (3), B (3), pad
   __shared__ T acc[NBN * 8];                              // per node: gE (3), gB (3), pad
   __shared__ int64_t bnode[NBN];                          // global index of each brick node
@@ -624,7 +647,7 @@ __global__ void __launch_bounds__(NW * 64) k_backward_tiled(BwdArgs<T> A, int nt
     const int lc = it / kGS, e = it % kGS;
     const int cx = x0 + lc % TX, cy = y0 + (lc / TX) % TY, cz = z0 + lc / (TX * TY);
     if (cx < g.nx && cy < g.ny && cz < g.nz)
-      A.gtab[(int64_t)(cx + g.nx * (cy + g.ny * cz)) * kGS + e] = cg[it];
+      A.gtab[(int64_t)(cx + g.nx * (cy + g.ny * cz)) * kGS + e] = cg[lc * kGL + e];
   }
 
   // ---- the wavefront's cells (lane j < CPW: local cell wave + NW j) ----
@@ -666,6 +689,9 @@ __global__ void __launch_bounds__(NW * 64) k_backward_tiled(BwdArgs<T> A, int nt
   ofs[0] = 0;
 #pragma unroll
   for (int k = 0; k < CPW; ++k) ofs[k + 1] = __builtin_amdgcn_readlane(incl, k);
+  int mmax = 0;
+#pragma unroll
+  for (int k = 0; k < CPW; ++k) mmax = max(mmax, ofs[k + 1] - ofs[k]);
   // this lane's cell j and its rank r among the cell's lanes
   int j = 0;
 #pragma unroll
@@ -680,7 +706,7 @@ __global__ void __launch_bounds__(NW * 64) k_backward_tiled(BwdArgs<T> A, int nt
   const T* const nb = nf + 8 * ((lc % TX) + NX * ((lc / TX) % TY + NY * (lc / (TX * TY))));
   auto corner = [&](int a) -> const T* { return nb + 8 * ((a & 1) + NX * (((a >> 1) & 1) + NY * ((a >> 2) & 1))); };
   auto pre = [&](int a, int k) -> T { return corner(a)[k]; };
-  const T* const Gcell = cg + lc * kGS;
+  const T* const Gcell = cg + lc * kGL;
   auto post_of = [&](const Stencil<T>&, int) {
     struct Post {
       const T* nb;
@@ -691,6 +717,13 @@ __global__ void __launch_bounds__(NW * 64) k_backward_tiled(BwdArgs<T> A, int nt
     };
     return Post{nb, Gcell};
   };
+
+  // grid-gradient sums at the cell's corners: [a][gE x, y, z, gB x, y, z]
+  T sum[8][6];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sum[a][k] = T(0);
 
   for (int step = 0; step < C; ++step) {
     const int i = r + step * mj;
@@ -705,7 +738,7 @@ __global__ void __launch_bounds__(NW * 64) k_backward_tiled(BwdArgs<T> A, int nt
     Vec3<T> gx, gv;
     GridSrc<T> src;
     int c1;
-    adjoint_core<T, CELL, THROUGH>(A, s0, A.p0[p], A.p1[p], A.p2[p], v, qp, pre, post_of, gx, gv, src, c1);
+    adjoint_core<T, CELL, THROUGH, false>(A, s0, A.p0[p], A.p1[p], A.p2[p], v, qp, pre, post_of, gx, gv, src, c1);
     const bool fast = valid && c0 == cj && c1 == cj;
     // the others go to the general path (a second kernel over the list)
     {
@@ -726,25 +759,46 @@ __global__ void __launch_bounds__(NW * 64) k_backward_tiled(BwdArgs<T> A, int nt
       A.gv0[p] = gv.x;
       A.gv1[p] = gv.y;
       A.gv2[p] = gv.z;
-      // the grid-gradient sources at the cell's corners, into the brick's
-      // node sums
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
-        T* const an = acc + (corner(a) - nf);
         const T w1 = corner_weight(src.s1, a);
         if constexpr (THROUGH) {
           const T w0 = corner_weight(s0, a);
-          atomicAdd(an + 0, w0 * src.gEp.x);
-          atomicAdd(an + 1, w0 * src.gEp.y);
-          atomicAdd(an + 2, w0 * src.gEp.z);
-          atomicAdd(an + 3, fma(w1, src.gB1.x, w0 * src.gBp.x));
-          atomicAdd(an + 4, fma(w1, src.gB1.y, w0 * src.gBp.y));
-          atomicAdd(an + 5, fma(w1, src.gB1.z, w0 * src.gBp.z));
+          sum[a][0] = fma(w0, src.gEp.x, sum[a][0]);
+          sum[a][1] = fma(w0, src.gEp.y, sum[a][1]);
+          sum[a][2] = fma(w0, src.gEp.z, sum[a][2]);
+          sum[a][3] = fma(w1, src.gB1.x, fma(w0, src.gBp.x, sum[a][3]));
+          sum[a][4] = fma(w1, src.gB1.y, fma(w0, src.gBp.y, sum[a][4]));
+          sum[a][5] = fma(w1, src.gB1.z, fma(w0, src.gBp.z, sum[a][5]));
         } else {
-          atomicAdd(an + 3, w1 * src.gB1.x);
-          atomicAdd(an + 4, w1 * src.gB1.y);
-          atomicAdd(an + 5, w1 * src.gB1.z);
+          sum[a][3] = fma(w1, src.gB1.x, sum[a][3]);
+          sum[a][4] = fma(w1, src.gB1.y, sum[a][4]);
+          sum[a][5] = fma(w1, src.gB1.z, sum[a][5]);
         }
+      }
+    }
+  }
+  // ---- the cell sums: a tree over each cell's lanes, then its first lane
+  // adds them to the brick's node sums ----
+  if (C > 0) {   // wave-uniform
+    for (int off = 1; off < mmax; off <<= 1) {
+      const bool take = r + off < mj;
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          if (!THROUGH && k < 3) continue;
+          const T o = __shfl_down(sum[a][k], off);
+          sum[a][k] += take ? o : T(0);
+        }
+    }
+    if (own && r == 0) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        T* const an = acc + (corner(a) - nf);
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          if (THROUGH || k >= 3) atomicAdd(an + k, sum[a][k]);
       }
     }
   }
@@ -783,6 +837,11 @@ hipError_t launch_T(const Grid& g, const SpeciesArgs& sp, const void* E, const v
   A.q = (const T*)sp.q;
   A.q_const = (T)sp.q_const;
   A.beta = (T)(sp.qom * g.dt / 2.0);
+  A.inv_V = (T)(1.0 / g.V);
+  A.beta_V = (T)(sp.qom * g.dt / 2.0 / g.V);
+  A.inv_h[0] = (T)(1.0 / g.hx);
+  A.inv_h[1] = (T)(1.0 / g.hy);
+  A.inv_h[2] = (T)(1.0 / g.hz);
   A.dth0 = (T)(g.pdt[0] / g.hx);
   A.dth1 = (T)(g.pdt[1] / g.hy);
   A.dth2 = (T)(g.pdt[2] / g.hz);
@@ -828,11 +887,11 @@ hipError_t launch_T(const Grid& g, const SpeciesArgs& sp, const void* E, const v
                            ntx, nty, ntz);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const unsigned lb = (unsigned)std::min<int64_t>(1024, (sp.np + kBlock - 1) / kBlock);
+    const unsigned lb = (unsigned)std::min<int64_t>(4096, (sp.np + kListBlock - 1) / kListBlock);
     if (through)
-      hipLaunchKernelGGL((k_backward_list<T, CELL, true>), dim3(lb), dim3(kBlock), 0, st, A);
+      hipLaunchKernelGGL((k_backward_list<T, CELL, true>), dim3(lb), dim3(kListBlock), 0, st, A);
     else
-      hipLaunchKernelGGL((k_backward_list<T, CELL, false>), dim3(lb), dim3(kBlock), 0, st, A);
+      hipLaunchKernelGGL((k_backward_list<T, CELL, false>), dim3(lb), dim3(kListBlock), 0, st, A);
     return hipGetLastError();
   }
   dim3 grid((unsigned)((sp.np + kBlock - 1) / kBlock)), block(kBlock);

@@ -22,16 +22,15 @@
 // The deposit kernel: a workgroup owns a brick of TX x TY x TZ cells; each
 // cell's particles are its species ranges (entries outside the cell carry
 // zero charge) followed by its entries of the sorted stray list. Each
-// wavefront takes a fixed set of the brick's cells and lays their lists end
-// to end, each padded to a multiple of 4 particles:
+// wavefront takes cells wave, wave + NW, ... of the brick, one at a time, in
+// blocks of 64 of the cell's particles:
 //   1. each lane takes one particle and writes a record to LDS: the 12 values
 //      and the 27 class weights, with the mover's stencil and field gather
 //      (alpha_p bit for bit in FP64, to rounding in FP32);
 //   2. the contraction runs on the matrix cores: v_mfma 16x16x4 with rows =
 //      the 12 values (padded to 16), columns = the 27 classes (two tiles of 16)
-//      and K = 4 particles of one cell per instruction; FP32 sums are formed
-//      in blocks of 64 particles and the blocks combined with Kahan
-//      compensation;
+//      and K = 4 particles per instruction; FP32 sums are formed in blocks of
+//      64 particles and the blocks combined with Kahan compensation;
 //   3. a finished cell's sums (27 x 9 mass-matrix classes and 8 x 3 corner
 //      currents) go to its record in HBM, written once, no atomics.
 // The flush kernel then stages bricks of cell records in LDS and gives every
@@ -1458,244 +1457,6 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
 }
 
 // ---------------------------------------------------------------------------
-// packed deposit (no regrouping)
-// ---------------------------------------------------------------------------
-// Each wavefront owns cells lc = wave, wave + NW, ... of the brick (CPW of
-// them). Their particle lists (species ranges, then arrived strays) are laid
-// end to end, each padded to a multiple of 4, so that blocks of 64 lanes stay
-// full across cell boundaries (a cell of the 64^3 x 64 ppc x 2 species
-// workload holds about 130 particles: one cell per block would leave a third
-// of the lanes idle) while every matrix-core step, 4 list positions, lies in
-// one cell. The step's cell (wavefront-uniform) owns the running sums; when
-// the cell changes, the finished cell's sums are written to its record.
-template <typename T, int TX, int TY, int TZ, int NW>
-__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
-k_deposit_packed(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
-  using MF = Mfma<T>;
-  using acc_t = typename MF::acc;
-  constexpr int NCELL = TX * TY * TZ;
-  constexpr int CPW = NCELL / NW;   // cells per wavefront
-  static_assert(NCELL % NW == 0 && CPW <= 16, "the wavefront's cells fit its first lanes");
-  constexpr int WREC = kRows * kSlots;
-  constexpr int NX = TX + 1, NY = TY + 1, NZ = TZ + 1, NBN = NX * NY * NZ;   // brick nodes
-  constexpr int CT = 13;   // cell table entry: d0, inc[4], end[4], total, cell, lc, list offset
-  // the wavefront records, and two rows more: the matrix-core operand reads
-  // of the unused classes 27-31 reach two rows past a wavefront's records
-  __shared__ __attribute__((aligned(16))) T smem[NW * WREC + 2 * kSlots];
-  __shared__ __attribute__((aligned(16))) T bst[NBN * 4];   // B at the brick's nodes: x, y, z, pad
-  __shared__ int ctab[NW * CPW * CT];
-  __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
-  __shared__ PtrSet<T> lptr_tab[kZeroSlot + 1];
-  LdsPtrSet<T>* const lptr = (LdsPtrSet<T>*)lptr_tab;
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int col = lane & 15;   // MFMA column (class) of this lane
-  const int grp = lane >> 4;   // MFMA k-group of this lane
-  int x0, y0, z0;
-  brick_origin<TX, TY, TZ>(ntx, nty, ntz, x0, y0, z0);
-
-  for (int i = tid; i < NW * WREC + 2 * kSlots; i += NW * 64) smem[i] = T(0);
-  fill_tables(args, lsp, lptr_tab, tid);
-  for (int nl = tid; nl < NBN; nl += NW * 64) {
-    const int gx = (x0 + nl % NX) % g.nx, gy = (y0 + (nl / NX) % NY) % g.ny, gz = (z0 + nl / (NX * NY)) % g.nz;
-    const int64_t gn = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) bst[4 * nl + c] = args.Bdep[c * g.nn + gn];
-    bst[4 * nl + 3] = T(0);
-  }
-  __syncthreads();
-
-  T* const wrec = smem + wave * WREC;
-  const T* const opnd = wrec + col * kSlots + grp;   // row col, slot grp
-  T* const tcur = wrec + kTcur;                       // current class sums [27][3]
-  int* const wtab = ctab + wave * CPW * CT;
-
-  // the wavefront's cells: lane j < CPW takes cell j (local index wave + NW j)
-  int total = 0, pad = 0;
-  if (lane < CPW) {
-    const BrickCell c = brick_cell<TX, TY, TZ>(g, x0, y0, z0, wave + NW * lane);
-    const Ranges r = make_ranges<T, kSlots5>(args, load_ranges<T, kSlots5>(args, lsp, c), c);
-    int* const e = wtab + lane * CT;
-    e[0] = r.d0;
-#pragma unroll
-    for (int k = 0; k < kSlots5 - 1; ++k) {
-      e[1 + k] = r.inc[k];
-      e[5 + k] = r.end[k];
-    }
-    e[9] = r.total;
-    e[10] = c.cell;   // -1: not a cell of the grid
-    e[11] = c.lc;
-    total = r.total;
-    pad = (total + 3) & ~3;
-  }
-  int incl = pad;
-#pragma unroll
-  for (int o = 1; o < CPW; o <<= 1) {
-    const int y = __shfl_up(incl, o);
-    if (lane >= o) incl += y;
-  }
-  if (lane < CPW) wtab[lane * CT + 12] = incl - pad;
-  // list offsets of the cells and the list length, in scalar registers
-  int ofs[CPW + 1];
-  ofs[0] = 0;
-#pragma unroll
-  for (int k = 0; k < CPW; ++k) ofs[k + 1] = __builtin_amdgcn_readlane(incl, k);
-  const int L = ofs[CPW];
-  wave_sync();
-  // an empty cell has no matrix-core step: its record is zero
-#pragma unroll
-  for (int k = 0; k < CPW; ++k) {
-    const int ck = __builtin_amdgcn_readfirstlane(wtab[k * CT + 10]);
-    if (ofs[k + 1] == ofs[k] && ck >= 0)
-      for (int i = lane; i < SCS; i += 64) gst(args.csum + (int64_t)ck * SCS + i, T(0));
-  }
-  if (L == 0) return;   // wave-uniform
-
-  // the cell holding list position i (the last cell starting at or before it)
-  auto cell_at = [&](int i) -> int {
-    int j = 0;
-#pragma unroll
-    for (int k = 1; k < CPW; ++k) j += i >= ofs[k] ? 1 : 0;
-    return j;
-  };
-  // particle at list position i of this lane (past the list: no particle)
-  auto load_at = [&](int i, int& j) -> PData<T> {
-    j = cell_at(i < L ? i : L - 1);
-    const int* const e = wtab + j * CT;
-    Ranges r;
-    r.d0 = e[0];
-#pragma unroll
-    for (int k = 0; k < kSlots5 - 1; ++k) {
-      r.inc[k] = e[1 + k];
-      r.end[k] = e[5 + k];
-    }
-    r.total = i < L ? e[9] : 0;
-    return load_dep<T>(lptr, r, i - e[12]);
-  };
-
-  // per-cell sums to the record; the current classes via LDS to the corner
-  // currents J_a = sum_b T_{a+b}
-  auto finish_cell = [&](int j, T (&S)[2][4], T (&C)[2][4]) {
-    const int cell = __builtin_amdgcn_readfirstlane(wtab[j * CT + 10]);
-    T* const sc = args.csum + (int64_t)(cell >= 0 ? cell : 0) * SCS;
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int cls = t * 16 + col;
-      if (cls >= 27) continue;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = MF::row(lane, q);
-        T v = S[t][q];
-        if constexpr (sizeof(T) == 4) v -= C[t][q];
-        if (row < 9) {
-          if (cell >= 0) gst(sc + cls * 9 + row, v);
-        } else if (row < 12) {
-          tcur[cls * 3 + (row - 9)] = v;
-        }
-      }
-    }
-    wave_sync();
-    if (lane < 24 && cell >= 0) {
-      const int a = lane / 3, comp = lane % 3;
-      const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
-      T s = T(0);
-#pragma unroll
-      for (int bb = 0; bb < 8; ++bb) {
-        const int cls = (ax + (bb & 1)) + 3 * (ay + ((bb >> 1) & 1)) + 9 * (az + ((bb >> 2) & 1));
-        s += tcur[cls * 3 + comp];
-      }
-      gst(sc + 243 + 3 * a + comp, s);
-    }
-    wave_sync();
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) { S[t][q] = T(0); C[t][q] = T(0); }
-  };
-  auto fold = [&](T (&S)[2][4], T (&C)[2][4], const acc_t& d0, const acc_t& d1) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if constexpr (sizeof(T) == 4) {
-        kahan(S[0][q], C[0][q], d0[q]);
-        kahan(S[1][q], C[1][q], d1[q]);
-      } else {
-        S[0][q] += d0[q];
-        S[1][q] += d1[q];
-      }
-    }
-  };
-
-  T S[2][4], C[2][4];   // running sums of the open cell [tile][reg]
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) { S[t][r] = T(0); C[t][r] = T(0); }
-  int jcur = cell_at(0);   // the open cell (wave-uniform)
-  int pj;
-  PData<T> pd = load_at(lane, pj);
-
-  for (int base = 0; base < L; base += 64) {
-    // ---- 1. this lane's record; lanes without a particle of their cell
-    // (past its count, or no longer in it) carry zero charge ----
-    {
-      const int* const e = wtab + pj * CT;
-      const int cell = e[10];
-      const int lcl = e[11];
-      const TSpecies<T>& sp = lsp[dep_species(pd)];
-      const Stencil<T> ps = particle_stencil<T>(g, pd.x0, pd.x1, pd.x2, pd.c);
-      bool keep;
-      if constexpr (sizeof(T) == 4) keep = pd.ok && pd.c == cell;
-      else keep = pd.ok && ps.i[0] + g.nx * (ps.i[1] + g.ny * ps.i[2]) == cell;
-      T W[8];
-#pragma unroll
-      for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
-      // B at the cell's corners from the brick's nodes
-      const T* const nb = bst + 4 * ((lcl % TX) + NX * ((lcl / TX) % TY + NY * (lcl / (TX * TY))));
-      Vec3<T> B1{T(0), T(0), T(0)};
-#pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const T* const f = nb + 4 * ((a & 1) + NX * (((a >> 1) & 1) + NY * ((a >> 2) & 1)));
-        B1.x = fma(W[a], f[0], B1.x);
-        B1.y = fma(W[a], f[1], B1.y);
-        B1.z = fma(W[a], f[2], B1.z);
-      }
-      T r[39];
-      particle_record(ps, B1, Vec3<T>{pd.v0, pd.v1, pd.v2}, keep ? dep_charge(pd, lptr) : T(0), sp, r);
-#pragma unroll
-      for (int i = 0; i < 39; ++i) wrec[i * kSlots + lane] = r[i];
-    }
-    wave_sync();
-    // ---- 2. the next block's loads, in flight while this block is reduced ----
-    pd = load_at(base + 64 + lane, pj);
-    // ---- 3. matrix cores, 4 list positions per step; a change of cell
-    // writes the finished cell ----
-    acc_t d0 = {0, 0, 0, 0}, d1 = {0, 0, 0, 0};
-#pragma unroll
-    for (int k4 = 0; k4 < 64; k4 += 4) {
-      if (base + k4 >= L) break;   // wave-uniform
-      const int jt = cell_at(base + k4);
-      if (jt != jcur) {   // wave-uniform
-        fold(S, C, d0, d1);
-        finish_cell(jcur, S, C);
-        d0 = acc_t{0, 0, 0, 0};
-        d1 = acc_t{0, 0, 0, 0};
-        jcur = jt;
-      }
-      const T a = opnd[k4];
-      const T b0 = opnd[12 * kSlots + k4];
-      const T b1 = opnd[28 * kSlots + k4];
-      d0 = MF::run(a, b0, d0);
-      d1 = MF::run(a, b1, d1);
-    }
-    fold(S, C, d0, d1);
-    wave_sync();
-  }
-  finish_cell(jcur, S, C);
-}
-
-// ---------------------------------------------------------------------------
 // node flush: every node's J and 14 mass-matrix blocks from the per-cell sums
 // ---------------------------------------------------------------------------
 // Node g is corner a of the 8 cells g - a. Block k of g holds every stored
@@ -1712,7 +1473,10 @@ __global__ void __launch_bounds__(256) k_flush_nodes(Grid g, const T* __restrict
                                                      T* __restrict__ M, int accumulate, int nbx, int nby, int nbz) {
   constexpr int CX = FX + 1, CY = FY + 1, CZ = FZ + 1, NC = CX * CY * CZ;
   constexpr int NN = FX * FY * FZ;
-  __shared__ T rec[NC * SCS];
+  // staged cells SL apart: an odd stride puts the same entry of neighbouring
+  // cells (the lanes' nodes) in distinct LDS banks
+  constexpr int SL = SCS + 1;
+  __shared__ T rec[NC * SL];
   __shared__ int64_t cbase[NC];
   int x0, y0, z0;
   brick_origin<FX, FY, FZ>(nbx, nby, nbz, x0, y0, z0);
@@ -1740,7 +1504,8 @@ __global__ void __launch_bounds__(256) k_flush_nodes(Grid g, const T* __restrict
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
       const int i = i0 + j * 256 + tid;
-      if (i < TOT) rec[i] = v[j];
+      const int c = i / SCS;
+      if (i < TOT) rec[i + c] = v[j];   // c * SL + (i - c * SCS)
     }
   }
   __syncthreads();
@@ -1759,7 +1524,7 @@ __global__ void __launch_bounds__(256) k_flush_nodes(Grid g, const T* __restrict
     if (gx >= g.nx || gy >= g.ny || gz >= g.nz) continue;   // a clipped brick
     const int64_t gn = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
     // the staged cell g - a is (lx + 1 - ax, ly + 1 - ay, lz + 1 - az)
-    const T* const cb = rec + ((lx + 1) + CX * ((ly + 1) + CY * (lz + 1))) * SCS;
+    const T* const cb = rec + ((lx + 1) + CX * ((ly + 1) + CY * (lz + 1))) * SL;
     if (grp < 9) {
       const int ij = grp;
 #pragma unroll
@@ -1770,7 +1535,7 @@ __global__ void __launch_bounds__(256) k_flush_nodes(Grid g, const T* __restrict
           const int cls = pair_class(k, a);
           if (cls < 0) continue;
           const int off = (a & 1) + CX * (((a >> 1) & 1) + CY * ((a >> 2) & 1));
-          v += (double)cb[-off * SCS + cls * 9 + ij];
+          v += (double)cb[-off * SL + cls * 9 + ij];
         }
         put(M + (int64_t)(k * 9 + ij) * g.nn + gn, v);
       }
@@ -1781,7 +1546,7 @@ __global__ void __launch_bounds__(256) k_flush_nodes(Grid g, const T* __restrict
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
           const int off = (a & 1) + CX * (((a >> 1) & 1) + CY * ((a >> 2) & 1));
-          v += (double)cb[-off * SCS + 243 + 3 * a + comp];
+          v += (double)cb[-off * SL + 243 + 3 * a + comp];
         }
         put(J + (int64_t)comp * g.nn + gn, v);
       }
@@ -2318,7 +2083,7 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
     hipLaunchKernelGGL((k_deposit<T, TX, TY, TZ, NW, true>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty,
                        ntz);
   } else {
-    hipLaunchKernelGGL((k_deposit_packed<T, TX, TY, TZ, NW>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty,
+    hipLaunchKernelGGL((k_deposit<T, TX, TY, TZ, NW, false>), dim3(ntiles), dim3(NW * 64), 0, st, g, a, ntx, nty,
                        ntz);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;

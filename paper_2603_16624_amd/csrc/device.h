@@ -315,7 +315,10 @@ __device__ __forceinline__ Vec3<T> rotation_vjp(const T a[9], Vec3<T> B, T beta,
   T gby = (G[3] * bx + G[4] * by + G[5] * bz) + (G[1] * bx + G[4] * by + G[7] * bz) + (G[6] - G[2]);
   T gbz = (G[6] * bx + G[7] * by + G[8] * bz) + (G[2] * bx + G[5] * by + G[8] * bz) + (G[1] - G[3]);
   T two_ga = T(2) * ga;
-  T inv = T(1) / den;
+  // FP32: the hardware reciprocal (1 ulp); FP64 divides
+  T inv;
+  if constexpr (sizeof(T) == 4) inv = __builtin_amdgcn_rcpf(den);
+  else inv = T(1) / den;
   return Vec3<T>{beta * ((gbx - two_ga * bx) * inv), beta * ((gby - two_ga * by) * inv),
                  beta * ((gbz - two_ga * bz) * inv)};
 }
