@@ -254,19 +254,6 @@ __device__ __forceinline__ Stencil<double> particle_stencil<double>(const Grid& 
   return stencil_abs(g, x0, x1, x2);
 }
 
-// F_p = sum_a W_a F_a over staged corner values [3][8], in the order of gather().
-template <typename T>
-__device__ __forceinline__ Vec3<T> gather_staged(const T W[8], const T* F) {
-  Vec3<T> r{T(0), T(0), T(0)};
-#pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    r.x = fma(W[a], F[a], r.x);
-    r.y = fma(W[a], F[8 + a], r.y);
-    r.z = fma(W[a], F[16 + a], r.z);
-  }
-  return r;
-}
-
 // stored block k: offset o_k (same order as the C ABI)
 __host__ __device__ constexpr int koff(int k, int d) {
   return k == 0 ? 0
@@ -496,19 +483,6 @@ __device__ __forceinline__ Ranges make_ranges(const TArgs<T>& args, const RangeL
   }
   q.total = e;
   return q;
-}
-
-// corner nodes of a cell
-template <typename T>
-__device__ __forceinline__ Stencil<T> cell_stencil(const Grid& g, const BrickCell& c) {
-  Stencil<T> st{};
-  st.i[0] = c.valid ? c.cx : 0;
-  st.i[1] = c.valid ? c.cy : 0;
-  st.i[2] = c.valid ? c.cz : 0;
-  st.ip[0] = wrap_up(st.i[0], g.nx);
-  st.ip[1] = wrap_up(st.i[1], g.ny);
-  st.ip[2] = wrap_up(st.i[2], g.nz);
-  return st;
 }
 
 // A particle's record: the 12 values ((q beta / V) alpha, (q / V) alpha v)
@@ -1196,11 +1170,11 @@ k_mover(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
 // ---------------------------------------------------------------------------
 // tiled deposit
 // ---------------------------------------------------------------------------
-// A workgroup owns a brick of cells; each wavefront takes the brick's cells
-// one at a time. Per cell the wavefront-uniform quantities (the cell's
-// particle ranges, its corner B, the regrouping starts) are loaded one cell
-// ahead, one value per lane, and moved to scalar registers; each block of 64
-// list positions is one particle per lane:
+// A workgroup owns a brick of cells and stages B at the brick's nodes in
+// LDS; each wavefront takes the brick's cells one at a time. Per cell the
+// wavefront-uniform quantities (the cell's particle ranges, the regrouping
+// starts) are loaded one cell ahead, one value per lane, and moved to scalar
+// registers; each block of 64 list positions is one particle per lane:
 //   1. the lane's record (12 values, 27 class weights) goes to LDS;
 //   2. the next block's loads are issued (this cell's, else the next cell's);
 //   3. 16 matrix-core steps of K = 4 particles reduce the block, from zero,
@@ -1210,18 +1184,6 @@ k_mover(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
 // With REGROUP the deposit also writes every particle it takes (the cell's own
 // range particles still in the cell, then its strays) to the targets, species
 // by species in cell order: the next pass's grouping, without a separate sort.
-template <typename T>
-__device__ __forceinline__ T lane_value(T v, int l) {
-  if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
-  } else {
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
-    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
-  }
-}
-
 template <typename T, int TX, int TY, int TZ, int NW, bool REGROUP>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
 k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
@@ -1229,9 +1191,11 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   using acc_t = typename MF::acc;
   constexpr int NCELL = TX * TY * TZ;
   constexpr int WREC = kRows * kSlots;
+  constexpr int NX = TX + 1, NY = TY + 1, NZ = TZ + 1, NBN = NX * NY * NZ;   // brick nodes
   // the wavefront records, and two rows more: the matrix-core operand reads
   // of the unused classes 27-31 reach two rows past a wavefront's records
   __shared__ __attribute__((aligned(16))) T smem[NW * WREC + 2 * kSlots];
+  __shared__ __attribute__((aligned(16))) T bst[NBN * 4];   // B at the brick's nodes: x, y, z, pad
   __shared__ TSpecies<T> lsp[kMaxTiledSpecies];
   __shared__ PtrSet<T> lptr_tab[kZeroSlot + 1];
   // regrouping targets, read from LDS where used (kept in scalar registers
@@ -1249,6 +1213,13 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
 
   for (int i = tid; i < NW * WREC + 2 * kSlots; i += NW * 64) smem[i] = T(0);
   fill_tables(args, lsp, lptr_tab, tid);
+  for (int nl = tid; nl < NBN; nl += NW * 64) {
+    const int gx = (x0 + nl % NX) % g.nx, gy = (y0 + (nl / NX) % NY) % g.ny, gz = (z0 + nl / (NX * NY)) % g.nz;
+    const int64_t gn = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bst[4 * nl + c] = args.Bdep[c * g.nn + gn];
+    bst[4 * nl + 3] = T(0);
+  }
   if constexpr (REGROUP) {
 #pragma unroll
     for (int k = 0; k < kMaxTiledSpecies; ++k)
@@ -1260,18 +1231,12 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   const T* const opnd = wrec + col * kSlots + grp;   // row col, slot grp
   T* const tcur = wrec + kTcur;                       // current class sums [27][3]
 
-  // One-cell-ahead loads, one value per lane: lanes 0..23 the cell's corner
-  // B (component l / 8, corner l % 8), lanes 0..9 its range bounds (lo, hi
-  // of slot l / 2), lanes 0..3 the regrouping starts.
-  auto load_cell = [&](const BrickCell& c, T& bv, int& rv, int& dv) {
-    bv = T(0);
+  // One-cell-ahead loads, one value per lane: lanes 0..9 the cell's range
+  // bounds (lo, hi of slot l / 2), lanes 0..3 the regrouping starts.
+  auto load_cell = [&](const BrickCell& c, int& rv, int& dv) {
     rv = 0;
     dv = 0;
     const int cl = c.valid ? c.cell : 0;
-    if (lane < 24) {
-      const Stencil<T> st = cell_stencil<T>(g, c);
-      bv = args.Bdep[(lane >> 3) * g.nn + corner_node(g, st, lane & 7)];
-    }
     if (lane < 2 * kSlots5) {
       const int s = lane >> 1;
       const int32_t* cs = s == kStraySlot ? args.ind_start : lsp[s < kMaxTiledSpecies ? s : 0].cell_start;
@@ -1293,26 +1258,23 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   };
 
   BrickCell cc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, wave);
-  T bv;
   int rv, dv;
-  load_cell(cc, bv, rv, dv);
+  load_cell(cc, rv, dv);
   Ranges cr = cell_ranges(cc, rv);
   PData<T> pd = load_dep<T>(lptr, cr, lane);
 
   for (int lc = wave; lc < NCELL; lc += NW) {
     const bool has_next = lc + NW < NCELL;   // wave-uniform
     const BrickCell nc = brick_cell<TX, TY, TZ>(g, x0, y0, z0, has_next ? lc + NW : lc);
-    // this cell's corner B and regrouping starts, in scalar registers
-    T Bc[24];
-#pragma unroll
-    for (int i = 0; i < 24; ++i) Bc[i] = lane_value(bv, i);
+    // this cell's regrouping starts, in scalar registers, and its corners'
+    // B in LDS
     int dst0[kMaxTiledSpecies];
 #pragma unroll
     for (int s = 0; s < kMaxTiledSpecies; ++s) dst0[s] = REGROUP ? __builtin_amdgcn_readlane(dv, s) : 0;
+    const T* const nb = bst + 4 * ((lc % TX) + NX * ((lc / TX) % TY + NY * (lc / (TX * TY))));
     // the next cell's, in flight while this cell is processed
-    T nbv = T(0);
     int nrv = 0, ndv = 0;
-    if (has_next) load_cell(nc, nbv, nrv, ndv);
+    if (has_next) load_cell(nc, nrv, ndv);
 
     const int cell = cc.cell;   // -1: not a cell of the grid (a clipped brick)
     const int cnt = cr.total;   // wave-uniform
@@ -1324,7 +1286,6 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
         pd = load_dep<T>(lptr, cr, lane);
       }
       cc = nc;
-      bv = nbv;
       rv = nrv;
       dv = ndv;
       continue;
@@ -1348,7 +1309,16 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
         T W[8];
 #pragma unroll
         for (int a = 0; a < 8; ++a) W[a] = corner_weight(ps, a);
-        const Vec3<T> B1 = gather_staged(W, Bc);
+        // B at the position from the cell's corners (the mover's order of
+        // accumulation, so the two agree bit for bit in FP64)
+        Vec3<T> B1{T(0), T(0), T(0)};
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const T* const f = nb + 4 * ((a & 1) + NX * (((a >> 1) & 1) + NY * ((a >> 2) & 1)));
+          B1.x = fma(W[a], f[0], B1.x);
+          B1.y = fma(W[a], f[1], B1.y);
+          B1.z = fma(W[a], f[2], B1.z);
+        }
         T r[39];
         particle_record(ps, B1, Vec3<T>{pd.v0, pd.v1, pd.v2}, keep ? dep_charge(pd, lptr) : T(0), sp, r);
 #pragma unroll
@@ -1450,7 +1420,6 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
     }
     wave_sync();
     cc = nc;
-    bv = nbv;
     rv = nrv;
     dv = ndv;
   }
@@ -1468,8 +1437,8 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
 // node) adds its at most 8 terms in FP64 and stores the rounded result once
 // (with accumulate: added to J and M). Every node has one owner: no atomics,
 // and J and M need no clearing.
-template <typename T, int FX, int FY, int FZ>
-__global__ void __launch_bounds__(256) k_flush_nodes(Grid g, const T* __restrict__ csum, T* __restrict__ J,
+template <typename T, int FX, int FY, int FZ, int NT>
+__global__ void __launch_bounds__(NT) k_flush_nodes(Grid g, const T* __restrict__ csum, T* __restrict__ J,
                                                      T* __restrict__ M, int accumulate, int nbx, int nby, int nbz) {
   constexpr int CX = FX + 1, CY = FY + 1, CZ = FZ + 1, NC = CX * CY * CZ;
   constexpr int NN = FX * FY * FZ;
@@ -1492,18 +1461,18 @@ __global__ void __launch_bounds__(256) k_flush_nodes(Grid g, const T* __restrict
   __syncthreads();
   // staged 16 values per thread at a time, all loads in flight together
   constexpr int TOT = NC * SCS, CH = 16;
-  for (int i0 = 0; i0 < TOT; i0 += 256 * CH) {
+  for (int i0 = 0; i0 < TOT; i0 += NT * CH) {
     T v[CH];
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
-      const int i = i0 + j * 256 + tid;
+      const int i = i0 + j * NT + tid;
       const int ic = i < TOT ? i : TOT - 1;
       const int c = ic / SCS, e = ic - c * SCS;
       v[j] = csum[cbase[c] + e];
     }
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
-      const int i = i0 + j * 256 + tid;
+      const int i = i0 + j * NT + tid;
       const int c = i / SCS;
       if (i < TOT) rec[i + c] = v[j];   // c * SL + (i - c * SCS)
     }
@@ -1517,7 +1486,7 @@ __global__ void __launch_bounds__(256) k_flush_nodes(Grid g, const T* __restrict
   };
   // items (group, node): groups 0..8 the mass-matrix entry ij of all 14
   // blocks, group 9 the three current components
-  for (int it = tid; it < 10 * NN; it += 256) {
+  for (int it = tid; it < 10 * NN; it += NT) {
     const int grp = it / NN, ln = it - grp * NN;
     const int lx = ln % FX, ly = (ln / FX) % FY, lz = ln / (FX * FY);
     const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
@@ -2091,7 +2060,8 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
   // LDS, two workgroups per CU); FP64 4 x 2 x 2 (45 cells, 94 KB)
   constexpr int FX = 4, FY = sizeof(T) == 4 ? 4 : 2, FZ = 2;
   const int nbx = (g.nx + FX - 1) / FX, nby = (g.ny + FY - 1) / FY, nbz = (g.nz + FZ - 1) / FZ;
-  hipLaunchKernelGGL((k_flush_nodes<T, FX, FY, FZ>), dim3((unsigned)(nbx * nby * nbz)), dim3(256), 0, st, g,
+  constexpr int NT = 256;
+  hipLaunchKernelGGL((k_flush_nodes<T, FX, FY, FZ, NT>), dim3((unsigned)(nbx * nby * nbz)), dim3(NT), 0, st, g,
                      (const T*)w.csum, (T*)J, (T*)M, accumulate ? 1 : 0, nbx, nby, nbz);
   return hipGetLastError();
 }
