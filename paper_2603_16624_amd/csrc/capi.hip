@@ -3,6 +3,7 @@
 // field solve (Eqs. 6-7). Declarations and the contract of every entry point
 // are in include/ecsim.h.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -546,33 +547,19 @@ ecsim_status ecsim_solve_workspace_size(const ecsim_grid* grid, int32_t restart,
   if (restart < 1 || restart > kMaxRestart) return fail(ECSIM_EINVAL, "restart = %d not in 1..%d", restart, kMaxRestart);
   if (!bytes) return fail(ECSIM_EINVAL, "bytes is NULL");
   const size_t vec = align256(sizeof(double) * 3 * (size_t)g.nn);
-  const size_t m = (size_t)restart;
-  // V (m+1 vectors), w, r/b, cc (curl scratch), dot partials, and the
-  // device-side GMRES state: both Gram-Schmidt passes, norms, H, the
-  // rotations, g, the residual history, -y and the iteration state
-  *bytes = vec * (m + 1) + 3 * vec + align256(sizeof(double) * kDotBlocks * (m + 2)) +
-           align256(sizeof(double) * (m * m + 8 * m + 16));
+  const size_t m = (size_t)restart, nb = (size_t)solve_blocks(g);
+  // V (m + 1 vectors), two w buffers, b; the partial sums of the two
+  // Gram-Schmidt passes; the read-back block (threshold, |r|, residual
+  // history, flags, partial |b|^2 and |w|^2); H, the rotations, g, h1, h2
+  *bytes = vec * (m + 1) + 3 * vec + 2 * align256(sizeof(double) * nb * m) +
+           align256(sizeof(double) * (5 + m + 2 * nb)) + align256(sizeof(double) * ((m + 1) * m + 5 * m + 1));
   return ECSIM_OK;
 }
 
 namespace {
-
-struct Solver {
-  Grid g;
-  bool mf32;
-  const void* M;
-  hipStream_t st;
-  double* cc;       // curl scratch (3 Nn)
-  double ctd2, cm;  // (c theta dt)^2, 4 pi theta dt
-
-  hipError_t apply(const double* x, double* out) {
-    hipError_t e;
-    if ((e = launch_curl_C(g, x, cc, st)) != hipSuccess) return e;
-    if ((e = launch_field_op_curl(g, x, cc, ctd2, out, st)) != hipSuccess) return e;
-    return launch_mass_apply(g, mf32, M, x, cm, 1.0, out, st);
-  }
-};
-
+// steps the first batch of a solve launches before its first read of the
+// residual history: what the last solve's first cycle needed
+std::atomic<int> g_first_batch{2};
 }  // namespace
 
 ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const void* M, const void* J,
@@ -591,140 +578,146 @@ ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const voi
   if (!ws || ws_bytes < need) return fail(ECSIM_EWORKSPACE, "ecsim_field_solve: workspace of %zu bytes needed", need);
 
   const int m = restart;
-  const int64_t n = 3 * g.nn;
-  const size_t vec = align256(sizeof(double) * (size_t)n);
+  const int nb = solve_blocks(g);
+  const size_t vec = align256(sizeof(double) * 3 * (size_t)g.nn);
   const int64_t ld = (int64_t)(vec / sizeof(double));
   char* w8 = (char*)ws;
   double* V = (double*)w8;
   w8 += vec * (size_t)(m + 1);
-  double* w = (double*)w8;
-  w8 += vec;
+  double* Wb[2] = {(double*)w8, (double*)(w8 + vec)};
+  w8 += 2 * vec;
   double* bvec = (double*)w8;
   w8 += vec;
-  double* cc = (double*)w8;
-  w8 += vec;
-  double* partial = (double*)w8;
-  w8 += align256(sizeof(double) * kDotBlocks * (m + 2));
-  // device-side state
-  double* d = (double*)w8;
-  double* h1 = d;                 // m + 1
-  double* h2 = h1 + (m + 1);      // m + 1
-  double* nrm = h2 + (m + 1);     // 4: |b|^2, |r|^2, |w|^2
-  double* H = nrm + 4;            // (m + 1) m
-  double* cs = H + (size_t)(m + 1) * m;
-  double* sn = cs + m;
-  double* gv = sn + m;            // m + 1
-  double* hist = gv + (m + 1);    // m
-  double* ny = hist + m;          // m
-  int* state = (int*)(ny + m);    // 2 ints
+  double* P1 = (double*)w8;
+  w8 += align256(sizeof(double) * (size_t)nb * m);
+  double* P2 = (double*)w8;
+  w8 += align256(sizeof(double) * (size_t)nb * m);
+  const size_t rb_count = 5 + (size_t)m + 2 * (size_t)nb;
+  double* rb = (double*)w8;
+  double* Pb = rb + 5 + m;
+  double* P3 = Pb + nb;
+  w8 += align256(sizeof(double) * rb_count);
+  GmresState G;
+  G.H = (double*)w8;
+  G.cs = G.H + (size_t)(m + 1) * m;
+  G.sn = G.cs + m;
+  G.gv = G.sn + m;
+  G.h1 = G.gv + (m + 1);
+  G.h2 = G.h1 + m;
+  G.rb = rb;
+  G.Pb = Pb;
+  G.m = m;
+  G.tol = tol;
 
   hipStream_t st = (hipStream_t)stream;
-  Solver S{g, m_prec == ECSIM_F32, M, st, cc, (kC * kTheta * g.dt) * (kC * kTheta * g.dt), 4.0 * kPi * kTheta * g.dt};
+  const bool mf32 = m_prec == ECSIM_F32;
+  const double ctd = kC * kTheta * g.dt, ctd2 = ctd * ctd, cm = 4.0 * kPi * kTheta * g.dt;
+  CurlK K;
+  curl_curl_stencil(g, ctd2, K);
   hipError_t e;
 #define HIPCK(x)                                                 \
   do {                                                           \
     if ((e = (x)) != hipSuccess) return hip_fail(e, "ecsim_field_solve"); \
   } while (0)
 
-  // b = E^n - 4 pi theta dt J + c theta dt curl_N B_C^n
-  HIPCK(launch_rhs(g, E_n, m_prec == ECSIM_F32, J, B_C_n, -4.0 * kPi * kTheta * g.dt, kC * kTheta * g.dt, bvec, st));
-  HIPCK(hipMemcpyAsync(E_theta, E_n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-  HIPCK(launch_dots(bvec, ld, 1, bvec, n, partial, nrm, st));
+  // Restarted GMRES(m), classical Gram-Schmidt applied twice, from E^n. A
+  // step is three kernels (operator with the first pass's inner products,
+  // first pass with the second's, second pass with the new norm); the
+  // normalisation and the Givens update of H and g ride on the next step's
+  // first kernel, and every inner product is summed by the kernel that needs
+  // it. The host only decides how many steps to launch before it next reads
+  // the residual history (what the last solve needed at the start, then as
+  // many as the observed convergence rate predicts): steps launched past
+  // convergence change nothing. A cycle ends with X += V y and the true
+  // residual, read back once with the field advance already launched.
+  std::vector<double> hb(rb_count);
+  auto read_back = [&]() -> hipError_t {
+    hipError_t r = hipMemcpyAsync(hb.data(), rb, sizeof(double) * rb_count, hipMemcpyDeviceToHost, st);
+    return r != hipSuccess ? r : hipStreamSynchronize(st);
+  };
+  auto host_sum = [&](size_t off) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += hb[off + b];
+    return s;
+  };
+  const size_t off_pb = 5 + (size_t)m, off_p3 = off_pb + nb;
+  const int* flags = (const int*)(hb.data() + 4 + m);
+  const double* hh = hb.data() + 4;
 
-  // Restarted GMRES(m) with classical Gram-Schmidt applied twice. Every
-  // Arnoldi step runs on the device (matrix apply, both projection passes,
-  // the norm, the new basis vector and the Givens update of H and g); the
-  // host only decides how many steps to launch before it next reads the
-  // residual history: two at the start of a cycle, then as many as the
-  // observed convergence rate predicts are needed, so that a cycle takes a
-  // few host reads instead of three per step. Steps launched past
-  // convergence change nothing (the Givens kernel freezes the state).
-  std::vector<double> hh((size_t)m);
-  int st2[2] = {0, 0};
-  double bnorm = 0.0;
+  HIPCK(launch_rhs_start(g, E_n, mf32, J, B_C_n, -4.0 * kPi * kTheta * g.dt, ctd, bvec, E_theta, Pb, st));
+  HIPCK(launch_residual_op(g, mf32, M, K, cm, E_theta, bvec, Wb[0], P3, st));
   int it = 0;
-  double rel = 0.0;
-  bool converged = false;
-  bool first = true;
+  double rel = 0.0, bnorm = 0.0;
+  bool converged = false, first = true;
   while (true) {
-    // r = b - A x  (into V_0) and its norm; the first cycle also reads |b|
-    HIPCK(S.apply(E_theta, w));
-    HIPCK(hipMemcpyAsync(V, bvec, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    HIPCK(launch_axpby(n, -1.0, w, 1.0, V, st));
-    HIPCK(launch_dots(V, ld, 1, V, n, partial, nrm + 1, st));
-    double nh[2] = {0.0, 0.0};
-    HIPCK(hipMemcpyAsync(nh, nrm, sizeof nh, hipMemcpyDeviceToHost, st));
-    HIPCK(hipStreamSynchronize(st));
-    if (first) {
-      if (!std::isfinite(nh[0]))
-        return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the right-hand side is not finite (J, E^n or B^n)");
-      bnorm = std::sqrt(nh[0]);
-      first = false;
-      if (bnorm == 0.0) {
-        HIPCK(launch_scale_copy(n, 0.0, E_n, E_theta, st));
-        converged = true;
-        break;
-      }
-    }
-    if (!std::isfinite(nh[1]))
-      return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the residual is not finite (M or the iterate)");
-    const double beta = std::sqrt(nh[1]);
-    rel = beta / bnorm;
-    if (rel <= tol) { converged = true; break; }
-    if (it >= maxit) break;
-    HIPCK(launch_scale_copy(n, 1.0 / beta, V, V, st));
-    HIPCK(launch_gmres_start(m, beta, gv, state, st));
-    const double thresh = 0.5 * tol * bnorm;
-    int j = 0;          // steps launched in this cycle
-    int used = 0;       // steps that count (up to convergence)
-    int batch = 2;
+    int j = 0, used = 0;
+    int batch = std::max(1, std::min(g_first_batch.load(std::memory_order_relaxed), m));
     bool done = false;
     while (!done) {
-      const int nb = std::min(std::min(batch, m - j), maxit - it - j);
-      for (int s = j; s < j + nb; ++s) {
-        double* Vs = V + (size_t)s * ld;
-        double* Vs1 = V + (size_t)(s + 1) * ld;
-        HIPCK(S.apply(Vs, w));
-        HIPCK(launch_dots(V, ld, s + 1, w, n, partial, h1, st));
-        HIPCK(launch_sub_combo_dev(V, ld, s + 1, h1, w, n, st));
-        HIPCK(launch_dots(V, ld, s + 1, w, n, partial, h2, st));
-        HIPCK(launch_sub_combo_dev(V, ld, s + 1, h2, w, n, st));
-        HIPCK(launch_dots(w, ld, 1, w, n, partial, nrm + 2, st));
-        HIPCK(launch_normalize(w, nrm + 2, Vs1, n, st));
-        HIPCK(launch_givens(s, m, H, cs, sn, gv, h1, h2, nrm + 2, thresh, state, hist, st));
+      const int nbat = std::min(std::min(batch, m - j), maxit - it - j);
+      for (int s = j; s < j + nbat; ++s) {
+        const int mode = s == 0 ? kArnoldiStart : (s > j ? kArnoldiGivens : kArnoldiNone);
+        double* w = Wb[(s + 1) & 1];
+        HIPCK(launch_arnoldi_op(g, mf32, M, K, cm, Wb[s & 1], w, V, ld, s, mode, P3, P1, G, st));
+        HIPCK(launch_cgs_pass(g, false, V, ld, s + 1, P1, G.h1, w, P2, st));
+        HIPCK(launch_cgs_pass(g, true, V, ld, s + 1, P2, G.h2, w, P3, st));
       }
-      HIPCK(hipMemcpyAsync(hh.data() + j, hist + j, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
-      HIPCK(hipMemcpyAsync(st2, state, sizeof st2, hipMemcpyDeviceToHost, st));
-      HIPCK(hipStreamSynchronize(st));
-      j += nb;
-      used = st2[1];
-      for (int s = j - nb; s < j; ++s)
+      HIPCK(launch_givens_tail(g, j + nbat - 1, P3, G, st));
+      HIPCK(read_back());
+      if (first) {
+        const double bb = host_sum(off_pb);
+        if (!std::isfinite(bb))
+          return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the right-hand side is not finite (J, E^n or B^n)");
+        bnorm = std::sqrt(bb);
+        first = false;
+      }
+      if (j == 0) {
+        if (!std::isfinite(hb[1]))
+          return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the residual is not finite (M or the iterate)");
+        if (bnorm == 0.0 || hb[1] <= tol * bnorm) break;   // nothing to do: used = 0
+      }
+      for (int s = j; s < j + nbat; ++s)
         if (!std::isfinite(hh[s]))
           return fail(ECSIM_ENONFINITE, "ecsim_field_solve: a Krylov vector is not finite (M is not finite)");
-      done = st2[0] == 0 || j >= m || it + j >= maxit;
+      j += nbat;
+      used = flags[1];
+      done = flags[0] == 0 || j >= m || it + j >= maxit;
       if (!done) {
         // steps still needed at the rate of the last two: |g| falls by about
         // hist[j-1] / hist[j-2] per step
         int next = 1;
         if (j >= 2 && hh[j - 1] > 0.0 && hh[j - 2] > hh[j - 1]) {
           const double rate = hh[j - 1] / hh[j - 2];
-          const double k = std::log(thresh / hh[j - 1]) / std::log(rate);
+          const double k = std::log(hb[0] / hh[j - 1]) / std::log(rate);
           next = k < 1.0 ? 1 : (k > (double)m ? m : (int)std::ceil(k));
         }
         batch = next;
       }
     }
+    if (it == 0 && used > 0) g_first_batch.store(used, std::memory_order_relaxed);
     it += used;
-    // x += V y, y from the j x j triangle (on the device)
-    if (used > 0) {
-      HIPCK(launch_backsolve(H, gv, m, used, ny, st));
-      HIPCK(launch_sub_combo_dev(V, ld, used, ny, E_theta, n, st));
+    if (bnorm == 0.0) {
+      // b = 0: E^{n+theta} = 0
+      HIPCK(launch_zero(E_theta, sizeof(double) * 3 * (size_t)g.nn, st));
+      HIPCK(launch_finish(g, E_n, E_theta, B_C_n, ctd, E_next, B_C_next, st));
+      HIPCK(hipStreamSynchronize(st));
+      converged = true;
+      rel = 0.0;
+      break;
     }
+    if (used > 0) HIPCK(launch_update_x(g, G.H, G.gv, m, used, V, ld, E_theta, st));
+    HIPCK(launch_residual_op(g, mf32, M, K, cm, E_theta, bvec, Wb[0], P3, st));
+    HIPCK(launch_finish(g, E_n, E_theta, B_C_n, ctd, E_next, B_C_next, st));
+    HIPCK(read_back());
+    rel = std::sqrt(host_sum(off_p3)) / bnorm;
+    if (!std::isfinite(rel))
+      return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the residual is not finite (M or the iterate)");
+    if (rel <= tol) {
+      converged = true;
+      break;
+    }
+    if (it >= maxit || used == 0) break;
   }
-  // advance the fields: B_C^{n+theta} = B_C^n - c theta dt curl_C E^{n+theta}
-  HIPCK(launch_curl_C(g, E_theta, cc, st));
-  HIPCK(launch_finish(g, E_n, E_theta, B_C_n, cc, kC * kTheta * g.dt, E_next, B_C_next, st));
-  HIPCK(hipStreamSynchronize(st));
 #undef HIPCK
   if (iters_out) *iters_out = it;
   if (resid_out) *resid_out = rel;

@@ -324,7 +324,7 @@ __device__ __forceinline__ Vec3<T> rotation_vjp(const T a[9], Vec3<T> B, T beta,
 }
 
 // The 14 stored neighbour offsets (see the header): o_k for k = 0..13.
-__device__ __forceinline__ void offset14(int k, int& ox, int& oy, int& oz) {
+__host__ __device__ __forceinline__ void offset14(int k, int& ox, int& oy, int& oz) {
   if (k == 0) { ox = 0; oy = 0; oz = 0; }
   else if (k == 1) { ox = 1; oy = 0; oz = 0; }
   else if (k < 5) { ox = k - 3; oy = 1; oz = 0; }

@@ -80,10 +80,8 @@ __global__ void __launch_bounds__(kBlock) k_mass_apply(Grid g, const TM* __restr
 // staggered curls: E on nodes, B on cell centres; each derivative averages the
 // four edge differences parallel to its axis (curl_N = curl_C^T).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_curl_C(Grid g, const double* __restrict__ E, double* __restrict__ out) {
+__device__ __forceinline__ void curl_C_at(const Grid& g, const double* __restrict__ E, int64_t c, double r[3]) {
   const int64_t nn = g.nn;
-  const int64_t c = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (c >= nn) return;
   int cx, cy, cz;
   decode_cell(g, (int)c, cx, cy, cz);
   const int xs[2] = {cx, wp(cx, g.nx)}, ys[2] = {cy, wp(cy, g.ny)}, zs[2] = {cz, wp(cz, g.nz)};
@@ -107,9 +105,9 @@ __global__ void __launch_bounds__(kBlock) k_curl_C(Grid g, const double* __restr
       }
     }
   const double ix = 1.0 / (4.0 * g.hx), iy = 1.0 / (4.0 * g.hy), iz = 1.0 / (4.0 * g.hz);
-  out[c] = d[1][2] * iy - d[2][1] * iz;
-  out[nn + c] = d[2][0] * iz - d[0][2] * ix;
-  out[2 * nn + c] = d[0][1] * ix - d[1][0] * iy;
+  r[0] = d[1][2] * iy - d[2][1] * iz;
+  r[1] = d[2][0] * iz - d[0][2] * ix;
+  r[2] = d[0][1] * ix - d[1][0] * iy;
 }
 
 __device__ __forceinline__ void curl_N_at(const Grid& g, const double* __restrict__ B, int64_t nd, double r[3]) {
@@ -141,41 +139,6 @@ __device__ __forceinline__ void curl_N_at(const Grid& g, const double* __restric
   r[0] = d[1][2] * iy - d[2][1] * iz;
   r[1] = d[2][0] * iz - d[0][2] * ix;
   r[2] = d[0][1] * ix - d[1][0] * iy;
-}
-
-// out = E + ctd2 * curl_N(cC), cC = curl_C E (the curl-curl part of A E)
-__global__ void __launch_bounds__(kBlock) k_field_op_curl(Grid g, const double* __restrict__ E,
-                                                          const double* __restrict__ cC, double ctd2,
-                                                          double* __restrict__ out) {
-  const int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (nd >= g.nn) return;
-  double r[3];
-  curl_N_at(g, cC, nd, r);
-  for (int c = 0; c < 3; ++c) out[c * g.nn + nd] = E[c * g.nn + nd] + ctd2 * r[c];
-}
-
-// b = E_n + c_j J + c_b curl_N(BC)
-template <typename TJ>
-__global__ void __launch_bounds__(kBlock) k_rhs(Grid g, const double* __restrict__ En, const TJ* __restrict__ J,
-                                                const double* __restrict__ BC, double c_j, double c_b,
-                                                double* __restrict__ b) {
-  const int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (nd >= g.nn) return;
-  double r[3];
-  curl_N_at(g, BC, nd, r);
-  for (int c = 0; c < 3; ++c) b[c * g.nn + nd] = (En[c * g.nn + nd] + c_j * (double)J[c * g.nn + nd]) + c_b * r[c];
-}
-
-// E^{n+1} = 2 E^{n+theta} - E^n; B^{n+1} = 2 (B^n - ctd curl_C E^{n+theta}) - B^n
-__global__ void __launch_bounds__(kBlock) k_finish(int64_t n3, const double* __restrict__ En,
-                                                   const double* __restrict__ Et, const double* __restrict__ BCn,
-                                                   const double* __restrict__ cc, double ctd,
-                                                   double* __restrict__ En1, double* __restrict__ BCn1) {
-  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i >= n3) return;
-  En1[i] = 2.0 * Et[i] - En[i];
-  double bt = BCn[i] - ctd * cc[i];
-  BCn1[i] = 2.0 * bt - BCn[i];
 }
 
 __global__ void __launch_bounds__(kBlock) k_centres_to_nodes(Grid g, const double* __restrict__ BC,
@@ -217,30 +180,6 @@ __device__ __forceinline__ double block_reduce(double v) {
   return s;
 }
 
-// partial[v * kDotBlocks + blk] = sum over this block's slice of V_v . w
-__global__ void __launch_bounds__(kBlock) k_dots_partial(const double* __restrict__ V, int64_t ld, int nv,
-                                                         const double* __restrict__ w, int64_t n,
-                                                         double* __restrict__ partial) {
-  for (int v = 0; v < nv; ++v) {
-    const double* Vv = V + v * ld;
-    double s = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-      s = fma(Vv[i], w[i], s);
-    s = block_reduce(s);
-    if (threadIdx.x == 0) partial[v * kDotBlocks + blockIdx.x] = s;
-  }
-}
-
-__global__ void __launch_bounds__(kBlock) k_dots_final(const double* __restrict__ partial, int nv,
-                                                       double* __restrict__ out) {
-  // one block per vector
-  const int v = blockIdx.x;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < kDotBlocks; i += kBlock) s += partial[v * kDotBlocks + i];
-  s = block_reduce(s);
-  if (threadIdx.x == 0) out[v] = s;
-}
-
 __global__ void __launch_bounds__(kBlock) k_sumsq_partial(const double* __restrict__ x, int64_t n,
                                                           double* __restrict__ partial) {
   double s = 0.0;
@@ -256,104 +195,6 @@ __global__ void __launch_bounds__(kBlock) k_sumsq_final(const double* __restrict
   for (int i = threadIdx.x; i < kDotBlocks; i += kBlock) s += partial[i];
   s = block_reduce(s);
   if (threadIdx.x == 0) *out = accumulate ? *out + scale * s : scale * s;
-}
-
-struct Coefs {
-  double c[kMaxRestart + 1];
-};
-
-__global__ void __launch_bounds__(kBlock) k_sub_combo(const double* __restrict__ V, int64_t ld, int nv, Coefs coef,
-                                                      double* __restrict__ w, int64_t n) {
-  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i >= n) return;
-  double s = w[i];
-  for (int v = 0; v < nv; ++v) s -= coef.c[v] * V[v * ld + i];
-  w[i] = s;
-}
-
-// w -= sum_v coef[v] V_v with the coefficients in device memory
-__global__ void __launch_bounds__(kBlock) k_sub_combo_dev(const double* __restrict__ V, int64_t ld, int nv,
-                                                          const double* __restrict__ coef, double* __restrict__ w,
-                                                          int64_t n) {
-  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i >= n) return;
-  double s = w[i];
-  for (int v = 0; v < nv; ++v) s -= coef[v] * V[v * ld + i];
-  w[i] = s;
-}
-
-// out = w / sqrt(*nrm2) (zeros when the norm is zero: a Krylov breakdown)
-__global__ void __launch_bounds__(kBlock) k_normalize(const double* __restrict__ w, const double* __restrict__ nrm2,
-                                                      double* __restrict__ out, int64_t n) {
-  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double s = *nrm2;
-  out[i] = s > 0.0 ? w[i] / sqrt(s) : 0.0;
-}
-
-// One Arnoldi column on the device (one thread): H[:, j] from the two
-// Gram-Schmidt passes and the new vector's norm, the earlier Givens rotations
-// applied to it, a new rotation that zeroes H[j+1][j], and the rotated
-// right-hand side g. hist[j] = |g[j+1]|, the residual norm of the least-squares
-// problem after j + 1 steps. Once that norm is below thresh (or the Krylov
-// space broke down), state[0] = 0 and later calls leave everything as is, so
-// steps launched past convergence change nothing. state[1] = columns used.
-__global__ void k_givens(int j, int m, double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
-                         double* __restrict__ gv, const double* __restrict__ h1, const double* __restrict__ h2,
-                         const double* __restrict__ hn2, double thresh, int* __restrict__ state,
-                         double* __restrict__ hist) {
-  if (state[0] == 0) {
-    hist[j] = -1.0;
-    return;
-  }
-  const double hn = sqrt(*hn2 > 0.0 ? *hn2 : 0.0);
-  for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] = h1[i] + h2[i];
-  H[(int64_t)(j + 1) * m + j] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double a = H[(int64_t)i * m + j], b = H[(int64_t)(i + 1) * m + j];
-    H[(int64_t)i * m + j] = cs[i] * a + sn[i] * b;
-    H[(int64_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
-  }
-  const double a = H[(int64_t)j * m + j], b = H[(int64_t)(j + 1) * m + j];
-  const double rr = hypot(a, b);
-  cs[j] = rr > 0.0 ? a / rr : 1.0;
-  sn[j] = rr > 0.0 ? b / rr : 0.0;
-  H[(int64_t)j * m + j] = rr;
-  H[(int64_t)(j + 1) * m + j] = 0.0;
-  gv[j + 1] = -sn[j] * gv[j];
-  gv[j] = cs[j] * gv[j];
-  hist[j] = fabs(gv[j + 1]);
-  state[1] = j + 1;
-  if (hist[j] <= thresh || hn == 0.0) state[0] = 0;
-}
-
-// start of a restart cycle: g = (beta, 0, ...), one active iteration state
-__global__ void k_gmres_start(int m, double beta, double* __restrict__ gv, int* __restrict__ state) {
-  for (int i = 0; i <= m; ++i) gv[i] = i == 0 ? beta : 0.0;
-  state[0] = 1;
-  state[1] = 0;
-}
-
-// back substitution of the j x j triangle H y = g (one thread); writes -y
-__global__ void k_backsolve(const double* __restrict__ H, const double* __restrict__ gv, int m, int j,
-                            double* __restrict__ ny) {
-  for (int i = j - 1; i >= 0; --i) {
-    double s = gv[i];
-    for (int k = i + 1; k < j; ++k) s += H[(int64_t)i * m + k] * ny[k];   // ny[k] = -y[k]
-    ny[i] = -(s / H[(int64_t)i * m + i]);
-  }
-}
-
-__global__ void __launch_bounds__(kBlock) k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
-                                                  double* __restrict__ y) {
-  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i < n) y[i] = a * x[i] + b * y[i];
-}
-
-__global__ void __launch_bounds__(kBlock) k_scale_copy(int64_t n, double a, const double* __restrict__ x,
-                                                       double* __restrict__ y) {
-  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i < n) y[i] = a * x[i];
 }
 
 // the non-finite flag, read and cleared in stream order
@@ -373,6 +214,380 @@ __global__ void __launch_bounds__(kBlock) k_zero16(uint4* __restrict__ p, int64_
   for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n16; i += (int64_t)gridDim.x * kBlock) p[i] = z;
 }
 
+
+// ---------------------------------------------------------------------------
+// GMRES kernels (FP64). Each takes one node (its three components) per thread
+// in workgroups of kSolveBlock threads, so all of them write and read
+// per-workgroup partial sums over the same nblk = ceil(Nn / kSolveBlock)
+// slots. A kernel that needs an inner product sums the partials of the kernel
+// before it (every workgroup in the same fixed order, so all of them get the
+// same value) instead of waiting for a reduction launch of its own.
+// ---------------------------------------------------------------------------
+constexpr int kVW = kSolveBlock / 64;                 // wavefronts per workgroup
+constexpr int kRed = (kMaxRestart + 1) * kVW;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  return v;  // in lane 0
+}
+
+// out[v] (LDS) = sum over b < nblk of P[v nblk + b], for v < nv
+__device__ void sum_partials(const double* __restrict__ P, int nblk, int nv, double* red, double* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int v = 0; v < nv; ++v) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kSolveBlock) s += P[(int64_t)v * nblk + b];
+    s = wave_sum(s);
+    if (lane == 0) red[v * kVW + wv] = s;
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < nv; v += kSolveBlock) {
+    double s = 0.0;
+    for (int i = 0; i < kVW; ++i) s += red[v * kVW + i];
+    out[v] = s;
+  }
+  __syncthreads();
+}
+
+// P[v nblk + slot] = this workgroup's sum of val(v), for v < nv
+template <class F>
+__device__ void write_partials(int nv, F val, double* red, double* __restrict__ P, int nblk, int slot) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int v = 0; v < nv; ++v) {
+    const double s = wave_sum(val(v));
+    if (lane == 0) red[v * kVW + wv] = s;
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < nv; v += kSolveBlock) {
+    double s = 0.0;
+    for (int i = 0; i < kVW; ++i) s += red[v * kVW + i];
+    P[(int64_t)v * nblk + slot] = s;
+  }
+}
+
+// Workgroups go to the 8 XCDs in turn; give each XCD a contiguous eighth of
+// the nodes, so that the blocks and values read again from a neighbouring
+// node are still in that XCD's L2.
+__device__ __forceinline__ int xcd_block() {
+  int blk = blockIdx.x;
+  if ((gridDim.x & 7) == 0) blk = (blk & 7) * (gridDim.x >> 3) + (blk >> 3);
+  return blk;
+}
+
+// y = (A x)(node) for x = sc X: x + (c theta dt)^2 curl_N curl_C x + cm M x;
+// xo = x at the node itself. The curl-curl term is a 27-point stencil over
+// the same neighbours the 14 stored mass-matrix blocks couple. It is even in
+// the offset o, so it acts on u(o) = x(g + o) + x(g - o) over the 13 stored
+// offsets (u(0) = x(g)), and each of its coefficients is an integer weight
+// of o times (c theta dt)^2 / (16 h_r h_c) (curl_curl_stencil):
+//   (curl_N curl_C x)_r = sum_{c != r} K_rc S_rc - sum_{d != r} K_dd L_dr,
+//   S_rc = sum_o o_r o_c (2 - |o_e|) u_c(o)        (e: the third axis),
+//   L_dr = sum_o q(o_d) prod_{a != d} (2 - |o_a|) u_r(o),  q(0) = -2, q(+-1) = 1,
+// so the weights are compile-time constants and only the six K values are
+// read at run time.
+template <typename TM>
+__device__ __forceinline__ void apply_at(const Grid& g, const TM* __restrict__ M, const CurlK& K, double cm,
+                                         const double* __restrict__ X, double sc, int64_t gid, double y[3],
+                                         double xo[3]) {
+  const int64_t nn = g.nn;
+  int ix, iy, iz;
+  decode_cell(g, (int)gid, ix, iy, iz);
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+  double S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+  for (int k = 0; k < 14; ++k) {
+    int o[3];
+    offset14(k, o[0], o[1], o[2]);
+    const TM* Mk = M + (int64_t)k * 9 * nn;
+    double u[3];
+    {
+      const int64_t gp =
+          shift(ix, o[0], g.nx) + (int64_t)g.nx * (shift(iy, o[1], g.ny) + (int64_t)g.ny * shift(iz, o[2], g.nz));
+      const double e0 = sc * X[gp], e1 = sc * X[nn + gp], e2 = sc * X[2 * nn + gp];
+      if (k == 0) {
+        xo[0] = e0;
+        xo[1] = e1;
+        xo[2] = e2;
+      }
+      m0 = fma((double)Mk[0 * nn + gid], e0, m0);
+      m0 = fma((double)Mk[1 * nn + gid], e1, m0);
+      m0 = fma((double)Mk[2 * nn + gid], e2, m0);
+      m1 = fma((double)Mk[3 * nn + gid], e0, m1);
+      m1 = fma((double)Mk[4 * nn + gid], e1, m1);
+      m1 = fma((double)Mk[5 * nn + gid], e2, m1);
+      m2 = fma((double)Mk[6 * nn + gid], e0, m2);
+      m2 = fma((double)Mk[7 * nn + gid], e1, m2);
+      m2 = fma((double)Mk[8 * nn + gid], e2, m2);
+      u[0] = e0;
+      u[1] = e1;
+      u[2] = e2;
+    }
+    if (k > 0) {
+      const int64_t gm = shift(ix, -o[0], g.nx) +
+                         (int64_t)g.nx * (shift(iy, -o[1], g.ny) + (int64_t)g.ny * shift(iz, -o[2], g.nz));
+      const double e0 = sc * X[gm], e1 = sc * X[nn + gm], e2 = sc * X[2 * nn + gm];
+      m0 = fma((double)Mk[0 * nn + gm], e0, m0);
+      m0 = fma((double)Mk[1 * nn + gm], e1, m0);
+      m0 = fma((double)Mk[2 * nn + gm], e2, m0);
+      m1 = fma((double)Mk[3 * nn + gm], e0, m1);
+      m1 = fma((double)Mk[4 * nn + gm], e1, m1);
+      m1 = fma((double)Mk[5 * nn + gm], e2, m1);
+      m2 = fma((double)Mk[6 * nn + gm], e0, m2);
+      m2 = fma((double)Mk[7 * nn + gm], e1, m2);
+      m2 = fma((double)Mk[8 * nn + gm], e2, m2);
+      u[0] += e0;
+      u[1] += e1;
+      u[2] += e2;
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (r == c) continue;
+        const int e = 3 - r - c;
+        const int ws = o[r] * o[c] * (2 - abs(o[e]));
+        if (ws != 0) S[r][c] = fma((double)ws, u[c], S[r][c]);
+        // L[d = r][comp = c]
+        const int wl = (o[r] == 0 ? -2 : 1) * (2 - abs(o[c])) * (2 - abs(o[e]));
+        L[r][c] = fma((double)wl, u[c], L[r][c]);
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    double cc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (c != r) cc = fma(K.k[r][c], S[r][c], fma(-K.k[c][c], L[c][r], cc));
+    y[r] = xo[r] + cc + cm * (r == 0 ? m0 : (r == 1 ? m1 : m2));
+  }
+}
+
+__device__ __forceinline__ int* gmres_flags(const GmresState& G) { return (int*)(G.rb + 4 + G.m); }
+
+// Column j of the Arnoldi process on the device (one thread): H[:, j] from
+// the two Gram-Schmidt passes and the new vector's norm hn, the earlier
+// Givens rotations applied to it, a new rotation that zeroes H[j+1][j], and
+// the rotated right-hand side g. hist[j] = |g[j+1]|, the least-squares
+// residual after j + 1 steps. Once it is below the threshold (or the Krylov
+// space broke down) flags[0] = 0, and later columns leave everything as it
+// is, so steps launched past convergence change nothing. flags[1] = columns
+// that count.
+__device__ void givens_column(int j, const GmresState& G, double hn) {
+  int* fl = gmres_flags(G);
+  double* hist = G.rb + 4;
+  if (fl[0] == 0) {
+    hist[j] = -1.0;
+    return;
+  }
+  const int m = G.m;
+  double* H = G.H;
+  for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] = G.h1[i] + G.h2[i];
+  H[(int64_t)(j + 1) * m + j] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = H[(int64_t)i * m + j], b = H[(int64_t)(i + 1) * m + j];
+    H[(int64_t)i * m + j] = G.cs[i] * a + G.sn[i] * b;
+    H[(int64_t)(i + 1) * m + j] = -G.sn[i] * a + G.cs[i] * b;
+  }
+  const double a = H[(int64_t)j * m + j], b = H[(int64_t)(j + 1) * m + j];
+  const double rr = hypot(a, b);
+  G.cs[j] = rr > 0.0 ? a / rr : 1.0;
+  G.sn[j] = rr > 0.0 ? b / rr : 0.0;
+  H[(int64_t)j * m + j] = rr;
+  H[(int64_t)(j + 1) * m + j] = 0.0;
+  G.gv[j + 1] = -G.sn[j] * G.gv[j];
+  G.gv[j] = G.cs[j] * G.gv[j];
+  hist[j] = fabs(G.gv[j + 1]);
+  fl[1] = j + 1;
+  if (hist[j] <= G.rb[0] || hn == 0.0) fl[0] = 0;
+}
+
+// b = E^n + c_j J + c_b curl_N(B_C^n), E_theta = E^n, Pb: partial |b|^2
+template <typename TJ>
+__global__ void __launch_bounds__(kSolveBlock) k_rhs_start(Grid g, const double* __restrict__ En,
+                                                           const TJ* __restrict__ J, const double* __restrict__ BC,
+                                                           double c_j, double c_b, double* __restrict__ b,
+                                                           double* __restrict__ Et, double* __restrict__ Pb,
+                                                           int nblk) {
+  __shared__ double red[kVW];
+  const int64_t nn = g.nn, i = (int64_t)blockIdx.x * kSolveBlock + threadIdx.x;
+  double bv[3] = {0.0, 0.0, 0.0};
+  if (i < nn) {
+    double r[3];
+    curl_N_at(g, BC, i, r);
+    for (int c = 0; c < 3; ++c) {
+      const double e = En[c * nn + i];
+      bv[c] = (e + c_j * (double)J[c * nn + i]) + c_b * r[c];
+      b[c * nn + i] = bv[c];
+      Et[c * nn + i] = e;
+    }
+  }
+  write_partials(1, [&](int) { return bv[0] * bv[0] + bv[1] * bv[1] + bv[2] * bv[2]; }, red, Pb, nblk, blockIdx.x);
+}
+
+// R = b - A X, P3: partial |R|^2
+template <typename TM>
+__global__ void __launch_bounds__(kSolveBlock) k_residual_op(Grid g, const TM* __restrict__ M, CurlK K,
+                                                             double cm, const double* __restrict__ X,
+                                                             const double* __restrict__ b, double* __restrict__ R,
+                                                             double* __restrict__ P3, int nblk) {
+  __shared__ double red[kVW];
+  const int blk = xcd_block();
+  const int64_t nn = g.nn, i = (int64_t)blk * kSolveBlock + threadIdx.x;
+  double r[3] = {0.0, 0.0, 0.0};
+  if (i < nn) {
+    double y[3], xo[3];
+    apply_at(g, M, K, cm, X, 1.0, i, y, xo);
+    for (int c = 0; c < 3; ++c) {
+      r[c] = b[c * nn + i] - y[c];
+      R[c * nn + i] = r[c];
+    }
+  }
+  write_partials(1, [&](int) { return r[0] * r[0] + r[1] * r[1] + r[2] * r[2]; }, red, P3, nblk, blk);
+}
+
+// Step s of the Arnoldi process, first kernel: V_s = w_s / |w_s| (|w_s|^2
+// from the partials P3), w = A V_s into Wout and the first Gram-Schmidt
+// pass's partial inner products <V_v, w>, v <= s, into P1. Workgroup 0 also
+// starts the restart cycle (s = 0: g = (beta, 0, ...), the threshold from
+// |b|) or closes column s - 1 (its Givens rotation needs |w_s|).
+template <typename TM>
+__global__ void __launch_bounds__(kSolveBlock) k_arnoldi_op(Grid g, const TM* __restrict__ M, CurlK K,
+                                                            double cm, const double* __restrict__ Win,
+                                                            double* __restrict__ Wout, double* __restrict__ V,
+                                                            int64_t ld, int s, int mode,
+                                                            const double* __restrict__ P3, double* __restrict__ P1,
+                                                            int nblk, GmresState G) {
+  __shared__ double red[kRed];
+  __shared__ double sc[2];
+  sum_partials(P3, nblk, 1, red, sc);
+  const double hn = sqrt(sc[0]);
+  const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
+  if (blockIdx.x == 0 && mode != kArnoldiNone) {
+    if (mode == kArnoldiStart) sum_partials(G.Pb, nblk, 1, red, sc + 1);
+    if (threadIdx.x == 0) {
+      if (mode == kArnoldiStart) {
+        const double thresh = 0.5 * G.tol * sqrt(sc[1]);
+        G.rb[0] = thresh;
+        G.rb[1] = hn;
+        for (int i = 0; i <= G.m; ++i) G.gv[i] = i == 0 ? hn : 0.0;
+        int* fl = gmres_flags(G);
+        fl[0] = hn > thresh ? 1 : 0;
+        fl[1] = 0;
+      } else {
+        givens_column(s - 1, G, hn);
+      }
+    }
+  }
+  const int blk = xcd_block();
+  const int64_t nn = g.nn, i = (int64_t)blk * kSolveBlock + threadIdx.x;
+  const bool live = i < nn;
+  double y[3] = {0.0, 0.0, 0.0}, xo[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    apply_at(g, M, K, cm, Win, inv, i, y, xo);
+    double* Vs = V + (int64_t)s * ld;
+    for (int c = 0; c < 3; ++c) {
+      Vs[c * nn + i] = xo[c];
+      Wout[c * nn + i] = y[c];
+    }
+  }
+  write_partials(
+      s + 1,
+      [&](int v) {
+        if (!live) return 0.0;
+        if (v == s) return xo[0] * y[0] + xo[1] * y[1] + xo[2] * y[2];
+        const double* Vv = V + (int64_t)v * ld;
+        return Vv[i] * y[0] + Vv[nn + i] * y[1] + Vv[2 * nn + i] * y[2];
+      },
+      red, P1, nblk, blk);
+}
+
+// A Gram-Schmidt pass over V_0..V_{k-1}: h_v = the sums of the partials Pin,
+// w -= sum_v h_v V_v, then either the next pass's partial inner products
+// <V_v, w> (NORM false) or the partial |w|^2 (NORM true) into Pout.
+// Workgroup 0 stores h into coef for the Givens update.
+template <bool NORM>
+__global__ void __launch_bounds__(kSolveBlock) k_cgs_pass(const double* __restrict__ V, int64_t ld, int k, int64_t nn,
+                                                          const double* __restrict__ Pin, double* __restrict__ coef,
+                                                          double* __restrict__ W, double* __restrict__ Pout,
+                                                          int nblk) {
+  __shared__ double red[kRed];
+  __shared__ double h[kMaxRestart + 1];
+  sum_partials(Pin, nblk, k, red, h);
+  if (blockIdx.x == 0)
+    for (int v = threadIdx.x; v < k; v += kSolveBlock) coef[v] = h[v];
+  const int64_t i = (int64_t)blockIdx.x * kSolveBlock + threadIdx.x;
+  const bool live = i < nn;
+  double w[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    for (int c = 0; c < 3; ++c) w[c] = W[c * nn + i];
+    for (int v = 0; v < k; ++v) {
+      const double* Vv = V + (int64_t)v * ld;
+      for (int c = 0; c < 3; ++c) w[c] = fma(-h[v], Vv[c * nn + i], w[c]);
+    }
+    for (int c = 0; c < 3; ++c) W[c * nn + i] = w[c];
+  }
+  if (NORM) {
+    write_partials(1, [&](int) { return w[0] * w[0] + w[1] * w[1] + w[2] * w[2]; }, red, Pout, nblk, blockIdx.x);
+  } else {
+    write_partials(
+        k,
+        [&](int v) {
+          if (!live) return 0.0;
+          const double* Vv = V + (int64_t)v * ld;
+          return Vv[i] * w[0] + Vv[nn + i] * w[1] + Vv[2 * nn + i] * w[2];
+        },
+        red, Pout, nblk, blockIdx.x);
+  }
+}
+
+// the Givens update of column j after the last step of a batch
+__global__ void __launch_bounds__(kSolveBlock) k_givens_tail(int j, const double* __restrict__ P3, int nblk,
+                                                             GmresState G) {
+  __shared__ double red[kVW];
+  __shared__ double sc[1];
+  sum_partials(P3, nblk, 1, red, sc);
+  if (threadIdx.x == 0) givens_column(j, G, sqrt(sc[0]));
+}
+
+// X += V y, y from the j x j upper triangle H y = g (each workgroup solves
+// it, one thread, in the same order)
+__global__ void __launch_bounds__(kSolveBlock) k_update_x(const double* __restrict__ H, const double* __restrict__ gv,
+                                                          int m, int j, const double* __restrict__ V, int64_t ld,
+                                                          int64_t nn, double* __restrict__ X) {
+  __shared__ double y[kMaxRestart];
+  if (threadIdx.x == 0) {
+    for (int i = j - 1; i >= 0; --i) {
+      double s = gv[i];
+      for (int k = i + 1; k < j; ++k) s -= H[(int64_t)i * m + k] * y[k];
+      y[i] = s / H[(int64_t)i * m + i];
+    }
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kSolveBlock + threadIdx.x;
+  if (i >= nn) return;
+  for (int c = 0; c < 3; ++c) {
+    double x = X[c * nn + i];
+    for (int v = 0; v < j; ++v) x = fma(y[v], V[(int64_t)v * ld + c * nn + i], x);
+    X[c * nn + i] = x;
+  }
+}
+
+// E^{n+1} = 2 E^{n+theta} - E^n; B^{n+1} = 2 (B^n - ctd curl_C E^{n+theta}) - B^n
+__global__ void __launch_bounds__(kBlock) k_finish(Grid g, const double* __restrict__ En,
+                                                   const double* __restrict__ Et, const double* __restrict__ BCn,
+                                                   double ctd, double* __restrict__ En1, double* __restrict__ BCn1) {
+  const int64_t nn = g.nn, c = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (c >= nn) return;
+  double cc[3];
+  curl_C_at(g, Et, c, cc);
+  for (int comp = 0; comp < 3; ++comp) {
+    const int64_t i = comp * nn + c;
+    En1[i] = 2.0 * Et[i] - En[i];
+    const double bt = BCn[i] - ctd * cc[comp];
+    BCn1[i] = 2.0 * bt - BCn[i];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_mass_apply(const Grid& g, bool f32, const void* M, const double* x, double a, double b, double* y,
@@ -383,35 +598,6 @@ hipError_t launch_mass_apply(const Grid& g, bool f32, const void* M, const doubl
   else
     hipLaunchKernelGGL(k_mass_apply<double>, dim3(nblocks(g.nn, kBlock)), dim3(kBlock), 0, st, g, (const double*)M,
                        x, a, b, y);
-  return hipGetLastError();
-}
-
-hipError_t launch_curl_C(const Grid& g, const double* E, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_curl_C, dim3(nblocks(g.nn, kBlock)), dim3(kBlock), 0, st, g, E, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_field_op_curl(const Grid& g, const double* E, const double* cC, double ctd2, double* out,
-                                hipStream_t st) {
-  hipLaunchKernelGGL(k_field_op_curl, dim3(nblocks(g.nn, kBlock)), dim3(kBlock), 0, st, g, E, cC, ctd2, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_rhs(const Grid& g, const double* E_n, bool jf32, const void* J, const double* BC, double c_j,
-                      double c_b, double* b, hipStream_t st) {
-  if (jf32)
-    hipLaunchKernelGGL(k_rhs<float>, dim3(nblocks(g.nn, kBlock)), dim3(kBlock), 0, st, g, E_n, (const float*)J, BC,
-                       c_j, c_b, b);
-  else
-    hipLaunchKernelGGL(k_rhs<double>, dim3(nblocks(g.nn, kBlock)), dim3(kBlock), 0, st, g, E_n, (const double*)J,
-                       BC, c_j, c_b, b);
-  return hipGetLastError();
-}
-
-hipError_t launch_finish(const Grid& g, const double* E_n, const double* E_t, const double* BC_n,
-                         const double* curlC_Et, double ctd, double* E_next, double* BC_next, hipStream_t st) {
-  hipLaunchKernelGGL(k_finish, dim3(nblocks(3 * g.nn, kBlock)), dim3(kBlock), 0, st, 3 * g.nn, E_n, E_t, BC_n,
-                     curlC_Et, ctd, E_next, BC_next);
   return hipGetLastError();
 }
 
@@ -447,58 +633,84 @@ hipError_t launch_take_flag(int* flag, int32_t* out, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_dots(const double* V, int64_t ld, int nv, const double* w, int64_t n, double* partial, double* out,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_dots_partial, dim3(kDotBlocks), dim3(kBlock), 0, st, V, ld, nv, w, n, partial);
-  hipLaunchKernelGGL(k_dots_final, dim3(nv), dim3(kBlock), 0, st, partial, nv, out);
+// ---------------------------------------------------------------------------
+// GMRES launchers
+// ---------------------------------------------------------------------------
+void curl_curl_stencil(const Grid& g, double ctd2, CurlK& K) {
+  // curl_C and curl_N each weigh a difference along axis d by 1 / (4 h_d)
+  const double ih[3] = {1.0 / (4.0 * g.hx), 1.0 / (4.0 * g.hy), 1.0 / (4.0 * g.hz)};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) K.k[r][c] = ctd2 * ih[r] * ih[c];
+}
+
+int solve_blocks(const Grid& g) { return (int)((g.nn + kSolveBlock - 1) / kSolveBlock); }
+
+hipError_t launch_rhs_start(const Grid& g, const double* E_n, bool jf32, const void* J, const double* BC, double c_j,
+                            double c_b, double* b, double* E_t, double* Pb, hipStream_t st) {
+  const int nb = solve_blocks(g);
+  if (jf32)
+    hipLaunchKernelGGL(k_rhs_start<float>, dim3(nb), dim3(kSolveBlock), 0, st, g, E_n, (const float*)J, BC, c_j, c_b,
+                       b, E_t, Pb, nb);
+  else
+    hipLaunchKernelGGL(k_rhs_start<double>, dim3(nb), dim3(kSolveBlock), 0, st, g, E_n, (const double*)J, BC, c_j,
+                       c_b, b, E_t, Pb, nb);
   return hipGetLastError();
 }
 
-hipError_t launch_sub_combo(const double* V, int64_t ld, int nv, const double* coef_host, double* w, int64_t n,
-                            hipStream_t st) {
-  if (nv < 1 || nv > kMaxRestart + 1) return hipErrorInvalidValue;
-  Coefs c;
-  for (int v = 0; v < nv; ++v) c.c[v] = coef_host[v];
-  hipLaunchKernelGGL(k_sub_combo, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, st, V, ld, nv, c, w, n);
+hipError_t launch_residual_op(const Grid& g, bool mf32, const void* M, const CurlK& K, double cm,
+                              const double* X, const double* b, double* R, double* P3, hipStream_t st) {
+  const int nb = solve_blocks(g);
+  if (mf32)
+    hipLaunchKernelGGL(k_residual_op<float>, dim3(nb), dim3(kSolveBlock), 0, st, g, (const float*)M, K, cm, X,
+                       b, R, P3, nb);
+  else
+    hipLaunchKernelGGL(k_residual_op<double>, dim3(nb), dim3(kSolveBlock), 0, st, g, (const double*)M, K, cm,
+                       X, b, R, P3, nb);
   return hipGetLastError();
 }
 
-hipError_t launch_sub_combo_dev(const double* V, int64_t ld, int nv, const double* coef_dev, double* w, int64_t n,
-                                hipStream_t st) {
-  if (nv < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_sub_combo_dev, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, st, V, ld, nv, coef_dev, w, n);
+hipError_t launch_arnoldi_op(const Grid& g, bool mf32, const void* M, const CurlK& K, double cm,
+                             const double* Win, double* Wout, double* V, int64_t ld, int s, int mode,
+                             const double* P3, double* P1, const GmresState& G, hipStream_t st) {
+  if (s < 0 || s >= G.m) return hipErrorInvalidValue;
+  const int nb = solve_blocks(g);
+  if (mf32)
+    hipLaunchKernelGGL(k_arnoldi_op<float>, dim3(nb), dim3(kSolveBlock), 0, st, g, (const float*)M, K, cm, Win,
+                       Wout, V, ld, s, mode, P3, P1, nb, G);
+  else
+    hipLaunchKernelGGL(k_arnoldi_op<double>, dim3(nb), dim3(kSolveBlock), 0, st, g, (const double*)M, K, cm,
+                       Win, Wout, V, ld, s, mode, P3, P1, nb, G);
   return hipGetLastError();
 }
 
-hipError_t launch_normalize(const double* w, const double* nrm2, double* out, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_normalize, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, st, w, nrm2, out, n);
+hipError_t launch_cgs_pass(const Grid& g, bool norm, const double* V, int64_t ld, int k, const double* Pin,
+                           double* coef, double* W, double* Pout, hipStream_t st) {
+  if (k < 1 || k > kMaxRestart) return hipErrorInvalidValue;
+  const int nb = solve_blocks(g);
+  if (norm)
+    hipLaunchKernelGGL(k_cgs_pass<true>, dim3(nb), dim3(kSolveBlock), 0, st, V, ld, k, g.nn, Pin, coef, W, Pout, nb);
+  else
+    hipLaunchKernelGGL(k_cgs_pass<false>, dim3(nb), dim3(kSolveBlock), 0, st, V, ld, k, g.nn, Pin, coef, W, Pout, nb);
   return hipGetLastError();
 }
 
-hipError_t launch_givens(int j, int m, double* H, double* cs, double* sn, double* gv, const double* h1,
-                         const double* h2, const double* hn2, double thresh, int* state, double* hist,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, st, j, m, H, cs, sn, gv, h1, h2, hn2, thresh, state, hist);
+hipError_t launch_givens_tail(const Grid& g, int j, const double* P3, const GmresState& G, hipStream_t st) {
+  if (j < 0 || j >= G.m) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_givens_tail, dim3(1), dim3(kSolveBlock), 0, st, j, P3, solve_blocks(g), G);
   return hipGetLastError();
 }
 
-hipError_t launch_gmres_start(int m, double beta, double* gv, int* state, hipStream_t st) {
-  hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(1), 0, st, m, beta, gv, state);
+hipError_t launch_update_x(const Grid& g, const double* H, const double* gv, int m, int j, const double* V,
+                           int64_t ld, double* X, hipStream_t st) {
+  if (j < 1 || j > m || m > kMaxRestart) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_update_x, dim3(solve_blocks(g)), dim3(kSolveBlock), 0, st, H, gv, m, j, V, ld, g.nn, X);
   return hipGetLastError();
 }
 
-hipError_t launch_backsolve(const double* H, const double* gv, int m, int j, double* ny, hipStream_t st) {
-  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, st, H, gv, m, j, ny);
-  return hipGetLastError();
-}
-
-hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_axpby, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, st, n, a, x, b, y);
-  return hipGetLastError();
-}
-
-hipError_t launch_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_scale_copy, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, st, n, a, x, y);
+hipError_t launch_finish(const Grid& g, const double* E_n, const double* E_t, const double* BC_n, double ctd,
+                         double* E_next, double* BC_next, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish, dim3(nblocks(g.nn, kBlock)), dim3(kBlock), 0, st, g, E_n, E_t, BC_n, ctd, E_next,
+                     BC_next);
   return hipGetLastError();
 }
 

@@ -80,38 +80,56 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 // *out = *flag, then *flag = 0 (one thread, on the stream)
 hipError_t launch_take_flag(int* flag, int32_t* out, hipStream_t st);
 
-// field-solve building blocks (FP64)
-hipError_t launch_curl_C(const Grid& g, const double* E, double* out, hipStream_t st);
-hipError_t launch_field_op_curl(const Grid& g, const double* E, const double* curlC_E, double ctd2,
-                                double* out, hipStream_t st);
-hipError_t launch_rhs(const Grid& g, const double* E_n, bool jf32, const void* J, const double* BC, double c_j,
-                      double c_b, double* b, hipStream_t st);
-hipError_t launch_finish(const Grid& g, const double* E_n, const double* E_t, const double* BC_n,
-                         const double* curlC_Et, double ctd, double* E_next, double* BC_next, hipStream_t st);
-// out[v] = <V_v, w> for v < nv (V_v = V + v*ld); partial: >= nv*kDotBlocks doubles
-constexpr int kDotBlocks = 256;
-hipError_t launch_dots(const double* V, int64_t ld, int nv, const double* w, int64_t n, double* partial,
-                       double* out, hipStream_t st);
-// w -= sum_v coef[v] V_v  (coef: host array of nv <= kMaxRestart + 1 values,
-// passed to the kernel by value)
+// Field solve (FP64 GMRES). Every kernel takes one node per thread in
+// workgroups of kSolveBlock threads and writes or reads per-workgroup
+// partial sums over solve_blocks(g) slots.
+constexpr int kSolveBlock = 1024;
 constexpr int kMaxRestart = 120;
-hipError_t launch_sub_combo(const double* V, int64_t ld, int nv, const double* coef_host, double* w, int64_t n,
-                            hipStream_t st);
-// w -= sum_v coef[v] V_v with device coefficients
-hipError_t launch_sub_combo_dev(const double* V, int64_t ld, int nv, const double* coef_dev, double* w, int64_t n,
-                                hipStream_t st);
-// out = w / sqrt(*nrm2)
-hipError_t launch_normalize(const double* w, const double* nrm2, double* out, int64_t n, hipStream_t st);
-// the device-side GMRES bookkeeping: one Arnoldi column with its Givens
-// rotation, the start of a restart cycle, the final back substitution
-hipError_t launch_givens(int j, int m, double* H, double* cs, double* sn, double* gv, const double* h1,
-                         const double* h2, const double* hn2, double thresh, int* state, double* hist,
-                         hipStream_t st);
-hipError_t launch_gmres_start(int m, double beta, double* gv, int* state, hipStream_t st);
-hipError_t launch_backsolve(const double* H, const double* gv, int m, int j, double* ny, hipStream_t st);
-// y = a x + b y
-hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
-hipError_t launch_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t st);
+constexpr int kDotBlocks = 256;  // partials of launch_sumsq
+int solve_blocks(const Grid& g);
+// (c theta dt)^2 / (16 h_r h_c): the run-time factors of the curl-curl
+// stencil, whose integer weights the operator kernels hold as constants
+struct CurlK {
+  double k[3][3];
+};
+void curl_curl_stencil(const Grid& g, double ctd2, CurlK& K);
+// Device state of the Arnoldi process. rb: [0] convergence threshold,
+// [1] |r| at the cycle's start, [4, 4 + m) hist, then two ints (active,
+// columns used); Pb: the partial sums of |b|^2.
+struct GmresState {
+  double* H;   // (m + 1) x m
+  double* cs;  // m
+  double* sn;  // m
+  double* gv;  // m + 1
+  double* h1;  // first Gram-Schmidt pass, m
+  double* h2;  // second pass, m
+  double* rb;
+  const double* Pb;
+  int m;
+  double tol;
+};
+enum { kArnoldiNone = 0, kArnoldiStart = 1, kArnoldiGivens = 2 };
+// b = E^n + c_j J + c_b curl_N B_C, E_t = E^n, Pb: partial |b|^2
+hipError_t launch_rhs_start(const Grid& g, const double* E_n, bool jf32, const void* J, const double* BC, double c_j,
+                            double c_b, double* b, double* E_t, double* Pb, hipStream_t st);
+// R = b - A X, P3: partial |R|^2
+hipError_t launch_residual_op(const Grid& g, bool mf32, const void* M, const CurlK& K, double cm,
+                              const double* X, const double* b, double* R, double* P3, hipStream_t st);
+// step s: V_s = Win / |Win| (|Win|^2 from P3), Wout = A V_s, P1: partial
+// <V_v, Wout>, v <= s; mode: start the cycle or close column s - 1
+hipError_t launch_arnoldi_op(const Grid& g, bool mf32, const void* M, const CurlK& K, double cm,
+                             const double* Win, double* Wout, double* V, int64_t ld, int s, int mode,
+                             const double* P3, double* P1, const GmresState& G, hipStream_t st);
+// W -= sum_{v<k} h_v V_v with h from the partials Pin (stored to coef);
+// Pout: the partials <V_v, W> (norm false) or |W|^2 (norm true)
+hipError_t launch_cgs_pass(const Grid& g, bool norm, const double* V, int64_t ld, int k, const double* Pin,
+                           double* coef, double* W, double* Pout, hipStream_t st);
+hipError_t launch_givens_tail(const Grid& g, int j, const double* P3, const GmresState& G, hipStream_t st);
+// X += V y with H y = g over the first j columns
+hipError_t launch_update_x(const Grid& g, const double* H, const double* gv, int m, int j, const double* V,
+                           int64_t ld, double* X, hipStream_t st);
+hipError_t launch_finish(const Grid& g, const double* E_n, const double* E_t, const double* BC_n, double ctd,
+                         double* E_next, double* BC_next, hipStream_t st);
 hipError_t launch_sumsq(const double* x, int64_t n, double scale, double* partial, double* out, bool accumulate,
                         hipStream_t st);
 

@@ -644,10 +644,13 @@ def test_mass_apply_dense_2x2x2(E, O, I):
 # field solve and the full step
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("mprec", ["f64", "f32"])
-def test_field_solve(E, O, I, mprec):
-    say("field solve", mprec)
-    p, _, BN = make_case(I, (6, 5, 4), 6, 10)
+@pytest.mark.parametrize("mprec,n", [("f64", (6, 5, 4)), ("f32", (6, 5, 4)), ("f64", (32, 16, 16)),
+                                     ("f32", (13, 11, 9))])
+def test_field_solve(E, O, I, mprec, n):
+    """One workgroup (120 nodes), eight (8192 nodes: the XCD-contiguous block
+    order of the operator kernels) and two with a ragged tail (1287 nodes)."""
+    say("field solve", mprec, n)
+    p, _, BN = make_case(I, n, 6, 10)
     J, M27 = O.species_moments(p, [s.x for s in p.species], [s.v for s in p.species], BN)
     rng = np.random.default_rng(11)
     En = 1e-3 * rng.standard_normal((3, p.nn))
@@ -669,6 +672,86 @@ def test_field_solve(E, O, I, mprec):
     b = O.field_rhs(p.n, p.h, p.dt, J, En, BC)
     r = b - O.field_operator(p.n, p.h, p.dt, M27, host(Et))
     assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
+
+
+def solve_inputs(E, O, I, n=(6, 5, 4)):
+    p, _, BN = make_case(I, n, 6, 10)
+    J, M27 = O.species_moments(p, [s.x for s in p.species], [s.v for s in p.species], BN)
+    rng = np.random.default_rng(11)
+    En = 1e-3 * rng.standard_normal((3, p.nn))
+    BC = BN + 1e-3 * rng.standard_normal((3, p.nn))
+    return p, J, M27, En, BC
+
+
+@pytest.mark.parametrize("restart", [1, 2, 3])
+def test_field_solve_restarted(E, O, I, restart):
+    """GMRES(1..3): several restart cycles, each closed by the true residual;
+    the result is the same solution."""
+    say("field solve restarted", restart)
+    p, J, M27, En, BC = solve_inputs(E, O, I)
+    ref = O.field_solve(p.n, p.h, p.dt, M27, J, En, BC, tol=1e-13)
+    grid = E.Grid(p.n, p.h, p.dt)
+    Et, En1, Bn1 = (torch.empty((3, p.nn), dtype=torch.float64, device="cuda") for _ in range(3))
+    it, res = E.field_solve(grid, dev(O.m14(p.n, M27)), dev(J), dev(En), dev(BC), Et, En1, Bn1, tol=1e-10,
+                            restart=restart, maxit=500)
+    assert it > restart and res <= 1e-10
+    assert rel(host(Et), ref["E_theta"]) < 1e-9
+    assert rel(host(Bn1), ref["BC_next"]) < 1e-9
+    b = O.field_rhs(p.n, p.h, p.dt, J, En, BC)
+    r = b - O.field_operator(p.n, p.h, p.dt, M27, host(Et))
+    assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
+
+
+def test_field_solve_no_convergence(E, O, I):
+    """maxit below what tol needs: ENOCONV, and the outputs hold the last
+    iterate advanced consistently (E^{n+1} = 2 E^{n+theta} - E^n)."""
+    say("field solve, no convergence")
+    p, J, M27, En, BC = solve_inputs(E, O, I)
+    grid = E.Grid(p.n, p.h, p.dt)
+    Et, En1, Bn1 = (torch.empty((3, p.nn), dtype=torch.float64, device="cuda") for _ in range(3))
+    with pytest.raises(E.EcsimError) as ex:
+        E.field_solve(grid, dev(O.m14(p.n, M27)), dev(J), dev(En), dev(BC), Et, En1, Bn1, tol=1e-14, restart=30,
+                      maxit=2)
+    assert ex.value.status == E.ENOCONV
+    et = host(Et)
+    assert np.isfinite(et).all()
+    assert rel(host(En1), 2.0 * et - En) < 1e-14
+    b = O.field_rhs(p.n, p.h, p.dt, J, En, BC)
+    r = b - O.field_operator(p.n, p.h, p.dt, M27, et)
+    r0 = b - O.field_operator(p.n, p.h, p.dt, M27, En)
+    assert 1e-14 * np.linalg.norm(b) < np.linalg.norm(r) < np.linalg.norm(r0)
+
+
+def test_field_solve_zero_rhs(E, O, I):
+    """b = 0 (E^n, J and B^n zero): E^{n+theta} = 0 after no iterations."""
+    say("field solve, zero right-hand side")
+    p, J, M27, En, BC = solve_inputs(E, O, I)
+    grid = E.Grid(p.n, p.h, p.dt)
+    z = torch.zeros((3, p.nn), dtype=torch.float64, device="cuda")
+    Et, En1, Bn1 = (torch.full((3, p.nn), 7.0, dtype=torch.float64, device="cuda") for _ in range(3))
+    it, res = E.field_solve(grid, dev(O.m14(p.n, M27)), z, z, z, Et, En1, Bn1, tol=1e-10)
+    assert it == 0 and res == 0.0
+    for t in (Et, En1, Bn1):
+        assert not host(t).any()
+
+
+@pytest.mark.parametrize("where", ["M", "J"])
+def test_field_solve_nonfinite(E, O, I, where):
+    """A NaN in M or J ends the solve with ENONFINITE."""
+    say("field solve, NaN in", where)
+    p, J, M27, En, BC = solve_inputs(E, O, I)
+    M14 = O.m14(p.n, M27)
+    if where == "M":
+        M14 = M14.copy()
+        M14.flat[37] = np.nan
+    else:
+        J = J.copy()
+        J[1, 5] = np.nan
+    grid = E.Grid(p.n, p.h, p.dt)
+    Et, En1, Bn1 = (torch.empty((3, p.nn), dtype=torch.float64, device="cuda") for _ in range(3))
+    with pytest.raises(E.EcsimError) as ex:
+        E.field_solve(grid, dev(M14), dev(J), dev(En), dev(BC), Et, En1, Bn1, tol=1e-10)
+    assert ex.value.status == E.ENONFINITE
 
 
 def test_centres_to_nodes_and_energy(E, O, I):
