@@ -360,7 +360,7 @@ ecsim_status ecsim_to_f32(int64_t n, const double *src, float *dst, void *stream
  *   A E = b,  A E = E + (c theta dt)^2 curl_N curl_C E + 4 pi theta dt (M E),
  *   b = E^n - 4 pi theta dt J + c theta dt curl_N B_C^n,
  * by restarted GMRES(restart), 1 <= restart <= 120, from E^n, stopping when ||b - A E||_2 <=
- * tol ||b||_2; then B_C^{n+theta} = B_C^n - c theta dt curl_C E^{n+theta},
+ * tol ||b||_2 (grids of fewer than 2^29 cells, else ECSIM_EINVAL); then B_C^{n+theta} = B_C^n - c theta dt curl_C E^{n+theta},
  * E^{n+1} = 2 E^{n+theta} - E^n and B_C^{n+1} = 2 B_C^{n+theta} - B_C^n.
  * The curls average the four edge differences of a cell (curl_C, nodes to
  * centres) or the four around a node (curl_N, centres to nodes); curl_N is the

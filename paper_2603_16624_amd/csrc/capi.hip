@@ -548,17 +548,18 @@ ecsim_status ecsim_solve_workspace_size(const ecsim_grid* grid, int32_t restart,
   if (!bytes) return fail(ECSIM_EINVAL, "bytes is NULL");
   const size_t vec = align256(sizeof(double) * 3 * (size_t)g.nn);
   const size_t m = (size_t)restart, nb = (size_t)solve_blocks(g);
-  // V (m + 1 vectors), two w buffers, b; the partial sums of the two
-  // Gram-Schmidt passes; the read-back block (threshold, |r|, residual
-  // history, flags, partial |b|^2 and |w|^2); H, the rotations, g, h1, h2
-  *bytes = vec * (m + 1) + 3 * vec + 2 * align256(sizeof(double) * nb * m) +
-           align256(sizeof(double) * (5 + m + 2 * nb)) + align256(sizeof(double) * ((m + 1) * m + 5 * m + 1));
+  // V (m + 1 vectors), two w buffers, the residual, b; the partial sums of
+  // the two Gram-Schmidt passes and of |w|^2; the read-back block
+  // (threshold, |r|, residual history, flags, partial |b|^2 and |r|^2); H,
+  // the rotations, g, h1, h2 and the two least-squares solutions
+  *bytes = vec * (m + 1) + 4 * vec + 2 * align256(sizeof(double) * nb * m) + align256(sizeof(double) * nb) +
+           align256(sizeof(double) * (6 + m + 2 * nb)) + align256(sizeof(double) * ((m + 1) * m + 7 * m + 1));
   return ECSIM_OK;
 }
 
 namespace {
-// steps the first batch of a solve launches before its first read of the
-// residual history: what the last solve's first cycle needed
+// steps the first batch of a solve launches before its first read-back:
+// what the last solve's first cycle needed
 std::atomic<int> g_first_batch{2};
 }  // namespace
 
@@ -573,6 +574,7 @@ ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const voi
     return fail(ECSIM_EINVAL, "ecsim_field_solve: NULL array");
   if (!(tol > 0.0) || !(tol < 1.0)) return fail(ECSIM_EINVAL, "ecsim_field_solve: tol must be in (0, 1)");
   if (maxit < 1) return fail(ECSIM_EINVAL, "ecsim_field_solve: maxit must be >= 1");
+  if (g.nn >= ((int64_t)1 << 29)) return fail(ECSIM_EINVAL, "ecsim_field_solve: at most 2^29 - 1 cells");
   size_t need = 0;
   if (ecsim_solve_workspace_size(grid, restart, &need) != ECSIM_OK) return ECSIM_EINVAL;
   if (!ws || ws_bytes < need) return fail(ECSIM_EWORKSPACE, "ecsim_field_solve: workspace of %zu bytes needed", need);
@@ -586,16 +588,20 @@ ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const voi
   w8 += vec * (size_t)(m + 1);
   double* Wb[2] = {(double*)w8, (double*)(w8 + vec)};
   w8 += 2 * vec;
+  double* Wr = (double*)w8;
+  w8 += vec;
   double* bvec = (double*)w8;
   w8 += vec;
   double* P1 = (double*)w8;
   w8 += align256(sizeof(double) * (size_t)nb * m);
   double* P2 = (double*)w8;
   w8 += align256(sizeof(double) * (size_t)nb * m);
-  const size_t rb_count = 5 + (size_t)m + 2 * (size_t)nb;
+  double* P3 = (double*)w8;
+  w8 += align256(sizeof(double) * (size_t)nb);
+  const size_t rb_count = 6 + (size_t)m + 2 * (size_t)nb;
   double* rb = (double*)w8;
-  double* Pb = rb + 5 + m;
-  double* P3 = Pb + nb;
+  double* Pb = rb + 6 + m;
+  double* Pr = Pb + nb;
   w8 += align256(sizeof(double) * rb_count);
   GmresState G;
   G.H = (double*)w8;
@@ -604,6 +610,8 @@ ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const voi
   G.gv = G.sn + m;
   G.h1 = G.gv + (m + 1);
   G.h2 = G.h1 + m;
+  G.yn = G.h2 + m;
+  G.yp = G.yn + m;
   G.rb = rb;
   G.Pb = Pb;
   G.m = m;
@@ -625,11 +633,15 @@ ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const voi
   // first pass with the second's, second pass with the new norm); the
   // normalisation and the Givens update of H and g ride on the next step's
   // first kernel, and every inner product is summed by the kernel that needs
-  // it. The host only decides how many steps to launch before it next reads
-  // the residual history (what the last solve needed at the start, then as
-  // many as the observed convergence rate predicts): steps launched past
-  // convergence change nothing. A cycle ends with X += V y and the true
-  // residual, read back once with the field advance already launched.
+  // it. Steps go out in batches, and every batch ends as if it closed the
+  // solve: y over the columns so far, X moved by V times the change in y,
+  // the true residual and the field advance. The host reads back once per
+  // batch; if the residual is not yet below tol it launches more steps of
+  // the same cycle (or, once the cycle has m columns or its estimate has
+  // converged, a new cycle from the residual just computed). The first
+  // batch is as long as the last solve's first cycle, later ones as long as
+  // the observed convergence rate predicts; steps past convergence change
+  // nothing.
   std::vector<double> hb(rb_count);
   auto read_back = [&]() -> hipError_t {
     hipError_t r = hipMemcpyAsync(hb.data(), rb, sizeof(double) * rb_count, hipMemcpyDeviceToHost, st);
@@ -640,83 +652,82 @@ ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const voi
     for (int b = 0; b < nb; ++b) s += hb[off + b];
     return s;
   };
-  const size_t off_pb = 5 + (size_t)m, off_p3 = off_pb + nb;
+  const size_t off_pb = 6 + (size_t)m, off_pr = off_pb + nb;
   const int* flags = (const int*)(hb.data() + 4 + m);
   const double* hh = hb.data() + 4;
 
   HIPCK(launch_rhs_start(g, E_n, mf32, J, B_C_n, -4.0 * kPi * kTheta * g.dt, ctd, bvec, E_theta, Pb, st));
-  HIPCK(launch_residual_op(g, mf32, M, K, cm, E_theta, bvec, Wb[0], P3, st));
+  HIPCK(launch_residual_op(g, mf32, M, K, cm, E_theta, bvec, Wr, Pr, st));
+  int it_done = 0;    // columns of the cycles before this one
   int it = 0;
+  int j = 0;          // steps launched in this cycle
   double rel = 0.0, bnorm = 0.0;
   bool converged = false, first = true;
+  int batch = std::max(1, std::min(g_first_batch.load(std::memory_order_relaxed), m));
   while (true) {
-    int j = 0, used = 0;
-    int batch = std::max(1, std::min(g_first_batch.load(std::memory_order_relaxed), m));
-    bool done = false;
-    while (!done) {
-      const int nbat = std::min(std::min(batch, m - j), maxit - it - j);
-      for (int s = j; s < j + nbat; ++s) {
-        const int mode = s == 0 ? kArnoldiStart : (s > j ? kArnoldiGivens : kArnoldiNone);
-        double* w = Wb[(s + 1) & 1];
-        HIPCK(launch_arnoldi_op(g, mf32, M, K, cm, Wb[s & 1], w, V, ld, s, mode, P3, P1, G, st));
-        HIPCK(launch_cgs_pass(g, false, V, ld, s + 1, P1, G.h1, w, P2, st));
-        HIPCK(launch_cgs_pass(g, true, V, ld, s + 1, P2, G.h2, w, P3, st));
-      }
-      HIPCK(launch_givens_tail(g, j + nbat - 1, P3, G, st));
-      HIPCK(read_back());
-      if (first) {
-        const double bb = host_sum(off_pb);
-        if (!std::isfinite(bb))
-          return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the right-hand side is not finite (J, E^n or B^n)");
-        bnorm = std::sqrt(bb);
-        first = false;
-      }
-      if (j == 0) {
-        if (!std::isfinite(hb[1]))
-          return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the residual is not finite (M or the iterate)");
-        if (bnorm == 0.0 || hb[1] <= tol * bnorm) break;   // nothing to do: used = 0
-      }
-      for (int s = j; s < j + nbat; ++s)
-        if (!std::isfinite(hh[s]))
-          return fail(ECSIM_ENONFINITE, "ecsim_field_solve: a Krylov vector is not finite (M is not finite)");
-      j += nbat;
-      used = flags[1];
-      done = flags[0] == 0 || j >= m || it + j >= maxit;
-      if (!done) {
-        // steps still needed at the rate of the last two: |g| falls by about
-        // hist[j-1] / hist[j-2] per step
-        int next = 1;
-        if (j >= 2 && hh[j - 1] > 0.0 && hh[j - 2] > hh[j - 1]) {
-          const double rate = hh[j - 1] / hh[j - 2];
-          const double k = std::log(hb[0] / hh[j - 1]) / std::log(rate);
-          next = k < 1.0 ? 1 : (k > (double)m ? m : (int)std::ceil(k));
-        }
-        batch = next;
-      }
+    const int nbat = std::min(std::min(batch, m - j), maxit - it_done - j);
+    for (int s = j; s < j + nbat; ++s) {
+      const int mode = s == 0 ? kArnoldiStart : (s > j ? kArnoldiGivens : kArnoldiNone);
+      double* w = Wb[(s + 1) & 1];
+      HIPCK(launch_arnoldi_op(g, mf32, M, K, cm, s == 0 ? Wr : Wb[s & 1], w, V, ld, s, mode, s == 0 ? Pr : P3,
+                              P1, G, st));
+      HIPCK(launch_cgs_pass(g, false, V, ld, s + 1, P1, G.h1, w, P2, st));
+      HIPCK(launch_cgs_pass(g, true, V, ld, s + 1, P2, G.h2, w, P3, st));
     }
-    if (it == 0 && used > 0) g_first_batch.store(used, std::memory_order_relaxed);
-    it += used;
-    if (bnorm == 0.0) {
-      // b = 0: E^{n+theta} = 0
-      HIPCK(launch_zero(E_theta, sizeof(double) * 3 * (size_t)g.nn, st));
-      HIPCK(launch_finish(g, E_n, E_theta, B_C_n, ctd, E_next, B_C_next, st));
-      HIPCK(hipStreamSynchronize(st));
-      converged = true;
-      rel = 0.0;
-      break;
-    }
-    if (used > 0) HIPCK(launch_update_x(g, G.H, G.gv, m, used, V, ld, E_theta, st));
-    HIPCK(launch_residual_op(g, mf32, M, K, cm, E_theta, bvec, Wb[0], P3, st));
-    HIPCK(launch_finish(g, E_n, E_theta, B_C_n, ctd, E_next, B_C_next, st));
+    HIPCK(launch_givens_tail(g, j + nbat - 1, P3, G, st));
+    HIPCK(launch_update_x(g, V, ld, E_theta, G, st));
+    HIPCK(launch_residual_op(g, mf32, M, K, cm, E_theta, bvec, Wr, Pr, st));
+    HIPCK(launch_finish(g, E_n, E_theta, B_C_n, ctd, E_next, B_C_next, &G, st));
     HIPCK(read_back());
-    rel = std::sqrt(host_sum(off_p3)) / bnorm;
+    if (first) {
+      const double bb = host_sum(off_pb);
+      if (!std::isfinite(bb))
+        return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the right-hand side is not finite (J, E^n or B^n)");
+      bnorm = std::sqrt(bb);
+      first = false;
+      if (bnorm == 0.0) {
+        // b = 0: E^{n+theta} = 0
+        HIPCK(launch_zero(E_theta, sizeof(double) * 3 * (size_t)g.nn, st));
+        HIPCK(launch_finish(g, E_n, E_theta, B_C_n, ctd, E_next, B_C_next, nullptr, st));
+        HIPCK(hipStreamSynchronize(st));
+        converged = true;
+        break;
+      }
+    }
+    if (j == 0 && !std::isfinite(hb[1]))
+      return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the residual is not finite (M or the iterate)");
+    for (int s = j; s < j + nbat; ++s)
+      if (!std::isfinite(hh[s]))
+        return fail(ECSIM_ENONFINITE, "ecsim_field_solve: a Krylov vector is not finite (M is not finite)");
+    j += nbat;
+    const int used = flags[1];
+    it = it_done + used;
+    rel = std::sqrt(host_sum(off_pr)) / bnorm;
     if (!std::isfinite(rel))
       return fail(ECSIM_ENONFINITE, "ecsim_field_solve: the residual is not finite (M or the iterate)");
+    if (it_done == 0 && used > 0) g_first_batch.store(used, std::memory_order_relaxed);
     if (rel <= tol) {
       converged = true;
       break;
     }
-    if (it >= maxit || used == 0) break;
+    if (it_done + j >= maxit) break;
+    if (flags[0] == 0 || j >= m) {
+      // a new cycle from the residual of the iterate
+      if (used == 0) break;   // no progress possible
+      it_done += used;
+      j = 0;
+      batch = std::max(1, std::min(g_first_batch.load(std::memory_order_relaxed), m));
+      continue;
+    }
+    // steps still needed at the rate of the last two: |g| falls by about
+    // hist[j-1] / hist[j-2] per step
+    int next = 1;
+    if (j >= 2 && hh[j - 1] > 0.0 && hh[j - 2] > hh[j - 1]) {
+      const double rate = hh[j - 1] / hh[j - 2];
+      const double k = std::log(hb[0] / hh[j - 1]) / std::log(rate);
+      next = k < 1.0 ? 1 : (k > (double)m ? m : (int)std::ceil(k));
+    }
+    batch = next;
   }
 #undef HIPCK
   if (iters_out) *iters_out = it;

@@ -289,52 +289,61 @@ template <typename TM>
 __device__ __forceinline__ void apply_at(const Grid& g, const TM* __restrict__ M, const CurlK& K, double cm,
                                          const double* __restrict__ X, double sc, int64_t gid, double y[3],
                                          double xo[3]) {
+  // every plane of X and M holds fewer than 2^29 values (the solver checks),
+  // so the per-thread part of an address is a 32-bit byte offset from a
+  // uniform base
   const int64_t nn = g.nn;
   int ix, iy, iz;
   decode_cell(g, (int)gid, ix, iy, iz);
+  const char* Xb = (const char*)X;
+  const uint32_t own = (uint32_t)gid * (uint32_t)sizeof(TM);
   double m0 = 0.0, m1 = 0.0, m2 = 0.0;
   double S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
   for (int k = 0; k < 14; ++k) {
     int o[3];
     offset14(k, o[0], o[1], o[2]);
-    const TM* Mk = M + (int64_t)k * 9 * nn;
+    const char* Mk = (const char*)(M + (int64_t)k * 9 * nn);
+    const int64_t pl = nn * (int64_t)sizeof(TM);   // bytes per plane of M
+    auto mat = [&](int q, uint32_t off) { return (double)*(const TM*)(Mk + q * pl + off); };
+    auto xv = [&](int c, uint32_t off) { return sc * *(const double*)(Xb + c * nn * 8 + off); };
     double u[3];
     {
-      const int64_t gp =
-          shift(ix, o[0], g.nx) + (int64_t)g.nx * (shift(iy, o[1], g.ny) + (int64_t)g.ny * shift(iz, o[2], g.nz));
-      const double e0 = sc * X[gp], e1 = sc * X[nn + gp], e2 = sc * X[2 * nn + gp];
+      const uint32_t gp =
+          (uint32_t)shift(ix, o[0], g.nx) + (uint32_t)g.nx * ((uint32_t)shift(iy, o[1], g.ny) + (uint32_t)g.ny * (uint32_t)shift(iz, o[2], g.nz));
+      const double e0 = xv(0, gp * 8u), e1 = xv(1, gp * 8u), e2 = xv(2, gp * 8u);
       if (k == 0) {
         xo[0] = e0;
         xo[1] = e1;
         xo[2] = e2;
       }
-      m0 = fma((double)Mk[0 * nn + gid], e0, m0);
-      m0 = fma((double)Mk[1 * nn + gid], e1, m0);
-      m0 = fma((double)Mk[2 * nn + gid], e2, m0);
-      m1 = fma((double)Mk[3 * nn + gid], e0, m1);
-      m1 = fma((double)Mk[4 * nn + gid], e1, m1);
-      m1 = fma((double)Mk[5 * nn + gid], e2, m1);
-      m2 = fma((double)Mk[6 * nn + gid], e0, m2);
-      m2 = fma((double)Mk[7 * nn + gid], e1, m2);
-      m2 = fma((double)Mk[8 * nn + gid], e2, m2);
+      m0 = fma(mat(0, own), e0, m0);
+      m0 = fma(mat(1, own), e1, m0);
+      m0 = fma(mat(2, own), e2, m0);
+      m1 = fma(mat(3, own), e0, m1);
+      m1 = fma(mat(4, own), e1, m1);
+      m1 = fma(mat(5, own), e2, m1);
+      m2 = fma(mat(6, own), e0, m2);
+      m2 = fma(mat(7, own), e1, m2);
+      m2 = fma(mat(8, own), e2, m2);
       u[0] = e0;
       u[1] = e1;
       u[2] = e2;
     }
     if (k > 0) {
-      const int64_t gm = shift(ix, -o[0], g.nx) +
-                         (int64_t)g.nx * (shift(iy, -o[1], g.ny) + (int64_t)g.ny * shift(iz, -o[2], g.nz));
-      const double e0 = sc * X[gm], e1 = sc * X[nn + gm], e2 = sc * X[2 * nn + gm];
-      m0 = fma((double)Mk[0 * nn + gm], e0, m0);
-      m0 = fma((double)Mk[1 * nn + gm], e1, m0);
-      m0 = fma((double)Mk[2 * nn + gm], e2, m0);
-      m1 = fma((double)Mk[3 * nn + gm], e0, m1);
-      m1 = fma((double)Mk[4 * nn + gm], e1, m1);
-      m1 = fma((double)Mk[5 * nn + gm], e2, m1);
-      m2 = fma((double)Mk[6 * nn + gm], e0, m2);
-      m2 = fma((double)Mk[7 * nn + gm], e1, m2);
-      m2 = fma((double)Mk[8 * nn + gm], e2, m2);
+      const uint32_t gm = (uint32_t)shift(ix, -o[0], g.nx) +
+                          (uint32_t)g.nx * ((uint32_t)shift(iy, -o[1], g.ny) + (uint32_t)g.ny * (uint32_t)shift(iz, -o[2], g.nz));
+      const uint32_t gmo = gm * (uint32_t)sizeof(TM);
+      const double e0 = xv(0, gm * 8u), e1 = xv(1, gm * 8u), e2 = xv(2, gm * 8u);
+      m0 = fma(mat(0, gmo), e0, m0);
+      m0 = fma(mat(1, gmo), e1, m0);
+      m0 = fma(mat(2, gmo), e2, m0);
+      m1 = fma(mat(3, gmo), e0, m1);
+      m1 = fma(mat(4, gmo), e1, m1);
+      m1 = fma(mat(5, gmo), e2, m1);
+      m2 = fma(mat(6, gmo), e0, m2);
+      m2 = fma(mat(7, gmo), e1, m2);
+      m2 = fma(mat(8, gmo), e2, m2);
       u[0] += e0;
       u[1] += e1;
       u[2] += e2;
@@ -362,7 +371,7 @@ __device__ __forceinline__ void apply_at(const Grid& g, const TM* __restrict__ M
   }
 }
 
-__device__ __forceinline__ int* gmres_flags(const GmresState& G) { return (int*)(G.rb + 4 + G.m); }
+__device__ __forceinline__ int* gmres_flags(const GmresState& G) { return (int*)(G.rb + 4 + G.m); }  // 4 ints
 
 // Column j of the Arnoldi process on the device (one thread): H[:, j] from
 // the two Gram-Schmidt passes and the new vector's norm hn, the earlier
@@ -473,6 +482,8 @@ __global__ void __launch_bounds__(kSolveBlock) k_arnoldi_op(Grid g, const TM* __
         int* fl = gmres_flags(G);
         fl[0] = hn > thresh ? 1 : 0;
         fl[1] = 0;
+        fl[2] = 0;
+        fl[3] = 0;
       } else {
         givens_column(s - 1, G, hn);
       }
@@ -540,42 +551,56 @@ __global__ void __launch_bounds__(kSolveBlock) k_cgs_pass(const double* __restri
   }
 }
 
-// the Givens update of column j after the last step of a batch
+// After the last step of a batch: the Givens update of column j, then y
+// from the upper triangle H y = g over the columns that count (flags[1]),
+// into yn (flags[3] = their number).
 __global__ void __launch_bounds__(kSolveBlock) k_givens_tail(int j, const double* __restrict__ P3, int nblk,
                                                              GmresState G) {
   __shared__ double red[kVW];
   __shared__ double sc[1];
   sum_partials(P3, nblk, 1, red, sc);
-  if (threadIdx.x == 0) givens_column(j, G, sqrt(sc[0]));
+  if (threadIdx.x == 0) {
+    givens_column(j, G, sqrt(sc[0]));
+    int* fl = gmres_flags(G);
+    const int m = G.m, jj = fl[1];
+    for (int i = jj - 1; i >= 0; --i) {
+      double s = G.gv[i];
+      for (int k = i + 1; k < jj; ++k) s -= G.H[(int64_t)i * m + k] * G.yn[k];
+      G.yn[i] = s / G.H[(int64_t)i * m + i];
+    }
+    fl[3] = jj;
+  }
 }
 
-// X += V y, y from the j x j upper triangle H y = g (each workgroup solves
-// it, one thread, in the same order)
-__global__ void __launch_bounds__(kSolveBlock) k_update_x(const double* __restrict__ H, const double* __restrict__ gv,
-                                                          int m, int j, const double* __restrict__ V, int64_t ld,
-                                                          int64_t nn, double* __restrict__ X) {
-  __shared__ double y[kMaxRestart];
-  if (threadIdx.x == 0) {
-    for (int i = j - 1; i >= 0; --i) {
-      double s = gv[i];
-      for (int k = i + 1; k < j; ++k) s -= H[(int64_t)i * m + k] * y[k];
-      y[i] = s / H[(int64_t)i * m + i];
-    }
-  }
+// X += V (yn - yp): the cycle's update so far is V yp (flags[2] columns),
+// the one wanted is V yn (flags[3] columns)
+__global__ void __launch_bounds__(kSolveBlock) k_update_x(const double* __restrict__ V, int64_t ld, int64_t nn,
+                                                          double* __restrict__ X, GmresState G) {
+  __shared__ double d[kMaxRestart];
+  const int* fl = gmres_flags(G);
+  const int jn = fl[3], jp = fl[2], j = jn > jp ? jn : jp;
+  for (int v = threadIdx.x; v < j; v += kSolveBlock) d[v] = (v < jn ? G.yn[v] : 0.0) - (v < jp ? G.yp[v] : 0.0);
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kSolveBlock + threadIdx.x;
   if (i >= nn) return;
   for (int c = 0; c < 3; ++c) {
     double x = X[c * nn + i];
-    for (int v = 0; v < j; ++v) x = fma(y[v], V[(int64_t)v * ld + c * nn + i], x);
+    for (int v = 0; v < j; ++v) x = fma(d[v], V[(int64_t)v * ld + c * nn + i], x);
     X[c * nn + i] = x;
   }
 }
 
 // E^{n+1} = 2 E^{n+theta} - E^n; B^{n+1} = 2 (B^n - ctd curl_C E^{n+theta}) - B^n
+// and, with G.m > 0, yp = yn: the update now in X
 __global__ void __launch_bounds__(kBlock) k_finish(Grid g, const double* __restrict__ En,
                                                    const double* __restrict__ Et, const double* __restrict__ BCn,
-                                                   double ctd, double* __restrict__ En1, double* __restrict__ BCn1) {
+                                                   double ctd, double* __restrict__ En1, double* __restrict__ BCn1,
+                                                   GmresState G) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && G.m > 0) {
+    int* fl = gmres_flags(G);
+    for (int v = 0; v < fl[3]; ++v) G.yp[v] = G.yn[v];
+    fl[2] = fl[3];
+  }
   const int64_t nn = g.nn, c = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (c >= nn) return;
   double cc[3];
@@ -700,17 +725,17 @@ hipError_t launch_givens_tail(const Grid& g, int j, const double* P3, const Gmre
   return hipGetLastError();
 }
 
-hipError_t launch_update_x(const Grid& g, const double* H, const double* gv, int m, int j, const double* V,
-                           int64_t ld, double* X, hipStream_t st) {
-  if (j < 1 || j > m || m > kMaxRestart) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_update_x, dim3(solve_blocks(g)), dim3(kSolveBlock), 0, st, H, gv, m, j, V, ld, g.nn, X);
+hipError_t launch_update_x(const Grid& g, const double* V, int64_t ld, double* X, const GmresState& G,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_update_x, dim3(solve_blocks(g)), dim3(kSolveBlock), 0, st, V, ld, g.nn, X, G);
   return hipGetLastError();
 }
 
 hipError_t launch_finish(const Grid& g, const double* E_n, const double* E_t, const double* BC_n, double ctd,
-                         double* E_next, double* BC_next, hipStream_t st) {
+                         double* E_next, double* BC_next, const GmresState* G, hipStream_t st) {
+  GmresState none{};
   hipLaunchKernelGGL(k_finish, dim3(nblocks(g.nn, kBlock)), dim3(kBlock), 0, st, g, E_n, E_t, BC_n, ctd, E_next,
-                     BC_next);
+                     BC_next, G ? *G : none);
   return hipGetLastError();
 }
 

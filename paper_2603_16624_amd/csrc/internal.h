@@ -94,8 +94,9 @@ struct CurlK {
 };
 void curl_curl_stencil(const Grid& g, double ctd2, CurlK& K);
 // Device state of the Arnoldi process. rb: [0] convergence threshold,
-// [1] |r| at the cycle's start, [4, 4 + m) hist, then two ints (active,
-// columns used); Pb: the partial sums of |b|^2.
+// [1] |r| at the cycle's start, [4, 4 + m) hist, then four ints (active,
+// columns that count, columns of the update in X, columns of yn); Pb: the
+// partial sums of |b|^2.
 struct GmresState {
   double* H;   // (m + 1) x m
   double* cs;  // m
@@ -103,6 +104,8 @@ struct GmresState {
   double* gv;  // m + 1
   double* h1;  // first Gram-Schmidt pass, m
   double* h2;  // second pass, m
+  double* yn;  // least-squares solution over the columns so far, m
+  double* yp;  // the one the iterate holds, m
   double* rb;
   const double* Pb;
   int m;
@@ -124,12 +127,14 @@ hipError_t launch_arnoldi_op(const Grid& g, bool mf32, const void* M, const Curl
 // Pout: the partials <V_v, W> (norm false) or |W|^2 (norm true)
 hipError_t launch_cgs_pass(const Grid& g, bool norm, const double* V, int64_t ld, int k, const double* Pin,
                            double* coef, double* W, double* Pout, hipStream_t st);
+// Givens update of column j and y over the columns so far (one workgroup)
 hipError_t launch_givens_tail(const Grid& g, int j, const double* P3, const GmresState& G, hipStream_t st);
-// X += V y with H y = g over the first j columns
-hipError_t launch_update_x(const Grid& g, const double* H, const double* gv, int m, int j, const double* V,
-                           int64_t ld, double* X, hipStream_t st);
+// X += V (yn - yp)
+hipError_t launch_update_x(const Grid& g, const double* V, int64_t ld, double* X, const GmresState& G,
+                           hipStream_t st);
+// E^{n+1}, B^{n+1} from E^{n+theta}; with G, also yp = yn
 hipError_t launch_finish(const Grid& g, const double* E_n, const double* E_t, const double* BC_n, double ctd,
-                         double* E_next, double* BC_next, hipStream_t st);
+                         double* E_next, double* BC_next, const GmresState* G, hipStream_t st);
 hipError_t launch_sumsq(const double* x, int64_t n, double scale, double* partial, double* out, bool accumulate,
                         hipStream_t st);
 
