@@ -656,8 +656,8 @@ ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const voi
   const int* flags = (const int*)(hb.data() + 4 + m);
   const double* hh = hb.data() + 4;
 
-  HIPCK(launch_rhs_start(g, E_n, mf32, J, B_C_n, -4.0 * kPi * kTheta * g.dt, ctd, bvec, E_theta, Pb, st));
-  HIPCK(launch_residual_op(g, mf32, M, K, cm, E_theta, bvec, Wr, Pr, st));
+  HIPCK(launch_residual_first(g, mf32, M, K, cm, E_n, J, B_C_n, -4.0 * kPi * kTheta * g.dt, ctd, bvec, E_theta, Wr,
+                              Pb, Pr, st));
   int it_done = 0;    // columns of the cycles before this one
   int it = 0;
   int j = 0;          // steps launched in this cycle
@@ -676,8 +676,7 @@ ecsim_status ecsim_field_solve(const ecsim_grid* grid, int32_t m_prec, const voi
     }
     HIPCK(launch_givens_tail(g, j + nbat - 1, P3, G, st));
     HIPCK(launch_update_x(g, V, ld, E_theta, G, st));
-    HIPCK(launch_residual_op(g, mf32, M, K, cm, E_theta, bvec, Wr, Pr, st));
-    HIPCK(launch_finish(g, E_n, E_theta, B_C_n, ctd, E_next, B_C_next, &G, st));
+    HIPCK(launch_residual_last(g, mf32, M, K, cm, E_theta, bvec, Wr, Pr, E_n, B_C_n, ctd, E_next, B_C_next, G, st));
     HIPCK(read_back());
     if (first) {
       const double bb = host_sum(off_pb);

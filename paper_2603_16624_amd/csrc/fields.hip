@@ -285,10 +285,13 @@ __device__ __forceinline__ int xcd_block() {
 //   L_dr = sum_o q(o_d) prod_{a != d} (2 - |o_a|) u_r(o),  q(0) = -2, q(+-1) = 1,
 // so the weights are compile-time constants and only the six K values are
 // read at run time.
-template <typename TM>
+// With CURL, d[axis][comp] also collects the edge differences of x over
+// cell gid (corners gid + a, a in {0,1}^3, all among the stored offsets):
+// curl_C x at that cell is their cross combination.
+template <typename TM, bool CURL = false>
 __device__ __forceinline__ void apply_at(const Grid& g, const TM* __restrict__ M, const CurlK& K, double cm,
                                          const double* __restrict__ X, double sc, int64_t gid, double y[3],
-                                         double xo[3]) {
+                                         double xo[3], double (*d)[3] = nullptr) {
   // every plane of X and M holds fewer than 2^29 values (the solver checks),
   // so the per-thread part of an address is a 32-bit byte offset from a
   // uniform base
@@ -329,6 +332,14 @@ __device__ __forceinline__ void apply_at(const Grid& g, const TM* __restrict__ M
       u[0] = e0;
       u[1] = e1;
       u[2] = e2;
+      if (CURL && o[0] >= 0 && o[1] >= 0 && o[2] >= 0) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          d[ax][0] += o[ax] ? e0 : -e0;
+          d[ax][1] += o[ax] ? e1 : -e1;
+          d[ax][2] += o[ax] ? e2 : -e2;
+        }
+      }
     }
     if (k > 0) {
       const uint32_t gm = (uint32_t)shift(ix, -o[0], g.nx) +
@@ -373,85 +384,136 @@ __device__ __forceinline__ void apply_at(const Grid& g, const TM* __restrict__ M
 
 __device__ __forceinline__ int* gmres_flags(const GmresState& G) { return (int*)(G.rb + 4 + G.m); }  // 4 ints
 
-// Column j of the Arnoldi process on the device (one thread): H[:, j] from
-// the two Gram-Schmidt passes and the new vector's norm hn, the earlier
-// Givens rotations applied to it, a new rotation that zeroes H[j+1][j], and
-// the rotated right-hand side g. hist[j] = |g[j+1]|, the least-squares
-// residual after j + 1 steps. Once it is below the threshold (or the Krylov
-// space broke down) flags[0] = 0, and later columns leave everything as it
-// is, so steps launched past convergence change nothing. flags[1] = columns
-// that count.
-__device__ void givens_column(int j, const GmresState& G, double hn) {
+// Column j of the Arnoldi process on the device, by one workgroup (every
+// thread calls it): H[:, j] from the two Gram-Schmidt passes and the new
+// vector's norm hn, the earlier Givens rotations applied to it, a new
+// rotation that zeroes H[j+1][j], and the rotated right-hand side g.
+// hist[j] = |g[j+1]|, the least-squares residual after j + 1 steps. Once it
+// is below the threshold (or the Krylov space broke down) flags[0] = 0, and
+// later columns leave everything as it is, so steps launched past
+// convergence change nothing. flags[1] = columns that count. The column and
+// the rotations are staged in LDS (sh: 3 kMaxRestart + 2 doubles), so the
+// serial part runs on LDS values.
+__device__ void givens_column(int j, const GmresState& G, double hn, double* sh) {
   int* fl = gmres_flags(G);
-  double* hist = G.rb + 4;
-  if (fl[0] == 0) {
-    hist[j] = -1.0;
-    return;
-  }
-  const int m = G.m;
-  double* H = G.H;
-  for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] = G.h1[i] + G.h2[i];
-  H[(int64_t)(j + 1) * m + j] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double a = H[(int64_t)i * m + j], b = H[(int64_t)(i + 1) * m + j];
-    H[(int64_t)i * m + j] = G.cs[i] * a + G.sn[i] * b;
-    H[(int64_t)(i + 1) * m + j] = -G.sn[i] * a + G.cs[i] * b;
-  }
-  const double a = H[(int64_t)j * m + j], b = H[(int64_t)(j + 1) * m + j];
-  const double rr = hypot(a, b);
-  G.cs[j] = rr > 0.0 ? a / rr : 1.0;
-  G.sn[j] = rr > 0.0 ? b / rr : 0.0;
-  H[(int64_t)j * m + j] = rr;
-  H[(int64_t)(j + 1) * m + j] = 0.0;
-  G.gv[j + 1] = -G.sn[j] * G.gv[j];
-  G.gv[j] = G.cs[j] * G.gv[j];
-  hist[j] = fabs(G.gv[j + 1]);
-  fl[1] = j + 1;
-  if (hist[j] <= G.rb[0] || hn == 0.0) fl[0] = 0;
-}
-
-// b = E^n + c_j J + c_b curl_N(B_C^n), E_theta = E^n, Pb: partial |b|^2
-template <typename TJ>
-__global__ void __launch_bounds__(kSolveBlock) k_rhs_start(Grid g, const double* __restrict__ En,
-                                                           const TJ* __restrict__ J, const double* __restrict__ BC,
-                                                           double c_j, double c_b, double* __restrict__ b,
-                                                           double* __restrict__ Et, double* __restrict__ Pb,
-                                                           int nblk) {
-  __shared__ double red[kVW];
-  const int64_t nn = g.nn, i = (int64_t)blockIdx.x * kSolveBlock + threadIdx.x;
-  double bv[3] = {0.0, 0.0, 0.0};
-  if (i < nn) {
-    double r[3];
-    curl_N_at(g, BC, i, r);
-    for (int c = 0; c < 3; ++c) {
-      const double e = En[c * nn + i];
-      bv[c] = (e + c_j * (double)J[c * nn + i]) + c_b * r[c];
-      b[c * nn + i] = bv[c];
-      Et[c * nn + i] = e;
+  double* col = sh;                        // j + 2
+  double* c = sh + kMaxRestart + 2;        // j
+  double* sn = c + kMaxRestart;            // j
+  const int t = threadIdx.x, m = G.m;
+  const bool active = fl[0] != 0;
+  if (active) {
+    if (t <= j) col[t] = G.h1[t] + G.h2[t];
+    if (t < j) {
+      c[t] = G.cs[t];
+      sn[t] = G.sn[t];
     }
   }
-  write_partials(1, [&](int) { return bv[0] * bv[0] + bv[1] * bv[1] + bv[2] * bv[2]; }, red, Pb, nblk, blockIdx.x);
+  __syncthreads();
+  if (t == 0) {
+    double* hist = G.rb + 4;
+    if (!active) {
+      hist[j] = -1.0;
+    } else {
+      col[j + 1] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = c[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + c[i] * b;
+      }
+      const double a = col[j], b = col[j + 1];
+      const double rr = hypot(a, b);
+      const double cj = rr > 0.0 ? a / rr : 1.0, sj = rr > 0.0 ? b / rr : 0.0;
+      col[j] = rr;
+      col[j + 1] = 0.0;
+      G.cs[j] = cj;
+      G.sn[j] = sj;
+      const double gj = G.gv[j];
+      G.gv[j + 1] = -sj * gj;
+      G.gv[j] = cj * gj;
+      hist[j] = fabs(sj * gj);
+      fl[1] = j + 1;
+      if (hist[j] <= G.rb[0] || hn == 0.0) fl[0] = 0;
+    }
+  }
+  __syncthreads();
+  if (active && t <= j + 1) G.H[(int64_t)t * m + j] = col[t];
 }
 
-// R = b - A X, P3: partial |R|^2
-template <typename TM>
-__global__ void __launch_bounds__(kSolveBlock) k_residual_op(Grid g, const TM* __restrict__ M, CurlK K,
-                                                             double cm, const double* __restrict__ X,
-                                                             const double* __restrict__ b, double* __restrict__ R,
-                                                             double* __restrict__ P3, int nblk) {
-  __shared__ double red[kVW];
+// R = b - A X and the partial |R|^2 into Pr. FIRST: X = E^n, and b =
+// E^n + c_j J + c_b curl_N(B_C^n) is formed here (written to bout, with
+// its partial |b|^2 into Pb = Pr - nblk) and E_theta = E^n. LAST (X =
+// E^{n+theta}, the end of a batch): also the field advance
+// E^{n+1} = 2 E^{n+theta} - E^n, B_C^{n+1} = 2 (B_C^n - ctd curl_C E^{n+theta}) - B_C^n
+// (cell gid's curl from the neighbours the operator loads), and yp = yn,
+// the update X now holds.
+struct ResidualArgs {
+  const double* X;
+  const double* b;
+  double* R;
+  double* Pr;
+  // FIRST
+  const void* J;
+  const double* BC;
+  double c_j, c_b;
+  double* bout;
+  double* Et;
+  // LAST
+  const double* En;
+  double ctd;
+  double* En1;
+  double* BCn1;
+};
+template <typename TM, bool FIRST, bool LAST>
+__global__ void __launch_bounds__(kSolveBlock) k_residual_op(Grid g, const TM* __restrict__ M, CurlK K, double cm,
+                                                             ResidualArgs A, int nblk, GmresState G) {
+  __shared__ double red[2 * kVW];
+  if (LAST && blockIdx.x == 0 && threadIdx.x == 0) {
+    int* fl = gmres_flags(G);
+    for (int v = 0; v < fl[3]; ++v) G.yp[v] = G.yn[v];
+    fl[2] = fl[3];
+  }
   const int blk = xcd_block();
   const int64_t nn = g.nn, i = (int64_t)blk * kSolveBlock + threadIdx.x;
-  double r[3] = {0.0, 0.0, 0.0};
+  double r[3] = {0.0, 0.0, 0.0}, bv[3] = {0.0, 0.0, 0.0};
   if (i < nn) {
-    double y[3], xo[3];
-    apply_at(g, M, K, cm, X, 1.0, i, y, xo);
+    if (FIRST) {
+      double cn[3];
+      curl_N_at(g, A.BC, i, cn);
+      const TM* J = (const TM*)A.J;
+      for (int c = 0; c < 3; ++c) {
+        const double e = A.X[c * nn + i];
+        bv[c] = (e + A.c_j * (double)J[c * nn + i]) + A.c_b * cn[c];
+        A.bout[c * nn + i] = bv[c];
+        A.Et[c * nn + i] = e;
+      }
+      // keep the right-hand side's loads out of the operator's schedule
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    double y[3], xo[3], d[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    apply_at<TM, LAST>(g, M, K, cm, A.X, 1.0, i, y, xo, d);
+    if (LAST) __builtin_amdgcn_sched_barrier(0);
+    if (!FIRST)
+      for (int c = 0; c < 3; ++c) bv[c] = A.b[c * nn + i];
     for (int c = 0; c < 3; ++c) {
-      r[c] = b[c * nn + i] - y[c];
-      R[c * nn + i] = r[c];
+      r[c] = bv[c] - y[c];
+      A.R[c * nn + i] = r[c];
+    }
+    if (LAST) {
+      const double ix = 1.0 / (4.0 * g.hx), iy = 1.0 / (4.0 * g.hy), iz = 1.0 / (4.0 * g.hz);
+      const double cc[3] = {d[1][2] * iy - d[2][1] * iz, d[2][0] * iz - d[0][2] * ix, d[0][1] * ix - d[1][0] * iy};
+      for (int c = 0; c < 3; ++c) {
+        const double en = A.En[c * nn + i], bc = A.BC[c * nn + i];
+        A.En1[c * nn + i] = 2.0 * xo[c] - en;
+        A.BCn1[c * nn + i] = 2.0 * (bc - A.ctd * cc[c]) - bc;
+      }
     }
   }
-  write_partials(1, [&](int) { return r[0] * r[0] + r[1] * r[1] + r[2] * r[2]; }, red, P3, nblk, blk);
+  if (FIRST)
+    write_partials(
+        2, [&](int v) { return v == 0 ? bv[0] * bv[0] + bv[1] * bv[1] + bv[2] * bv[2] : r[0] * r[0] + r[1] * r[1] + r[2] * r[2]; },
+        red, A.Pr - nblk, nblk, blk);
+  else
+    write_partials(1, [&](int) { return r[0] * r[0] + r[1] * r[1] + r[2] * r[2]; }, red, A.Pr, nblk, blk);
 }
 
 // Step s of the Arnoldi process, first kernel: V_s = w_s / |w_s| (|w_s|^2
@@ -471,10 +533,12 @@ __global__ void __launch_bounds__(kSolveBlock) k_arnoldi_op(Grid g, const TM* __
   sum_partials(P3, nblk, 1, red, sc);
   const double hn = sqrt(sc[0]);
   const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
-  if (blockIdx.x == 0 && mode != kArnoldiNone) {
-    if (mode == kArnoldiStart) sum_partials(G.Pb, nblk, 1, red, sc + 1);
+  __shared__ double gsh[3 * kMaxRestart + 2];
+  if (blockIdx.x == 0 && mode == kArnoldiGivens) givens_column(s - 1, G, hn, gsh);
+  if (blockIdx.x == 0 && mode == kArnoldiStart) {
+    sum_partials(G.Pb, nblk, 1, red, sc + 1);
     if (threadIdx.x == 0) {
-      if (mode == kArnoldiStart) {
+      {
         const double thresh = 0.5 * G.tol * sqrt(sc[1]);
         G.rb[0] = thresh;
         G.rb[1] = hn;
@@ -484,8 +548,6 @@ __global__ void __launch_bounds__(kSolveBlock) k_arnoldi_op(Grid g, const TM* __
         fl[1] = 0;
         fl[2] = 0;
         fl[3] = 0;
-      } else {
-        givens_column(s - 1, G, hn);
       }
     }
   }
@@ -515,7 +577,10 @@ __global__ void __launch_bounds__(kSolveBlock) k_arnoldi_op(Grid g, const TM* __
 // A Gram-Schmidt pass over V_0..V_{k-1}: h_v = the sums of the partials Pin,
 // w -= sum_v h_v V_v, then either the next pass's partial inner products
 // <V_v, w> (NORM false) or the partial |w|^2 (NORM true) into Pout.
-// Workgroup 0 stores h into coef for the Givens update.
+// Workgroup 0 stores h into coef for the Givens update. w and the first kKV
+// basis vectors are loaded before the partials are summed, so their latency
+// overlaps the reduction.
+constexpr int kKV = 8;
 template <bool NORM>
 __global__ void __launch_bounds__(kSolveBlock) k_cgs_pass(const double* __restrict__ V, int64_t ld, int k, int64_t nn,
                                                           const double* __restrict__ Pin, double* __restrict__ coef,
@@ -523,46 +588,101 @@ __global__ void __launch_bounds__(kSolveBlock) k_cgs_pass(const double* __restri
                                                           int nblk) {
   __shared__ double red[kRed];
   __shared__ double h[kMaxRestart + 1];
+  const int64_t i = (int64_t)blockIdx.x * kSolveBlock + threadIdx.x;
+  const bool live = i < nn;
+  double w[3] = {0.0, 0.0, 0.0}, vr[kKV][3];
+#pragma unroll
+  for (int v = 0; v < kKV; ++v) vr[v][0] = vr[v][1] = vr[v][2] = 0.0;
+  if (live) {
+    for (int c = 0; c < 3; ++c) w[c] = W[c * nn + i];
+#pragma unroll
+    for (int v = 0; v < kKV; ++v)
+      if (v < k)
+        for (int c = 0; c < 3; ++c) vr[v][c] = V[(int64_t)v * ld + c * nn + i];
+  }
   sum_partials(Pin, nblk, k, red, h);
   if (blockIdx.x == 0)
     for (int v = threadIdx.x; v < k; v += kSolveBlock) coef[v] = h[v];
-  const int64_t i = (int64_t)blockIdx.x * kSolveBlock + threadIdx.x;
-  const bool live = i < nn;
-  double w[3] = {0.0, 0.0, 0.0};
   if (live) {
-    for (int c = 0; c < 3; ++c) w[c] = W[c * nn + i];
-    for (int v = 0; v < k; ++v) {
+#pragma unroll
+    for (int v = 0; v < kKV; ++v)
+      if (v < k)
+        for (int c = 0; c < 3; ++c) w[c] = fma(-h[v], vr[v][c], w[c]);
+    for (int v = kKV; v < k; ++v) {
       const double* Vv = V + (int64_t)v * ld;
       for (int c = 0; c < 3; ++c) w[c] = fma(-h[v], Vv[c * nn + i], w[c]);
     }
     for (int c = 0; c < 3; ++c) W[c * nn + i] = w[c];
   }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (NORM) {
-    write_partials(1, [&](int) { return w[0] * w[0] + w[1] * w[1] + w[2] * w[2]; }, red, Pout, nblk, blockIdx.x);
+    const double sq = wave_sum(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    if (lane == 0) red[wv] = sq;
   } else {
-    write_partials(
-        k,
-        [&](int v) {
-          if (!live) return 0.0;
-          const double* Vv = V + (int64_t)v * ld;
-          return Vv[i] * w[0] + Vv[nn + i] * w[1] + Vv[2 * nn + i] * w[2];
-        },
-        red, Pout, nblk, blockIdx.x);
+#pragma unroll
+    for (int v = 0; v < kKV; ++v)
+      if (v < k) {
+        const double d = wave_sum(vr[v][0] * w[0] + vr[v][1] * w[1] + vr[v][2] * w[2]);
+        if (lane == 0) red[v * kVW + wv] = d;
+      }
+    for (int v = kKV; v < k; ++v) {
+      const double* Vv = V + (int64_t)v * ld;
+      const double d = wave_sum(live ? Vv[i] * w[0] + Vv[nn + i] * w[1] + Vv[2 * nn + i] * w[2] : 0.0);
+      if (lane == 0) red[v * kVW + wv] = d;
+    }
+  }
+  __syncthreads();
+  const int nv = NORM ? 1 : k;
+  for (int v = threadIdx.x; v < nv; v += kSolveBlock) {
+    double t = 0.0;
+    for (int q = 0; q < kVW; ++q) t += red[v * kVW + q];
+    Pout[(int64_t)v * nblk + blockIdx.x] = t;
   }
 }
 
 // After the last step of a batch: the Givens update of column j, then y
 // from the upper triangle H y = g over the columns that count (flags[1]),
-// into yn (flags[3] = their number).
+// into yn (flags[3] = their number). The triangle is staged in LDS when it
+// has at most kTri columns.
+constexpr int kTri = 40;
 __global__ void __launch_bounds__(kSolveBlock) k_givens_tail(int j, const double* __restrict__ P3, int nblk,
                                                              GmresState G) {
   __shared__ double red[kVW];
   __shared__ double sc[1];
+  __shared__ double gsh[3 * kMaxRestart + 2];
+  __shared__ double tri[kTri * (kTri + 1) / 2 + kTri];
+  __shared__ double yl[kTri];
+  __shared__ int cols;
   sum_partials(P3, nblk, 1, red, sc);
-  if (threadIdx.x == 0) {
-    givens_column(j, G, sqrt(sc[0]));
-    int* fl = gmres_flags(G);
-    const int m = G.m, jj = fl[1];
+  givens_column(j, G, sqrt(sc[0]), gsh);
+  int* fl = gmres_flags(G);
+  if (threadIdx.x == 0) cols = fl[1];   // written by this thread in givens_column
+  __syncthreads();
+  const int m = G.m, jj = cols;
+  if (jj <= kTri) {
+    // row i of the triangle (columns i..jj-1) at tri[i jj - i (i - 1) / 2 ...], then g
+    for (int e = threadIdx.x; e < jj * (jj + 1) / 2; e += kSolveBlock) {
+      int i = 0, r = e;
+      while (r >= jj - i) {
+        r -= jj - i;
+        ++i;
+      }
+      tri[e] = G.H[(int64_t)i * m + i + r];
+    }
+    for (int e = threadIdx.x; e < jj; e += kSolveBlock) tri[jj * (jj + 1) / 2 + e] = G.gv[e];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double* gg = tri + jj * (jj + 1) / 2;
+      for (int i = jj - 1; i >= 0; --i) {
+        const double* row = tri + i * jj - i * (i - 1) / 2;   // row[k - i] = H[i][k]
+        double s = gg[i];
+        for (int k = i + 1; k < jj; ++k) s -= row[k - i] * yl[k];
+        yl[i] = s / row[0];
+        G.yn[i] = yl[i];
+      }
+      fl[3] = jj;
+    }
+  } else if (threadIdx.x == 0) {
     for (int i = jj - 1; i >= 0; --i) {
       double s = G.gv[i];
       for (int k = i + 1; k < jj; ++k) s -= G.H[(int64_t)i * m + k] * G.yn[k];
@@ -670,27 +790,52 @@ void curl_curl_stencil(const Grid& g, double ctd2, CurlK& K) {
 
 int solve_blocks(const Grid& g) { return (int)((g.nn + kSolveBlock - 1) / kSolveBlock); }
 
-hipError_t launch_rhs_start(const Grid& g, const double* E_n, bool jf32, const void* J, const double* BC, double c_j,
-                            double c_b, double* b, double* E_t, double* Pb, hipStream_t st) {
+hipError_t launch_residual_first(const Grid& g, bool mf32, const void* M, const CurlK& K, double cm,
+                                 const double* E_n, const void* J, const double* BC, double c_j, double c_b,
+                                 double* b, double* E_t, double* R, double* Pb, double* Pr, hipStream_t st) {
   const int nb = solve_blocks(g);
-  if (jf32)
-    hipLaunchKernelGGL(k_rhs_start<float>, dim3(nb), dim3(kSolveBlock), 0, st, g, E_n, (const float*)J, BC, c_j, c_b,
-                       b, E_t, Pb, nb);
+  if (Pr != Pb + nb) return hipErrorInvalidValue;
+  ResidualArgs A{};
+  A.X = E_n;
+  A.R = R;
+  A.Pr = Pr;
+  A.J = J;
+  A.BC = BC;
+  A.c_j = c_j;
+  A.c_b = c_b;
+  A.bout = b;
+  A.Et = E_t;
+  GmresState none{};
+  if (mf32)
+    hipLaunchKernelGGL((k_residual_op<float, true, false>), dim3(nb), dim3(kSolveBlock), 0, st, g, (const float*)M,
+                       K, cm, A, nb, none);
   else
-    hipLaunchKernelGGL(k_rhs_start<double>, dim3(nb), dim3(kSolveBlock), 0, st, g, E_n, (const double*)J, BC, c_j,
-                       c_b, b, E_t, Pb, nb);
+    hipLaunchKernelGGL((k_residual_op<double, true, false>), dim3(nb), dim3(kSolveBlock), 0, st, g,
+                       (const double*)M, K, cm, A, nb, none);
   return hipGetLastError();
 }
 
-hipError_t launch_residual_op(const Grid& g, bool mf32, const void* M, const CurlK& K, double cm,
-                              const double* X, const double* b, double* R, double* P3, hipStream_t st) {
+hipError_t launch_residual_last(const Grid& g, bool mf32, const void* M, const CurlK& K, double cm,
+                                const double* E_t, const double* b, double* R, double* Pr, const double* E_n,
+                                const double* BC_n, double ctd, double* E_next, double* BC_next,
+                                const GmresState& G, hipStream_t st) {
   const int nb = solve_blocks(g);
+  ResidualArgs A{};
+  A.X = E_t;
+  A.b = b;
+  A.R = R;
+  A.Pr = Pr;
+  A.BC = BC_n;
+  A.En = E_n;
+  A.ctd = ctd;
+  A.En1 = E_next;
+  A.BCn1 = BC_next;
   if (mf32)
-    hipLaunchKernelGGL(k_residual_op<float>, dim3(nb), dim3(kSolveBlock), 0, st, g, (const float*)M, K, cm, X,
-                       b, R, P3, nb);
+    hipLaunchKernelGGL((k_residual_op<float, false, true>), dim3(nb), dim3(kSolveBlock), 0, st, g, (const float*)M,
+                       K, cm, A, nb, G);
   else
-    hipLaunchKernelGGL(k_residual_op<double>, dim3(nb), dim3(kSolveBlock), 0, st, g, (const double*)M, K, cm,
-                       X, b, R, P3, nb);
+    hipLaunchKernelGGL((k_residual_op<double, false, true>), dim3(nb), dim3(kSolveBlock), 0, st, g,
+                       (const double*)M, K, cm, A, nb, G);
   return hipGetLastError();
 }
 

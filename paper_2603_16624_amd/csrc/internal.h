@@ -112,12 +112,16 @@ struct GmresState {
   double tol;
 };
 enum { kArnoldiNone = 0, kArnoldiStart = 1, kArnoldiGivens = 2 };
-// b = E^n + c_j J + c_b curl_N B_C, E_t = E^n, Pb: partial |b|^2
-hipError_t launch_rhs_start(const Grid& g, const double* E_n, bool jf32, const void* J, const double* BC, double c_j,
-                            double c_b, double* b, double* E_t, double* Pb, hipStream_t st);
-// R = b - A X, P3: partial |R|^2
-hipError_t launch_residual_op(const Grid& g, bool mf32, const void* M, const CurlK& K, double cm,
-                              const double* X, const double* b, double* R, double* P3, hipStream_t st);
+// R = b - A E^n with b = E^n + c_j J + c_b curl_N B_C formed on the way
+// (E_t = E^n); Pb, Pr: partial |b|^2 and |R|^2 (Pr = Pb + solve_blocks(g))
+hipError_t launch_residual_first(const Grid& g, bool mf32, const void* M, const CurlK& K, double cm,
+                                 const double* E_n, const void* J, const double* BC, double c_j, double c_b,
+                                 double* b, double* E_t, double* R, double* Pb, double* Pr, hipStream_t st);
+// R = b - A E_t, Pr: partial |R|^2, the field advance from E_t, and yp = yn
+hipError_t launch_residual_last(const Grid& g, bool mf32, const void* M, const CurlK& K, double cm,
+                                const double* E_t, const double* b, double* R, double* Pr, const double* E_n,
+                                const double* BC_n, double ctd, double* E_next, double* BC_next,
+                                const GmresState& G, hipStream_t st);
 // step s: V_s = Win / |Win| (|Win|^2 from P3), Wout = A V_s, P1: partial
 // <V_v, Wout>, v <= s; mode: start the cycle or close column s - 1
 hipError_t launch_arnoldi_op(const Grid& g, bool mf32, const void* M, const CurlK& K, double cm,
