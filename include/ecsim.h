@@ -286,7 +286,7 @@ ecsim_status ecsim_move_moments_regroup(const ecsim_grid *grid, const ecsim_part
  *   M_{g g'} x_{g'}, using the 14 stored blocks and M_{g,g-o} = M_{g-o,g}
  *   (identical, not transposed, blocks).
  * M: [14][9][Nn] in precision m_prec; x, y: FP64 [3][Nn]; x and y must not
- * alias. Arithmetic is FP64.
+ * alias. Arithmetic is FP64. Grids of fewer than 2^29 cells, else ECSIM_EINVAL.
  */
 ecsim_status ecsim_mass_apply(const ecsim_grid *grid, int32_t m_prec, const void *M,
                               const double *x, double a, double b, double *y,

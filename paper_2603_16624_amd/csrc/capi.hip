@@ -417,6 +417,7 @@ ecsim_status ecsim_mass_apply(const ecsim_grid* grid, int32_t m_prec, const void
   if (check_prec(m_prec) != ECSIM_OK) return ECSIM_EINVAL;
   if (!M || !x || !y) return fail(ECSIM_EINVAL, "ecsim_mass_apply: M, x and y are required");
   if ((const void*)x == (const void*)y) return fail(ECSIM_EINVAL, "ecsim_mass_apply: x and y must not alias");
+  if (g.nn >= ((int64_t)1 << 29)) return fail(ECSIM_EINVAL, "ecsim_mass_apply: at most 2^29 - 1 cells");
   hipError_t e = launch_mass_apply(g, m_prec == ECSIM_F32, M, x, a, b, y, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "ecsim_mass_apply");
   return ECSIM_OK;

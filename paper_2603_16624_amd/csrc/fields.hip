@@ -32,37 +32,48 @@ __global__ void __launch_bounds__(kBlock) k_mass_apply(Grid g, const TM* __restr
   if (gid >= nn) return;
   int ix, iy, iz;
   decode_cell(g, (int)gid, ix, iy, iz);
+  // a plane of x or M holds fewer than 2^29 values (checked by the caller),
+  // so the per-thread part of every address is a 32-bit byte offset from a
+  // uniform base
+  const char* xb = (const char*)x;
+  const uint32_t own = (uint32_t)gid * (uint32_t)sizeof(TM);
   double y0 = 0.0, y1 = 0.0, y2 = 0.0;
 #pragma unroll
   for (int k = 0; k < 14; ++k) {
     int ox, oy, oz;
     offset14(k, ox, oy, oz);
-    const TM* Mk = M + (int64_t)k * 9 * nn;
+    const char* Mk = (const char*)(M + (int64_t)k * 9 * nn);
+    const int64_t pl = nn * (int64_t)sizeof(TM);
+    auto mat = [&](int q, uint32_t off) { return (double)*(const TM*)(Mk + q * pl + off); };
+    auto xv = [&](int c, uint32_t off) { return *(const double*)(xb + c * nn * 8 + off); };
     {
-      int64_t gp = shift(ix, ox, g.nx) + (int64_t)g.nx * (shift(iy, oy, g.ny) + (int64_t)g.ny * shift(iz, oz, g.nz));
-      double e0 = x[gp], e1 = x[nn + gp], e2 = x[2 * nn + gp];
-      y0 = fma((double)Mk[0 * nn + gid], e0, y0);
-      y0 = fma((double)Mk[1 * nn + gid], e1, y0);
-      y0 = fma((double)Mk[2 * nn + gid], e2, y0);
-      y1 = fma((double)Mk[3 * nn + gid], e0, y1);
-      y1 = fma((double)Mk[4 * nn + gid], e1, y1);
-      y1 = fma((double)Mk[5 * nn + gid], e2, y1);
-      y2 = fma((double)Mk[6 * nn + gid], e0, y2);
-      y2 = fma((double)Mk[7 * nn + gid], e1, y2);
-      y2 = fma((double)Mk[8 * nn + gid], e2, y2);
+      const uint32_t gp = (uint32_t)shift(ix, ox, g.nx) +
+                          (uint32_t)g.nx * ((uint32_t)shift(iy, oy, g.ny) + (uint32_t)g.ny * (uint32_t)shift(iz, oz, g.nz));
+      const double e0 = xv(0, gp * 8u), e1 = xv(1, gp * 8u), e2 = xv(2, gp * 8u);
+      y0 = fma(mat(0, own), e0, y0);
+      y0 = fma(mat(1, own), e1, y0);
+      y0 = fma(mat(2, own), e2, y0);
+      y1 = fma(mat(3, own), e0, y1);
+      y1 = fma(mat(4, own), e1, y1);
+      y1 = fma(mat(5, own), e2, y1);
+      y2 = fma(mat(6, own), e0, y2);
+      y2 = fma(mat(7, own), e1, y2);
+      y2 = fma(mat(8, own), e2, y2);
     }
     if (k > 0) {
-      int64_t gm = shift(ix, -ox, g.nx) + (int64_t)g.nx * (shift(iy, -oy, g.ny) + (int64_t)g.ny * shift(iz, -oz, g.nz));
-      double e0 = x[gm], e1 = x[nn + gm], e2 = x[2 * nn + gm];
-      y0 = fma((double)Mk[0 * nn + gm], e0, y0);
-      y0 = fma((double)Mk[1 * nn + gm], e1, y0);
-      y0 = fma((double)Mk[2 * nn + gm], e2, y0);
-      y1 = fma((double)Mk[3 * nn + gm], e0, y1);
-      y1 = fma((double)Mk[4 * nn + gm], e1, y1);
-      y1 = fma((double)Mk[5 * nn + gm], e2, y1);
-      y2 = fma((double)Mk[6 * nn + gm], e0, y2);
-      y2 = fma((double)Mk[7 * nn + gm], e1, y2);
-      y2 = fma((double)Mk[8 * nn + gm], e2, y2);
+      const uint32_t gm = (uint32_t)shift(ix, -ox, g.nx) +
+                          (uint32_t)g.nx * ((uint32_t)shift(iy, -oy, g.ny) + (uint32_t)g.ny * (uint32_t)shift(iz, -oz, g.nz));
+      const uint32_t gmo = gm * (uint32_t)sizeof(TM);
+      const double e0 = xv(0, gm * 8u), e1 = xv(1, gm * 8u), e2 = xv(2, gm * 8u);
+      y0 = fma(mat(0, gmo), e0, y0);
+      y0 = fma(mat(1, gmo), e1, y0);
+      y0 = fma(mat(2, gmo), e2, y0);
+      y1 = fma(mat(3, gmo), e0, y1);
+      y1 = fma(mat(4, gmo), e1, y1);
+      y1 = fma(mat(5, gmo), e2, y1);
+      y2 = fma(mat(6, gmo), e0, y2);
+      y2 = fma(mat(7, gmo), e1, y2);
+      y2 = fma(mat(8, gmo), e2, y2);
     }
   }
   if (b == 0.0) {

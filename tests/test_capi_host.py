@@ -144,6 +144,12 @@ def test_mass_apply_and_solve_validation(E):
     bad = list(args)
     bad[6] = 0.0
     assert L.ecsim_field_solve(*bad, fake, need, ctypes.byref(it), ctypes.byref(res), None) == E.EINVAL
+    # 2^29 cells: beyond the 32-bit byte offsets of the operator kernels
+    big = E.Grid((1024, 1024, 512), (1.0, 1.0, 1.0), 0.1).c()
+    assert L.ecsim_mass_apply(ctypes.byref(big), E.F64, fake, fake, 1.0, 0.0, ctypes.c_void_p(0x2000), None) == E.EINVAL
+    big_args = [ctypes.byref(big)] + args[1:]
+    assert L.ecsim_field_solve(*big_args, fake, 1 << 62, ctypes.byref(it), ctypes.byref(res), None) == E.EINVAL
+    assert b"2^29" in L.ecsim_last_error()
 
 
 def test_sort_and_backward_validation(E):
