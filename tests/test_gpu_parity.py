@@ -702,6 +702,24 @@ def test_field_solve_restarted(E, O, I, restart):
     assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
 
 
+def test_field_solve_batches_of_one_cycle(E, O, I):
+    """After a GMRES(1) solve the first batch of the next solve is one step
+    long, so a GMRES(30) solve continues its cycle over several batches, each
+    closed by moving E by V times the change in y: the same solution."""
+    say("field solve, one cycle over several batches")
+    p, J, M27, En, BC = solve_inputs(E, O, I)
+    grid = E.Grid(p.n, p.h, p.dt)
+    M14 = dev(O.m14(p.n, M27))
+    Et, En1, Bn1 = (torch.empty((3, p.nn), dtype=torch.float64, device="cuda") for _ in range(3))
+    E.field_solve(grid, M14, dev(J), dev(En), dev(BC), Et, En1, Bn1, tol=1e-10, restart=1, maxit=500)
+    it, res = E.field_solve(grid, M14, dev(J), dev(En), dev(BC), Et, En1, Bn1, tol=1e-10, restart=30, maxit=500)
+    ref = O.field_solve(p.n, p.h, p.dt, M27, J, En, BC, tol=1e-13)
+    assert 1 < it <= 30 and res <= 1e-10
+    assert rel(host(Et), ref["E_theta"]) < 1e-9
+    assert rel(host(En1), ref["E_next"]) < 1e-9
+    assert rel(host(Bn1), ref["BC_next"]) < 1e-9
+
+
 def test_field_solve_no_convergence(E, O, I):
     """maxit below what tol needs: ENOCONV, and the outputs hold the last
     iterate advanced consistently (E^{n+1} = 2 E^{n+theta} - E^n)."""
