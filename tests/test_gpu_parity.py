@@ -645,10 +645,12 @@ def test_mass_apply_dense_2x2x2(E, O, I):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("mprec,n", [("f64", (6, 5, 4)), ("f32", (6, 5, 4)), ("f64", (32, 16, 16)),
-                                     ("f32", (13, 11, 9))])
+                                     ("f32", (13, 11, 9)), ("f64", (2, 2, 2)), ("f64", (1, 3, 2))])
 def test_field_solve(E, O, I, mprec, n):
     """One workgroup (120 nodes), eight (8192 nodes: the XCD-contiguous block
-    order of the operator kernels) and two with a ragged tail (1287 nodes)."""
+    order of the operator kernels), two with a ragged tail (1287 nodes), and
+    grids where the periodic images of g + o and g - o coincide (2 cells) or
+    equal g (1 cell), which the curl-curl stencil must count once per offset."""
     say("field solve", mprec, n)
     p, _, BN = make_case(I, n, 6, 10)
     J, M27 = O.species_moments(p, [s.x for s in p.species], [s.v for s in p.species], BN)
