@@ -742,6 +742,27 @@ def test_field_solve_no_convergence(E, O, I):
     assert 1e-14 * np.linalg.norm(b) < np.linalg.norm(r) < np.linalg.norm(r0)
 
 
+def test_field_solve_long_cycle(E, O, I):
+    """A 30 times longer time step makes the system harder: one GMRES(60)
+    cycle takes more than 40 columns, beyond the least-squares triangle the
+    last kernel of a batch stages in LDS, and must still give the oracle's
+    solution."""
+    say("field solve, more than 40 columns in one cycle")
+    p, J, M27, En, BC = solve_inputs(E, O, I)
+    dt = 30 * p.dt
+    grid = E.Grid(p.n, p.h, dt)
+    Et, En1, Bn1 = (torch.empty((3, p.nn), dtype=torch.float64, device="cuda") for _ in range(3))
+    it, res = E.field_solve(grid, dev(O.m14(p.n, M27)), dev(J), dev(En), dev(BC), Et, En1, Bn1, tol=1e-12,
+                            restart=60, maxit=200)
+    assert 40 < it <= 60 and res <= 1e-12
+    ref = O.field_solve(p.n, p.h, dt, M27, J, En, BC, tol=1e-14, restart=120, maxit=400)
+    assert rel(host(Et), ref["E_theta"]) < 1e-10
+    assert rel(host(Bn1), ref["BC_next"]) < 1e-10
+    b = O.field_rhs(p.n, p.h, dt, J, En, BC)
+    r = b - O.field_operator(p.n, p.h, dt, M27, host(Et))
+    assert np.linalg.norm(r) <= 2e-12 * np.linalg.norm(b)
+
+
 def test_field_solve_zero_rhs(E, O, I):
     """b = 0 (E^n, J and B^n zero): E^{n+theta} = 0 after no iterations."""
     say("field solve, zero right-hand side")
