@@ -485,15 +485,20 @@ __device__ __forceinline__ Ranges make_ranges(const TArgs<T>& args, const RangeL
   return q;
 }
 
+constexpr int kRec = 24;   // record rows: 12 values, 3 + 9 weight factors
+
 // A particle's record: the 12 values ((q beta / V) alpha, (q / V) alpha v)
-// and its 27 class weights, from the deposit field B1 at its position.
+// and the factors of its 27 class weights, from the deposit field B1 at its
+// position: the x factors f_x[cx] (3) and the products f_y[cy] f_z[cz] (9,
+// at cy + 3 cz); the weight of class cx + 3 (cy + 3 cz) is their product,
+// formed where the matrix cores take it.
 // FP64: alpha from rotation() (the mover's routine, so the two agree bit for
 // bit). FP32: alpha = N / D with N = I + b b^T - [b x], b = beta B, written
 // into the record with the charge factors folded into 1/D (one product per
 // entry instead of two).
 template <typename T>
 __device__ __forceinline__ void particle_record(const Stencil<T>& ps, const Vec3<T>& B1, const Vec3<T>& v, T q,
-                                                const TSpecies<T>& sp, T r[39]) {
+                                                const TSpecies<T>& sp, T r[kRec]) {
   if constexpr (sizeof(T) == 4) {
     const T bx = sp.beta * B1.x, by = sp.beta * B1.y, bz = sp.beta * B1.z;
     const T xx = bx * bx, yy = by * by, zz = bz * bz, xy = bx * by, xz = bx * bz, yz = by * bz;
@@ -526,18 +531,20 @@ __device__ __forceinline__ void particle_record(const Stencil<T>& ps, const Vec3
     f[d][2] = ps.w1[d] * ps.w1[d];
   }
 #pragma unroll
-  for (int c = 0; c < 27; ++c) r[12 + c] = (f[0][c % 3] * f[1][(c / 3) % 3]) * f[2][c / 9];
+  for (int c = 0; c < 3; ++c) r[12 + c] = f[0][c];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) r[15 + c] = f[1][c % 3] * f[2][c / 3];
 }
 
 // Records in LDS are stored transposed, rec[row][slot] with a row stride of
 // 66 slots (64 particles + 2): the matrix-core operand reads of 16 lanes with
-// consecutive rows and 2 lane groups then hit 32 different banks. Rows 39-41
-// are not read as used operands; they hold the cell's current class sums at
-// the end of a cell. A 4-wavefront workgroup needs 44 KB of LDS (FP32), so
-// three workgroups share a CU.
+// consecutive rows and 2 lane groups then hit 32 different banks. Rows 24-25
+// hold the cell's current class sums at the end of a cell (read as operands
+// only by the unused classes 27-31). A 4-wavefront workgroup needs 27 KB of
+// LDS (FP32), so four workgroups fit a CU.
 constexpr int kSlots = 66;
-constexpr int kRows = 42;
-constexpr int kTcur = 39 * kSlots;         // [27][3]: current class sums (end of a cell)
+constexpr int kRows = 26;
+constexpr int kTcur = kRec * kSlots;       // [27][3]: current class sums (end of a cell)
 
 
 // ---------------------------------------------------------------------------
@@ -1185,7 +1192,7 @@ k_mover(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
 // range particles still in the cell, then its strays) to the targets, species
 // by species in cell order: the next pass's grouping, without a separate sort.
 template <typename T, int TX, int TY, int TZ, int NW, bool REGROUP>
-__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
 k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   using MF = Mfma<T>;
   using acc_t = typename MF::acc;
@@ -1229,6 +1236,12 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
 
   T* const wrec = smem + wave * WREC;
   const T* const opnd = wrec + col * kSlots + grp;   // row col, slot grp
+  // this lane's classes col (tile 0) and 16 + col (tile 1): their x factor
+  // and y-z product rows
+  const T* const fx0 = wrec + (12 + col % 3) * kSlots + grp;
+  const T* const fq0 = wrec + (15 + col / 3) * kSlots + grp;
+  const T* const fx1 = wrec + (12 + (16 + col) % 3) * kSlots + grp;
+  const T* const fq1 = wrec + (15 + (16 + col) / 3) * kSlots + grp;
   T* const tcur = wrec + kTcur;                       // current class sums [27][3]
 
   // One-cell-ahead loads, one value per lane: lanes 0..9 the cell's range
@@ -1319,10 +1332,10 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
           B1.y = fma(W[a], f[1], B1.y);
           B1.z = fma(W[a], f[2], B1.z);
         }
-        T r[39];
+        T r[kRec];
         particle_record(ps, B1, Vec3<T>{pd.v0, pd.v1, pd.v2}, keep ? dep_charge(pd, lptr) : T(0), sp, r);
 #pragma unroll
-        for (int i = 0; i < 39; ++i) wrec[i * kSlots + lane] = r[i];
+        for (int i = 0; i < kRec; ++i) wrec[i * kSlots + lane] = r[i];
       }
       if constexpr (REGROUP) {
         // species by species (a block mostly holds one): the target index is
@@ -1368,8 +1381,8 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
       for (int k4 = 0; k4 < 64; k4 += 4) {
         if (k4 > 0 && k4 >= nk) break;
         const T a = opnd[k4];
-        const T b0 = opnd[12 * kSlots + k4];
-        const T b1 = opnd[28 * kSlots + k4];
+        const T b0 = fx0[k4] * fq0[k4];
+        const T b1 = fx1[k4] * fq1[k4];
         d0 = MF::run(a, b0, d0);
         d1 = MF::run(a, b1, d1);
       }
