@@ -1191,8 +1191,10 @@ k_mover(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
 // With REGROUP the deposit also writes every particle it takes (the cell's own
 // range particles still in the cell, then its strays) to the targets, species
 // by species in cell order: the next pass's grouping, without a separate sort.
+// FP32: 5 waves per SIMD (96 VGPRs, a few spilled: 709 -> 676 us at 64^3),
+// 4 for the regrouping form, which spills more at 5 (900 -> 930 us)
 template <typename T, int TX, int TY, int TZ, int NW, bool REGROUP>
-__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (REGROUP ? 4 : 5) : 1)))
 k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
   using MF = Mfma<T>;
   using acc_t = typename MF::acc;
