@@ -540,7 +540,7 @@ __device__ __forceinline__ void particle_record(const Stencil<T>& ps, const Vec3
 // 66 slots (64 particles + 2): the matrix-core operand reads of 16 lanes with
 // consecutive rows and 2 lane groups then hit 32 different banks. Rows 24-25
 // hold the cell's current class sums at the end of a cell (read as operands
-// only by the unused classes 27-31). A 4-wavefront workgroup needs 27 KB of
+// only by the unused classes 27-30). A 4-wavefront workgroup needs 27 KB of
 // LDS (FP32), so four workgroups fit a CU.
 constexpr int kSlots = 66;
 constexpr int kRows = 26;
@@ -1238,12 +1238,11 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
 
   T* const wrec = smem + wave * WREC;
   const T* const opnd = wrec + col * kSlots + grp;   // row col, slot grp
-  // this lane's classes col (tile 0) and 16 + col (tile 1): their x factor
-  // and y-z product rows
+  // this lane's classes: col in tile 0, 15 + col in tile 1 (classes 15-30:
+  // the same x factor, the y-z product 5 rows on; class 15 is taken from
+  // tile 0 and 27-30 are not used)
   const T* const fx0 = wrec + (12 + col % 3) * kSlots + grp;
   const T* const fq0 = wrec + (15 + col / 3) * kSlots + grp;
-  const T* const fx1 = wrec + (12 + (16 + col) % 3) * kSlots + grp;
-  const T* const fq1 = wrec + (15 + (16 + col) / 3) * kSlots + grp;
   T* const tcur = wrec + kTcur;                       // current class sums [27][3]
 
   // One-cell-ahead loads, one value per lane: lanes 0..9 the cell's range
@@ -1383,8 +1382,9 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
       for (int k4 = 0; k4 < 64; k4 += 4) {
         if (k4 > 0 && k4 >= nk) break;
         const T a = opnd[k4];
-        const T b0 = fx0[k4] * fq0[k4];
-        const T b1 = fx1[k4] * fq1[k4];
+        const T fx = fx0[k4];
+        const T b0 = fx * fq0[k4];
+        const T b1 = fx * fq0[5 * kSlots + k4];
         d0 = MF::run(a, b0, d0);
         d1 = MF::run(a, b1, d1);
       }
@@ -1406,8 +1406,8 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
     T* const sc = args.csum + (int64_t)(cell >= 0 ? cell : 0) * SCS;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      const int cls = t * 16 + col;
-      if (cls >= 27) continue;
+      const int cls = t * 15 + col;
+      if (cls >= 27 || (t == 1 && col == 0)) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int row = MF::row(lane, q);
