@@ -1390,14 +1390,23 @@ k_deposit(Grid g, TArgs<T> args, int ntx, int nty, int ntz) {
         d0 = MF::run(a, b0, d0);
         d1 = MF::run(a, b1, d1);
       }
+      if (cb == 0) {
+        // the cell's first block: the compensated sum of one term is the term
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if constexpr (sizeof(T) == 4) {
-          kahan(S[0][q], C[0][q], d0[q]);
-          kahan(S[1][q], C[1][q], d1[q]);
-        } else {
-          S[0][q] += d0[q];
-          S[1][q] += d1[q];
+        for (int q = 0; q < 4; ++q) {
+          S[0][q] = d0[q];
+          S[1][q] = d1[q];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if constexpr (sizeof(T) == 4) {
+            kahan(S[0][q], C[0][q], d0[q]);
+            kahan(S[1][q], C[1][q], d1[q]);
+          } else {
+            S[0][q] += d0[q];
+            S[1][q] += d1[q];
+          }
         }
       }
       wave_sync();
