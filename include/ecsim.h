@@ -369,7 +369,10 @@ ecsim_status ecsim_to_f32(int64_t n, const double *src, float *dst, void *stream
  * ws: device workspace of ecsim_solve_workspace_size() bytes.
  * iters_out, resid_out (host, nullable): iterations and final relative
  * residual. Returns ECSIM_ENOCONV if maxit iterations did not reach tol (the
- * outputs then hold the last iterate).
+ * outputs then hold the last iterate). The Arnoldi steps run on the device in
+ * batches; the host reads back once per batch (once per call when the call
+ * needs as many steps as the previous call in the process needed at its
+ * start), and the returned residual is the true one, ||b - A E|| / ||b||.
  */
 ecsim_status ecsim_solve_workspace_size(const ecsim_grid *grid, int32_t restart, size_t *bytes);
 ecsim_status ecsim_field_solve(const ecsim_grid *grid, int32_t m_prec, const void *M,
