@@ -1803,9 +1803,7 @@ __global__ void __launch_bounds__(256) k_move_strays(Grid g, TArgs<T> args) {
 // stray list: rank by cell, then scatter into cell order
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_stray_rank(const int* __restrict__ count, const int* __restrict__ cellv,
-                                                    int* __restrict__ counts, int* __restrict__ ranks,
-                                                    const int* __restrict__ items, int* __restrict__ scount,
-                                                    int64_t nn) {
+                                                    int* __restrict__ counts, int* __restrict__ ranks) {
   // one returning atomic per stray, all lanes at once: strays of a wavefront
   // mostly lie in different cells, so a per-key leader loop would serialise
   // (four entries per thread and pass, their atomics in flight together)
@@ -1820,22 +1818,29 @@ __global__ void __launch_bounds__(256) k_stray_rank(const int* __restrict__ coun
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (c[u] >= 0) ranks[i0 + u * stride] = r[u];
-    if (scount) {   // regrouping: listed strays per (species, cell)
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (c[u] >= 0) {
-          const int sp = (items[i0 + u * stride] >> kItemShift) & (kMaxTiledSpecies - 1);
-          atomicAdd(scount + (int64_t)sp * nn + c[u], 1);
-        }
-    }
   }
 }
 
 // regrouping: the particles of (species, cell) after the pass, in place of the
 // stray counts
+// each species' particles per cell after the pass: its stayers plus the
+// cell's sorted strays of that species (contiguous from start[c], their
+// species stored by the scatter; one thread per cell, no atomics)
 __global__ void __launch_bounds__(256) k_regroup_total(int* __restrict__ scount, const int* __restrict__ stay,
-                                                       int64_t n) {
-  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) scount[i] += stay[i];
+                                                       const int* __restrict__ start, const int32_t* __restrict__ ssp,
+                                                       int ns, int64_t nn) {
+  for (int64_t c = blockIdx.x * 256 + threadIdx.x; c < nn; c += (int64_t)gridDim.x * 256) {
+    int cnt[kMaxTiledSpecies] = {0, 0, 0, 0};
+    const int e = start[c + 1];
+    for (int i = start[c]; i < e; ++i) {
+      const int sp = ssp[i];
+#pragma unroll
+      for (int k = 0; k < kMaxTiledSpecies; ++k) cnt[k] += sp == k ? 1 : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxTiledSpecies; ++k)
+      if (k < ns) scount[k * nn + c] = stay[k * nn + c] + cnt[k];
+  }
 }
 
 // regrouping: the cell ranges of each species from the scan over (species, cell)
@@ -2061,16 +2066,16 @@ hipError_t run_T(const Grid& g, const SpeciesArgs* sp, int ns, const void* Emove
   // strays: counting sort by cell
   if ((e = launch_zero(w.counts, sizeof(int) * (size_t)g.nn, st)) != hipSuccess) return e;
   const int64_t nsn = (int64_t)ns * g.nn;
-  if (regroup && (e = launch_zero(w.scount, sizeof(int) * (size_t)nsn, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_stray_rank, dim3(1024), dim3(256), 0, st, (const int*)w.count, (const int*)w.cell, w.counts,
-                     w.rank, (const int*)w.item, regroup ? w.scount : nullptr, g.nn);
+                     w.rank);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_exclusive_scan(w.counts, g.nn, w.start, w.scan_sums, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_stray_scatter<T>, dim3(1024), dim3(256), 0, st, a, (const int*)w.rank);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (regroup) {
     // the species' cell ranges after the pass: stayers plus arriving strays
-    hipLaunchKernelGGL(k_regroup_total, dim3(1024), dim3(256), 0, st, w.scount, (const int*)w.stay, nsn);
+    hipLaunchKernelGGL(k_regroup_total, dim3(1024), dim3(256), 0, st, w.scount, (const int*)w.stay,
+                       (const int*)w.start, (const int32_t*)w.dsp, ns, g.nn);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_exclusive_scan(w.scount, nsn, w.rscan, w.rsums, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_regroup_starts<T>, dim3(1024), dim3(256), 0, st, a, (const int*)w.rscan, g.nn);
