@@ -206,6 +206,49 @@ def test_moments_sorted_tiled(E, O, I, n, ppc, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_moments_tiled_node_plane_positions(E, O, I, prec):
+    """The tiled deposit with particles exactly on node planes (weights exactly
+    0 and 1, so class-weight factors vanish), just below the next plane, and
+    on the periodic boundary, more than 64 to a cell."""
+    import types
+    say("moments tiled, node-plane positions", prec)
+    n, h, dt = (4, 3, 5), (0.5, 0.25, 0.4), 0.1
+    nn = int(np.prod(n))
+    rng = np.random.default_rng(21)
+    npart = 300
+    cells = np.stack([rng.integers(0, n[d], npart) for d in range(3)])
+    cells[:, :100] = np.array([[1], [2], [3]])   # 100 particles in one cell
+    frac = rng.random((3, npart))
+    pick = rng.integers(0, 4, (3, npart))
+    frac = np.where(pick == 0, 0.0, np.where(pick == 1, 1.0 - 2.0 ** -30, frac))
+    v = 0.3 * rng.standard_normal((3, npart))
+    q = 1e-3 * (1.0 + rng.random(npart))
+    B = np.array([[0.02], [-0.03], [0.2]]) + 0.05 * rng.standard_normal((3, nn))
+    grid = E.Grid(n, h, dt)
+    if prec == "f64":
+        x = (cells + frac) * np.array(h)[:, None]
+        sp = E.Species.from_f64(-1.0, x, v, q)
+        tdt, tol, Bo = torch.float64, TOL64, B
+    else:
+        off = frac.astype(np.float32)
+        off = np.where(off >= 1.0, np.float32(1.0) - np.finfo(np.float32).epsneg, off).astype(np.float32)
+        lin = (cells[0] + n[0] * (cells[1] + n[1] * cells[2])).astype(np.int32)
+        v32, q32 = v.astype(np.float32), q.astype(np.float32)
+        sp = E.Species.from_f32(-1.0, lin, off, v32, q32)
+        x = (cells + off.astype(np.float64)) * np.array(h)[:, None]
+        v, q = v32.astype(np.float64), q32.astype(np.float64)
+        tdt, tol, Bo = torch.float32, TOL32, round32(B)
+    sp = sorted_species(E, grid, [sp])
+    J = torch.full((3, nn), 7.0, dtype=tdt, device="cuda")
+    M = torch.full((14, 9, nn), 7.0, dtype=tdt, device="cuda")
+    E.moments(grid, sp, dev(Bo, tdt), J, M, flags=E.SORTED)
+    p = types.SimpleNamespace(n=n, h=h, dt=dt, nn=nn, species=[types.SimpleNamespace(qom=-1.0)])
+    Jo, Mo = oracle_moments(O, p, [x], [v], [q], Bo)
+    assert rel(host(J), Jo) < tol
+    assert rel(host(M), Mo) < tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("n,shift", [((9, 7, 6), (1, 2, 1)), ((8, 8, 4), (3, 1, 1)), ((10, 6, 1), (5, 3, 0))])
 def test_deposit_invariant_under_brick_placement(E, O, I, prec, n, shift):
     """The tiled deposit does not depend on where the bricks of its
